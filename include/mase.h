@@ -1,0 +1,274 @@
+/*
+ * mase.h -- C ABI of the MI355X multi-area WLS state-estimation library.
+ *
+ * The library implements the per-Gauss-Newton-iteration pipeline of
+ * hierarchical multi-area state estimation with boundary condensation
+ * (arXiv 2604.23175, Sections 2-4):
+ *
+ *   1. measurement evaluation fused with direct accumulation of each area's
+ *      normal-equation blocks G^k = H_k^T W_k H_k and b^k = H_k^T W_k r_k
+ *      (Eq. 4 and Eq. 7, Section 4.2), without forming H;
+ *   2. per-area elimination of the internal variables: a sparse Cholesky
+ *      factorisation of G_ii^k that leaves the dense Schur block
+ *      S_b^k = G_bb - G_bi G_ii^-1 G_ib and the condensed right-hand side
+ *      bhat_b^k (Eq. 8-10, Section 4.3);
+ *   3. assembly of the boundary system S_Gamma = sum_k E_k^T S_b^k E_k,
+ *      bhat_Gamma = sum_k E_k^T bhat_b^k (Eq. 11, Section 4.4), its Cholesky
+ *      solve, scatter-back dx_b^k = E_k dx_Gamma and interior recovery
+ *      dx_i^k = G_ii^-1 (b_i - G_ib dx_b^k) (Eq. 8), then x += dx.
+ *
+ * Many measurement snapshots of one grid are processed together (all areas
+ * and all snapshots in one launch per stage).
+ *
+ * Conventions
+ * -----------
+ * - State: bus voltage angle theta (rad) and magnitude |V| (p.u.).  The
+ *   slack bus angle is the reference, fixed at 0, and is not a state
+ *   variable (n = 2N - 1, Section 5.2 counts 5737 = 2*2869 - 1 states).
+ * - Branch model: pi model, series impedance r + jx, total line charging b
+ *   split b/2 per end, no taps, no bus shunts.
+ * - Measurements (Eq. 4, types below): |V| at a bus, active/reactive injection
+ *   at a bus, active/reactive flow at the from end or the to end of a branch.
+ *   Weights default to w_i = 1/sigma_i^2 (W = R^-1, Eq. 2); a zero weight
+ *   masks a row without changing any structure (Section 4.1).
+ * - Measurement ownership: |V| and injections at bus i belong to area(i); a
+ *   from-end flow to area(from), a to-end flow to area(to).  Boundary buses
+ *   are the terminals of branches whose ends lie in different areas; area
+ *   k's local boundary set is its own boundary buses plus the foreign
+ *   terminal of each of its cut branches (Section 2.3).
+ * - Canonical orders used by every export: the global variable id of bus b
+ *   is 2b for theta (never for the slack) and 2b+1 for |V|; an area's local
+ *   variables are its internal buses then its local boundary buses, each in
+ *   increasing bus id, theta before |V|; Gamma lists all boundary buses in
+ *   increasing bus id, theta before |V|.
+ * - Memory: every pointer argument is caller-owned.  Host pointers are read
+ *   (or written) only during the call; `mase_create` copies what it needs.
+ *   Pointers named *_dev are device pointers on the context's stream.
+ * - Errors: 0 is success, negative values are errors (MASE_ERR_*), and
+ *   `mase_solve` returns MASE_NOT_CONVERGED (+1) when a snapshot reached
+ *   max_iter.  `mase_last_error` returns a message for the last failure.
+ * - Threading: a context is used by one host thread at a time.
+ */
+#ifndef MASE_H
+#define MASE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mase_ctx mase_ctx;
+
+/* Measurement types (Eq. 4: one template per type). */
+enum {
+  MASE_VM = 0,   /* |V| at bus meas_at */
+  MASE_PINJ = 1, /* active injection at bus meas_at */
+  MASE_QINJ = 2, /* reactive injection at bus meas_at */
+  MASE_PF = 3,   /* active flow at the from end of branch meas_at */
+  MASE_QF = 4,   /* reactive flow at the from end of branch meas_at */
+  MASE_PT = 5,   /* active flow at the to end of branch meas_at */
+  MASE_QT = 6    /* reactive flow at the to end of branch meas_at */
+};
+
+/* Return codes. */
+enum {
+  MASE_OK = 0,
+  MASE_NOT_CONVERGED = 1,
+  MASE_ERR_ARG = -1,        /* bad argument: index out of range, sigma <= 0,
+                               non-finite value, area without internal bus,
+                               disconnected area, size over a limit */
+  MASE_ERR_STATE = -2,      /* call out of order (e.g. no measurements set) */
+  MASE_ERR_NOT_POSDEF = -3, /* a non-positive pivot in G_ii^k or S_Gamma:
+                               the area or boundary system is unobservable */
+  MASE_ERR_HIP = -4,        /* a HIP runtime call failed */
+  MASE_ERR_OOM = -5,        /* device or host allocation failed */
+  MASE_ERR_NO_DEVICE = -6   /* a GPU call on a host-only context */
+};
+
+/* How the boundary system S_Gamma dx_Gamma = bhat_Gamma is factored. */
+enum {
+  MASE_GAMMA_SPARSE = 0, /* minimum-degree ordering of Gamma, sparse
+                            elimination of all but the root separator, dense
+                            Cholesky of that separator block (default) */
+  MASE_GAMMA_DENSE = 1   /* dense Cholesky of the whole S_Gamma */
+};
+
+typedef struct {
+  void* stream;          /* hipStream_t to run on; NULL = library-owned stream */
+  int32_t batched;       /* 1 (default): one launch per stage over all areas x
+                            snapshots.  0: the paper's plain schedule -- one
+                            snapshot at a time, per-area launches on per-area
+                            streams, no graph */
+  int32_t use_graph;     /* 1: capture one GN iteration as a hipGraph and
+                            replay it (batched mode only); default 1 */
+  int32_t gamma_mode;    /* MASE_GAMMA_SPARSE (default) or MASE_GAMMA_DENSE */
+  int32_t host_only;     /* 1: build the maps and symbolic structures only,
+                            touch no GPU (exports work, solves return
+                            MASE_ERR_NO_DEVICE) */
+  int32_t autotune;      /* 1: time candidate launch shapes at create and
+                            keep the fastest (cached in tune_cache) */
+  const char* tune_cache;/* path of the autotune cache file, or NULL */
+} mase_options;
+
+/* Fill `opt` with the defaults listed above. */
+void mase_default_options(mase_options* opt);
+
+/*
+ * Build a context for one grid topology, partition and measurement set, for
+ * up to n_snap snapshots processed together (Sections 2.3, 4.1, 5.1: all
+ * templates, maps and buffers are built once and stay on the device).
+ *
+ *   br_from, br_to [n_branch]   bus indices in [0, n_bus), from != to
+ *   br_r, br_x, br_b [n_branch] series r, x (r + jx != 0) and total charging
+ *   slack_bus                   reference bus (angle 0)
+ *   bus_area [n_bus]            area index in [0, n_area) of every bus; each
+ *                               area must be connected and own at least one
+ *                               internal (non-boundary) bus
+ *   meas_type, meas_at [n_meas] type (MASE_VM..MASE_QT) and bus/branch index
+ *   meas_sigma [n_meas]         standard deviation, > 0
+ *   n_snap                      snapshots per batch, >= 1
+ *   opt                         options or NULL for defaults
+ *
+ * On success *out receives the context.  Fails with MASE_ERR_ARG on invalid
+ * input, MASE_ERR_OOM / MASE_ERR_HIP on device trouble.
+ */
+int mase_create(int32_t n_bus, int32_t n_branch,
+                const int32_t* br_from, const int32_t* br_to,
+                const double* br_r, const double* br_x, const double* br_b,
+                int32_t slack_bus, int32_t n_area, const int32_t* bus_area,
+                int32_t n_meas, const int32_t* meas_type, const int32_t* meas_at,
+                const double* meas_sigma, int32_t n_snap,
+                const mase_options* opt, mase_ctx** out);
+
+void mase_destroy(mase_ctx* ctx);
+
+/* Message describing the last error on this thread (never NULL). */
+const char* mase_last_error(void);
+
+/* Short name of a return code. */
+const char* mase_strerror(int code);
+
+/*
+ * Measurements z [n_snap][n_meas] (host) and weights w [n_meas] (host, or
+ * NULL for 1/sigma^2; w = 0 masks a row, Section 4.1).  Copied to the device.
+ */
+int mase_set_measurements(mase_ctx* ctx, const double* z, const double* w);
+
+/* Same with device pointers; z_dev is copied on the context's stream. */
+int mase_set_measurements_dev(mase_ctx* ctx, const double* z_dev, const double* w_dev);
+
+/*
+ * Starting state vm, va [n_snap][n_bus] (host), or NULL for flat start
+ * (|V| = 1, theta = 0).  The slack angle is forced to 0.  Marks every
+ * snapshot active and clears the iteration counters.
+ */
+int mase_set_state(mase_ctx* ctx, const double* vm, const double* va);
+int mase_set_state_dev(mase_ctx* ctx, const double* vm_dev, const double* va_dev);
+
+/*
+ * One Gauss-Newton iteration (Eq. 3 solved through Eq. 7-11) for every
+ * active snapshot: assembly, local condensation, boundary assembly and
+ * solve, scatter-back, interior recovery, x += dx.  max_abs_dx [n_snap]
+ * (host, may be NULL) receives max_i |dx_i| of each snapshot (0 for frozen
+ * snapshots).  Snapshots whose step is below the tolerance of the last
+ * mase_solve (default 1e-6) are frozen afterwards.
+ */
+int mase_gn_iter(mase_ctx* ctx, double* max_abs_dx);
+
+/*
+ * Iterate until every snapshot has taken a step with max |dx| < tol, or
+ * max_iter iterations (the paper caps Gauss-Newton at 10, Section 5.1).
+ * iters [n_snap] and converged [n_snap] (host, may be NULL) receive the
+ * per-snapshot step count and flag.  Returns MASE_NOT_CONVERGED if any
+ * snapshot did not converge.
+ */
+int mase_solve(mase_ctx* ctx, double tol, int32_t max_iter, int32_t* iters,
+               int32_t* converged);
+
+/* Current state vm, va [n_snap][n_bus] (host / device). */
+int mase_state(mase_ctx* ctx, double* vm, double* va);
+int mase_state_dev(mase_ctx* ctx, double* vm_dev, double* va_dev);
+
+/* WLS objective J = r^T W r (Eq. 2) at the current state, J [n_snap] (host). */
+int mase_objective(mase_ctx* ctx, double* J);
+
+/*
+ * Measurement functions h(x) at states vm, va [n_snap][n_bus] (device) into
+ * h_dev [n_snap][n_meas] (device): the per-type templates of Eq. 4 in
+ * evaluation-only mode.  Does not change the context's state.
+ */
+int mase_eval_h_dev(mase_ctx* ctx, const double* vm_dev, const double* va_dev, double* h_dev);
+
+/* ---- sizes and structure exports (work on host-only contexts too) ---- */
+
+enum {
+  MASE_INFO_N_GAMMA = 0,      /* number of boundary variables (slack angle excluded) */
+  MASE_INFO_N_BOUNDARY_BUS,   /* number of boundary buses */
+  MASE_INFO_GAMMA_TAIL,       /* buses in the dense block of the boundary system */
+  MASE_INFO_NNZ_FACTOR,       /* doubles of packed factor storage per snapshot */
+  MASE_INFO_MAX_LEVELS,       /* deepest level schedule over areas */
+  MASE_INFO_FLOPS_LOCAL,      /* flops per snapshot-iteration, local elimination */
+  MASE_INFO_FLOPS_GAMMA,      /* flops per snapshot-iteration, boundary solve */
+  MASE_INFO_BYTES_ASSEMBLY,   /* algorithmic HBM bytes per snapshot of assembly */
+  MASE_INFO_N_SNAP,
+  MASE_INFO_N_AREA
+};
+int mase_info(const mase_ctx* ctx, int32_t what, int64_t* value);
+
+enum {
+  MASE_MAP_BOUNDARY_FLAG = 0, /* [n_bus]: 1 if the bus is a boundary bus (area ignored) */
+  MASE_MAP_MEAS_AREA = 1,     /* [n_meas]: owning area of each measurement (area ignored) */
+  MASE_MAP_GAMMA_VARS = 2,    /* [n_gamma]: global variable ids of Gamma (area ignored) */
+  MASE_MAP_LOCAL_VARS = 3,    /* area's local variable ids, canonical order */
+  MASE_MAP_N_INTERNAL = 4,    /* [1]: number of internal variables of the area */
+  MASE_MAP_E = 5              /* area's E_k: Gamma index of each local boundary variable */
+};
+/*
+ * Copy one map into buf (capacity cap entries); *len receives the full
+ * length.  Fails with MASE_ERR_ARG if cap is too small (then *len is set).
+ */
+int mase_export_map(const mase_ctx* ctx, int32_t kind, int32_t area, int32_t* buf,
+                    int64_t cap, int64_t* len);
+
+/*
+ * Symbolic pattern of G^k (Eq. 7) over the area's local variables in
+ * canonical order, as CSR with sorted columns: rowptr [n_local + 1],
+ * colidx [cap].  *nnz receives the entry count.
+ */
+int mase_export_pattern(const mase_ctx* ctx, int32_t area, int32_t* rowptr,
+                        int32_t* colidx, int64_t cap, int64_t* nnz);
+
+/* ---- stage-level entry points (together they make one mase_gn_iter) ---- */
+
+/* Stage 1: assemble G^k, b^k for every area and active snapshot (Eq. 7). */
+int mase_stage_assemble(mase_ctx* ctx);
+/* Stage 2: eliminate internals, leaving S_b^k and bhat_b^k (Eq. 8-10). */
+int mase_stage_condense(mase_ctx* ctx);
+/* Stage 3a: assemble S_Gamma and bhat_Gamma from the areas (Eq. 11). */
+int mase_stage_gamma_assemble(mase_ctx* ctx);
+/* Stage 3b: factor S_Gamma in place and solve for dx_Gamma. */
+int mase_stage_gamma_solve(mase_ctx* ctx);
+/* Stage 4: scatter-back, interior recovery (Eq. 8), x += dx, convergence;
+ * max_abs_dx [n_snap] (host, may be NULL) as in mase_gn_iter. */
+int mase_stage_update(mase_ctx* ctx, double* max_abs_dx);
+
+/*
+ * Debug reads of stage results for one snapshot (host buffers, canonical
+ * orders, dense row-major, both triangles filled):
+ *   mase_read_local_system  after stage 1: G^k [n_local x n_local], b^k [n_local]
+ *   mase_read_schur         after stage 2: S_b^k [n_b x n_b], bhat_b^k [n_b]
+ *   mase_read_gamma_system  after stage 3a: S_Gamma [n_gamma x n_gamma], bhat_Gamma
+ *   mase_read_step          after stage 4: dx [2 n_bus] by global variable id
+ *                           (entry 2*slack is 0)
+ * The values are overwritten by later stages (factorisations work in place).
+ */
+int mase_read_local_system(mase_ctx* ctx, int32_t snap, int32_t area, double* G, double* b);
+int mase_read_schur(mase_ctx* ctx, int32_t snap, int32_t area, double* S, double* bhat);
+int mase_read_gamma_system(mase_ctx* ctx, int32_t snap, double* S, double* bhat);
+int mase_read_step(mase_ctx* ctx, int32_t snap, double* dx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MASE_H */

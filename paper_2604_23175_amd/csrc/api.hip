@@ -1,0 +1,862 @@
+// C ABI of the multi-area estimator (include/mase.h): context management,
+// device residency of the plan, launch schedules (batched, graph-captured,
+// or the plain per-area/per-snapshot schedule), host-side stage reads.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dev.hpp"
+#include "launch.hpp"
+#include "mase.h"
+#include "plan.hpp"
+
+using namespace mase;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPTRY(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(MASE_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+}  // namespace
+
+struct mase_ctx {
+  Plan plan;
+  mase_options opt{};
+  bool host_only = false;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<hipStream_t> astreams;
+  std::vector<hipEvent_t> aevents;
+  hipEvent_t ev_main = nullptr;
+  Dev d{};
+  std::vector<void*> dallocs;
+  double2* xscratch = nullptr;
+  double* stage_vm = nullptr;
+  double* stage_va = nullptr;
+  double* dtol = nullptr;
+  size_t lds_asm = 0;
+  int nslot_g = 0;
+  bool have_z = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int32_t* h_active = nullptr;
+  int32_t* h_status = nullptr;
+  int32_t* h_iters = nullptr;
+  double* h_maxdx = nullptr;
+  double* h_tol = nullptr;
+  std::vector<SysMeta> hsys;
+};
+
+namespace {
+
+template <class T>
+int dalloc(mase_ctx* c, size_t n, T** out) {
+  void* p = nullptr;
+  const size_t bytes = std::max<size_t>(1, n) * sizeof(T);
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) return fail(MASE_ERR_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  c->dallocs.push_back(p);
+  *out = static_cast<T*>(p);
+  return 0;
+}
+
+template <class D, class H>
+int upload(mase_ctx* c, const std::vector<H>& v, const D** out) {
+  static_assert(sizeof(D) == sizeof(H), "layout mismatch");
+  D* p = nullptr;
+  int rc = dalloc(c, v.size(), &p);
+  if (rc) return rc;
+  if (!v.empty()) HIPTRY(hipMemcpy(p, v.data(), v.size() * sizeof(H), hipMemcpyHostToDevice));
+  *out = p;
+  return 0;
+}
+
+void append_rebased(std::vector<int32_t>& dst, const std::vector<int32_t>& src, int32_t base) {
+  for (int32_t v : src) dst.push_back(v + base);
+}
+
+int upload_plan(mase_ctx* c) {
+  const Plan& p = c->plan;
+  const int K = p.n_area;
+  std::vector<SysMeta> sm(K + 1);
+  std::vector<AreaMeta> am(K);
+  std::vector<int32_t> gbus, cd_ptr, up_ptr, rb_ptr, bs_ptr;
+  std::vector<I4> cd_items, up_tgt, rb_tgt, bs_items;
+  std::vector<I2> up_con, rb_con, bs_con;
+  for (int i = 0; i <= K; ++i) {
+    const SysPlan& s = p.sys[i];
+    SysMeta m{};
+    m.nn = s.nn; m.ne = s.ne; m.nt = s.nt; m.ld = s.ld;
+    m.tail_off = s.tail_off; m.nval = s.nval; m.pin_off = s.pin_off; m.nlev = s.nlev;
+    m.val_off = p.val_off[i]; m.rhs_off = p.rhs_off[i];
+    m.gbus = (int32_t)gbus.size();
+    gbus.insert(gbus.end(), s.gbus.begin(), s.gbus.end());
+    m.cd_ptr = (int32_t)cd_ptr.size();
+    append_rebased(cd_ptr, s.cd_ptr, (int32_t)cd_items.size());
+    cd_items.insert(cd_items.end(), s.cd_items.begin(), s.cd_items.end());
+    m.up_ptr = (int32_t)up_ptr.size();
+    append_rebased(up_ptr, s.up_ptr, (int32_t)up_tgt.size());
+    for (const I4& t : s.up_tgt)
+      up_tgt.push_back({t.x, t.y, t.z + (int32_t)up_con.size(), t.w + (int32_t)up_con.size()});
+    up_con.insert(up_con.end(), s.up_con.begin(), s.up_con.end());
+    m.rb_ptr = (int32_t)rb_ptr.size();
+    append_rebased(rb_ptr, s.rb_ptr, (int32_t)rb_tgt.size());
+    for (const I4& t : s.rb_tgt)
+      rb_tgt.push_back({t.x, t.y + (int32_t)rb_con.size(), t.z + (int32_t)rb_con.size(), 0});
+    rb_con.insert(rb_con.end(), s.rb_con.begin(), s.rb_con.end());
+    m.bs_ptr = (int32_t)bs_ptr.size();
+    append_rebased(bs_ptr, s.bs_ptr, (int32_t)bs_items.size());
+    for (const I4& t : s.bs_items)
+      bs_items.push_back({t.x, t.y, t.z + (int32_t)bs_con.size(), t.w + (int32_t)bs_con.size()});
+    bs_con.insert(bs_con.end(), s.bs_con.begin(), s.bs_con.end());
+    sm[i] = m;
+  }
+  std::vector<int32_t> br_lf, br_lt, inc_ptr, inc_end, row_type, row_loc, row_meas;
+  std::vector<double> br_g, br_bs, br_hb;
+  std::vector<I4> slot;
+  std::vector<I2> scon, rslot, rcon;
+  size_t lds = 0;
+  for (int k = 0; k < K; ++k) {
+    const AreaTemplates& t = p.tpl[k];
+    AreaMeta a{};
+    a.nn = p.sys[k].nn;
+    a.nbr = (int32_t)t.br_lf.size();
+    a.nrow = (int32_t)t.row_type.size();
+    a.nslot = (int32_t)t.slot.size();
+    a.br = (int32_t)br_lf.size();
+    br_lf.insert(br_lf.end(), t.br_lf.begin(), t.br_lf.end());
+    br_lt.insert(br_lt.end(), t.br_lt.begin(), t.br_lt.end());
+    br_g.insert(br_g.end(), t.br_g.begin(), t.br_g.end());
+    br_bs.insert(br_bs.end(), t.br_bs.begin(), t.br_bs.end());
+    br_hb.insert(br_hb.end(), t.br_hb.begin(), t.br_hb.end());
+    a.inc_ptr = (int32_t)inc_ptr.size();
+    append_rebased(inc_ptr, t.inc_ptr, (int32_t)inc_end.size());
+    inc_end.insert(inc_end.end(), t.inc_end.begin(), t.inc_end.end());
+    a.row = (int32_t)row_type.size();
+    row_type.insert(row_type.end(), t.row_type.begin(), t.row_type.end());
+    row_loc.insert(row_loc.end(), t.row_loc.begin(), t.row_loc.end());
+    row_meas.insert(row_meas.end(), t.row_meas.begin(), t.row_meas.end());
+    a.slot = (int32_t)slot.size();
+    for (const I4& s : t.slot)
+      slot.push_back({s.x, s.y, s.z + (int32_t)scon.size(), s.w + (int32_t)scon.size()});
+    scon.insert(scon.end(), t.scon.begin(), t.scon.end());
+    a.rslot = (int32_t)rslot.size();
+    for (const I2& s : t.rslot)
+      rslot.push_back({s.x + (int32_t)rcon.size(), s.y + (int32_t)rcon.size()});
+    rcon.insert(rcon.end(), t.rcon.begin(), t.rcon.end());
+    a.tail_src = p.tail_src_ptr[k];
+    a.slack_local = p.local_of_bus[k][p.slack];
+    am[k] = a;
+    lds = std::max(lds, (size_t)(16 * a.nn + 16 * a.nbr + 48 * a.nn));
+  }
+  c->lds_asm = lds;
+  c->hsys = sm;
+  c->nslot_g = (int)p.g_slot.size();
+
+  Dev& d = c->d;
+  d.n_bus = p.n_bus; d.n_meas = p.n_meas; d.n_area = K; d.n_snap = p.n_snap; d.slack = p.slack;
+  d.vstride = p.vstride; d.rstride = p.rstride;
+  int rc = 0;
+#define UP(field, vec) if ((rc = upload(c, vec, &d.field))) return rc
+  UP(sys, sm); UP(area, am); UP(area_order, p.area_order); UP(gbus, gbus);
+  UP(br_lf, br_lf); UP(br_lt, br_lt); UP(br_g, br_g); UP(br_bs, br_bs); UP(br_hb, br_hb);
+  UP(inc_ptr, inc_ptr); UP(inc_end, inc_end);
+  UP(row_type, row_type); UP(row_loc, row_loc); UP(row_meas, row_meas);
+  UP(slot, slot); UP(scon, scon); UP(rslot, rslot); UP(rcon, rcon);
+  UP(cd_ptr, cd_ptr); UP(up_ptr, up_ptr); UP(rb_ptr, rb_ptr); UP(bs_ptr, bs_ptr);
+  UP(cd_items, cd_items); UP(up_tgt, up_tgt); UP(up_con, up_con);
+  UP(rb_tgt, rb_tgt); UP(rb_con, rb_con); UP(bs_items, bs_items); UP(bs_con, bs_con);
+  UP(g_slot, p.g_slot); UP(g_con, p.g_con); UP(g_rslot, p.g_rslot); UP(g_rcon, p.g_rcon);
+  UP(tail_src, p.tail_src); UP(bus_dx_src, p.bus_dx_src);
+#undef UP
+  const int64_t S = p.n_snap;
+  double* z = nullptr;
+  double* w = nullptr;
+  if ((rc = dalloc(c, S * p.n_meas, &z))) return rc;
+  if ((rc = dalloc(c, p.n_meas, &w))) return rc;
+  d.z = z;
+  d.w = w;
+  std::vector<double> w0(p.n_meas);
+  for (int i = 0; i < p.n_meas; ++i) w0[i] = 1.0 / (p.sigma[i] * p.sigma[i]);
+  HIPTRY(hipMemcpy(w, w0.data(), sizeof(double) * p.n_meas, hipMemcpyHostToDevice));
+  if ((rc = dalloc(c, S * p.n_bus, &d.x))) return rc;
+  if ((rc = dalloc(c, S * p.n_bus, &c->xscratch))) return rc;
+  if ((rc = dalloc(c, S * p.n_bus, &c->stage_vm))) return rc;
+  if ((rc = dalloc(c, S * p.n_bus, &c->stage_va))) return rc;
+  if ((rc = dalloc(c, S * p.vstride, &d.vals))) return rc;
+  if ((rc = dalloc(c, S * p.rstride, &d.rhs))) return rc;
+  if ((rc = dalloc(c, S * K, &d.jpart))) return rc;
+  if ((rc = dalloc(c, S, &d.active))) return rc;
+  if ((rc = dalloc(c, S, &d.iters))) return rc;
+  if ((rc = dalloc(c, S * (K + 1), &d.status))) return rc;
+  if ((rc = dalloc(c, S, &d.maxdx))) return rc;
+  if ((rc = dalloc(c, 1, &c->dtol))) return rc;
+  d.tol = c->dtol;
+  d.hout = nullptr;
+  HIPTRY(hipMemset(d.vals, 0, sizeof(double) * S * p.vstride));
+  HIPTRY(hipMemset(d.rhs, 0, sizeof(double) * S * p.rstride));
+  HIPTRY(hipHostMalloc((void**)&c->h_active, sizeof(int32_t) * S, hipHostMallocDefault));
+  HIPTRY(hipHostMalloc((void**)&c->h_iters, sizeof(int32_t) * S, hipHostMallocDefault));
+  HIPTRY(hipHostMalloc((void**)&c->h_status, sizeof(int32_t) * S * (K + 1), hipHostMallocDefault));
+  HIPTRY(hipHostMalloc((void**)&c->h_maxdx, sizeof(double) * S, hipHostMallocDefault));
+  HIPTRY(hipHostMalloc((void**)&c->h_tol, sizeof(double), hipHostMallocDefault));
+  c->h_tol[0] = 1e-6;
+  HIPTRY(hipMemcpy(c->dtol, c->h_tol, sizeof(double), hipMemcpyHostToDevice));
+
+  int dev = 0, maxlds = 0;
+  HIPTRY(hipGetDevice(&dev));
+  HIPTRY(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  if (c->lds_asm > (size_t)maxlds)
+    return fail(MASE_ERR_ARG, "an area needs " + std::to_string(c->lds_asm) +
+                                  " bytes of LDS for assembly; the device allows " +
+                                  std::to_string(maxlds));
+  if (c->lds_asm > 65536) HIPTRY(allow_assemble_lds(c->lds_asm));
+  return 0;
+}
+
+const SysMeta& gsys(const mase_ctx* c) { return c->hsys[c->plan.n_area]; }
+
+int launch_batched_iteration(mase_ctx* c, hipStream_t st) {
+  const int K = c->plan.n_area, S = c->plan.n_snap;
+  const Dev& d = c->d;
+  HIPTRY(launch_assemble(d, 0, K, 0, S, MODE_ASSEMBLE, c->lds_asm, st));
+  HIPTRY(launch_eliminate(d, 0, K, 0, S, st));
+  const SysMeta& g = gsys(c);
+  if (g.nn > 0) {
+    HIPTRY(launch_gamma_gather(d, 0, S, c->nslot_g, g.nn, st));
+    if (g.ne > 0) HIPTRY(launch_eliminate(d, K, 1, 0, S, st));
+    HIPTRY(launch_dense_chol(d, 0, S, g.ld, st));
+    if (g.ne > 0) HIPTRY(launch_backsolve(d, K, 1, 0, S, st));
+  }
+  HIPTRY(launch_backsolve(d, 0, K, 0, S, st));
+  HIPTRY(launch_update(d, 0, S, st));
+  return 0;
+}
+
+// The paper's schedule for one snapshot: per-area launches on per-area
+// streams for assembly + condensation, boundary work on the main stream,
+// per-area back substitution on the area streams again (Section 4.3).
+int launch_plain_iteration(mase_ctx* c, int s) {
+  const int K = c->plan.n_area;
+  const Dev& d = c->d;
+  hipStream_t st = c->stream;
+  const int ns = (int)c->astreams.size();
+  HIPTRY(hipEventRecord(c->ev_main, st));
+  for (int i = 0; i < ns; ++i) HIPTRY(hipStreamWaitEvent(c->astreams[i], c->ev_main, 0));
+  for (int ai = 0; ai < K; ++ai) {
+    hipStream_t as = c->astreams[ai % ns];
+    HIPTRY(launch_assemble(d, ai, 1, s, 1, MODE_ASSEMBLE, c->lds_asm, as));
+    HIPTRY(launch_eliminate(d, ai, 1, s, 1, as));
+  }
+  for (int i = 0; i < ns; ++i) {
+    HIPTRY(hipEventRecord(c->aevents[i], c->astreams[i]));
+    HIPTRY(hipStreamWaitEvent(st, c->aevents[i], 0));
+  }
+  const SysMeta& g = gsys(c);
+  if (g.nn > 0) {
+    HIPTRY(launch_gamma_gather(d, s, 1, c->nslot_g, g.nn, st));
+    if (g.ne > 0) HIPTRY(launch_eliminate(d, K, 1, s, 1, st));
+    HIPTRY(launch_dense_chol(d, s, 1, g.ld, st));
+    if (g.ne > 0) HIPTRY(launch_backsolve(d, K, 1, s, 1, st));
+  }
+  HIPTRY(hipEventRecord(c->ev_main, st));
+  for (int i = 0; i < ns; ++i) HIPTRY(hipStreamWaitEvent(c->astreams[i], c->ev_main, 0));
+  for (int ai = 0; ai < K; ++ai) HIPTRY(launch_backsolve(d, ai, 1, s, 1, c->astreams[ai % ns]));
+  for (int i = 0; i < ns; ++i) {
+    HIPTRY(hipEventRecord(c->aevents[i], c->astreams[i]));
+    HIPTRY(hipStreamWaitEvent(st, c->aevents[i], 0));
+  }
+  HIPTRY(launch_update(d, s, 1, st));
+  return 0;
+}
+
+int read_flags(mase_ctx* c) {
+  const int S = c->plan.n_snap, K = c->plan.n_area;
+  HIPTRY(hipMemcpyAsync(c->h_active, c->d.active, sizeof(int32_t) * S, hipMemcpyDeviceToHost, c->stream));
+  HIPTRY(hipMemcpyAsync(c->h_maxdx, c->d.maxdx, sizeof(double) * S, hipMemcpyDeviceToHost, c->stream));
+  HIPTRY(hipMemcpyAsync(c->h_status, c->d.status, sizeof(int32_t) * S * (K + 1), hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPTRY(hipStreamSynchronize(c->stream));
+  return 0;
+}
+
+bool snapshot_bad(const mase_ctx* c, int s) {
+  const int K = c->plan.n_area;
+  for (int k = 0; k <= K; ++k)
+    if (c->h_status[(size_t)s * (K + 1) + k]) return true;
+  return false;
+}
+
+int check_device(const mase_ctx* c) {
+  if (!c) return fail(MASE_ERR_ARG, "null context");
+  if (c->host_only) return fail(MASE_ERR_NO_DEVICE, "context was created host-only");
+  return 0;
+}
+
+// Canonical index of (local bus v, component comp) of system k, or -1 for
+// the slack angle.  For areas the canonical order is internal buses
+// ascending then boundary buses ascending; for the boundary system it is
+// Gamma order.
+std::vector<int32_t> canon_index(const Plan& p, int k) {
+  const SysPlan& s = p.sys[k];
+  std::vector<int32_t> out(2 * s.nn, -1);
+  std::vector<std::pair<int, int>> key;  // (rank, local)
+  for (int v = 0; v < s.nn; ++v) {
+    int rank;
+    if (k < p.n_area) rank = (v < s.ne ? 0 : 1) * p.n_bus + s.gbus[v];
+    else rank = p.gamma_canon_pos[s.gbus[v]];
+    key.push_back({rank, v});
+  }
+  std::sort(key.begin(), key.end());
+  int c = 0;
+  for (auto& kv : key) {
+    const int v = kv.second;
+    if (s.gbus[v] != p.slack) out[2 * v] = c++;
+    out[2 * v + 1] = c++;
+  }
+  return out;
+}
+
+// Dense symmetric matrix (row-major, dim x dim) of system k's packed blocks
+// whose row and column both satisfy `take`, in canonical order offset by off.
+template <class F>
+void unpack_blocks(const Plan& p, int k, const std::vector<double>& vals, const std::vector<int32_t>& ci,
+                   int dim, int off, F take, double* M) {
+  const SysPlan& s = p.sys[k];
+  auto put = [&](int i, int j, int32_t o, int32_t stride) {
+    for (int r = 0; r < 2; ++r)
+      for (int cc = 0; cc < 2; ++cc) {
+        const int a = ci[2 * i + r], b = ci[2 * j + cc];
+        if (a < 0 || b < 0 || !take(i) || !take(j)) continue;
+        const double v = vals[o + r + cc * stride];
+        M[(size_t)(a - off) * dim + (b - off)] = v;
+        M[(size_t)(b - off) * dim + (a - off)] = v;
+      }
+  };
+  for (int j = 0; j < s.ne; ++j) {
+    put(j, j, s.col_off[j], 2);
+    for (int i : s.strct[j]) put(i, j, s.blk_off(i, j), 2);
+  }
+  for (int q = s.ne; q < s.nn; ++q)
+    for (int i = q; i < s.nn; ++i) put(i, q, s.blk_off(i, q), s.ld);
+}
+
+}  // namespace
+
+extern "C" {
+
+void mase_default_options(mase_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->batched = 1;
+  opt->use_graph = 1;
+  opt->gamma_mode = MASE_GAMMA_SPARSE;
+}
+
+const char* mase_last_error(void) { return g_err.c_str(); }
+
+const char* mase_strerror(int code) {
+  switch (code) {
+    case MASE_OK: return "ok";
+    case MASE_NOT_CONVERGED: return "not converged";
+    case MASE_ERR_ARG: return "invalid argument";
+    case MASE_ERR_STATE: return "call out of order";
+    case MASE_ERR_NOT_POSDEF: return "non-positive pivot (unobservable system)";
+    case MASE_ERR_HIP: return "HIP runtime error";
+    case MASE_ERR_OOM: return "out of memory";
+    case MASE_ERR_NO_DEVICE: return "host-only context";
+    default: return "unknown error";
+  }
+}
+
+int mase_create(int32_t n_bus, int32_t n_branch, const int32_t* br_from, const int32_t* br_to,
+                const double* br_r, const double* br_x, const double* br_b, int32_t slack_bus,
+                int32_t n_area, const int32_t* bus_area, int32_t n_meas, const int32_t* meas_type,
+                const int32_t* meas_at, const double* meas_sigma, int32_t n_snap,
+                const mase_options* opt, mase_ctx** out) {
+  if (!out) return fail(MASE_ERR_ARG, "out is null");
+  *out = nullptr;
+  mase_options o;
+  mase_default_options(&o);
+  if (opt) o = *opt;
+  Input in{n_bus, n_branch, br_from, br_to, br_r, br_x, br_b, slack_bus, n_area, bus_area,
+           n_meas, meas_type, meas_at, meas_sigma, n_snap, o.gamma_mode};
+  mase_ctx* c = new (std::nothrow) mase_ctx();
+  if (!c) return fail(MASE_ERR_OOM, "host allocation failed");
+  c->opt = o;
+  c->host_only = o.host_only != 0;
+  std::string err;
+  try {
+    err = build_plan(in, c->plan);
+  } catch (std::exception& ex) {
+    err = std::string("setup failed: ") + ex.what();
+  }
+  if (!err.empty()) {
+    delete c;
+    return fail(MASE_ERR_ARG, err);
+  }
+  if (c->host_only) {
+    *out = c;
+    return 0;
+  }
+  int rc = 0;
+  if (o.stream) {
+    c->stream = (hipStream_t)o.stream;
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) { delete c; return fail(MASE_ERR_HIP, hipGetErrorString(e)); }
+    c->own_stream = true;
+  }
+  if (!o.batched) {
+    const int ns = std::max(1, std::min(n_area, 32));
+    c->astreams.resize(ns);
+    c->aevents.resize(ns);
+    for (int i = 0; i < ns && !rc; ++i) {
+      if (hipStreamCreateWithFlags(&c->astreams[i], hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&c->aevents[i], hipEventDisableTiming) != hipSuccess)
+        rc = fail(MASE_ERR_HIP, "stream creation failed");
+    }
+    if (!rc && hipEventCreateWithFlags(&c->ev_main, hipEventDisableTiming) != hipSuccess)
+      rc = fail(MASE_ERR_HIP, "event creation failed");
+  }
+  if (!rc) rc = upload_plan(c);
+  if (!rc) {
+    hipError_t e = launch_pack_state(c->d, nullptr, nullptr, c->d.x, c->stream);
+    if (e == hipSuccess) e = launch_reset_flags(c->d, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) rc = fail(MASE_ERR_HIP, hipGetErrorString(e));
+  }
+  if (rc) {
+    mase_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return 0;
+}
+
+void mase_destroy(mase_ctx* c) {
+  if (!c) return;
+  if (!c->host_only) {
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    for (auto s : c->astreams) if (s) { (void)hipStreamSynchronize(s); (void)hipStreamDestroy(s); }
+    for (auto e : c->aevents) if (e) (void)hipEventDestroy(e);
+    if (c->ev_main) (void)hipEventDestroy(c->ev_main);
+    for (void* p : c->dallocs) (void)hipFree(p);
+    if (c->h_active) (void)hipHostFree(c->h_active);
+    if (c->h_iters) (void)hipHostFree(c->h_iters);
+    if (c->h_status) (void)hipHostFree(c->h_status);
+    if (c->h_maxdx) (void)hipHostFree(c->h_maxdx);
+    if (c->h_tol) (void)hipHostFree(c->h_tol);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  }
+  delete c;
+}
+
+int mase_set_measurements(mase_ctx* c, const double* z, const double* w) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  if (!z) return fail(MASE_ERR_ARG, "z is null");
+  const Plan& p = c->plan;
+  HIPTRY(hipMemcpyAsync((void*)c->d.z, z, sizeof(double) * (size_t)p.n_snap * p.n_meas,
+                        hipMemcpyHostToDevice, c->stream));
+  std::vector<double> wv(p.n_meas);
+  for (int i = 0; i < p.n_meas; ++i) {
+    wv[i] = w ? w[i] : 1.0 / (p.sigma[i] * p.sigma[i]);
+    if (!(wv[i] >= 0.0) || !std::isfinite(wv[i])) return fail(MASE_ERR_ARG, "weights must be finite and >= 0");
+  }
+  HIPTRY(hipMemcpyAsync((void*)c->d.w, wv.data(), sizeof(double) * p.n_meas, hipMemcpyHostToDevice, c->stream));
+  HIPTRY(hipStreamSynchronize(c->stream));
+  c->have_z = true;
+  return 0;
+}
+
+int mase_set_measurements_dev(mase_ctx* c, const double* z_dev, const double* w_dev) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  if (!z_dev) return fail(MASE_ERR_ARG, "z_dev is null");
+  const Plan& p = c->plan;
+  HIPTRY(hipMemcpyAsync((void*)c->d.z, z_dev, sizeof(double) * (size_t)p.n_snap * p.n_meas,
+                        hipMemcpyDeviceToDevice, c->stream));
+  if (w_dev)
+    HIPTRY(hipMemcpyAsync((void*)c->d.w, w_dev, sizeof(double) * p.n_meas, hipMemcpyDeviceToDevice, c->stream));
+  c->have_z = true;
+  return 0;
+}
+
+int mase_set_state(mase_ctx* c, const double* vm, const double* va) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  if ((vm == nullptr) != (va == nullptr)) return fail(MASE_ERR_ARG, "give both vm and va or neither");
+  const size_t n = (size_t)c->plan.n_snap * c->plan.n_bus;
+  if (vm) {
+    HIPTRY(hipMemcpyAsync(c->stage_vm, vm, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+    HIPTRY(hipMemcpyAsync(c->stage_va, va, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+    HIPTRY(launch_pack_state(c->d, c->stage_vm, c->stage_va, c->d.x, c->stream));
+  } else {
+    HIPTRY(launch_pack_state(c->d, nullptr, nullptr, c->d.x, c->stream));
+  }
+  HIPTRY(launch_reset_flags(c->d, c->stream));
+  HIPTRY(hipStreamSynchronize(c->stream));
+  return 0;
+}
+
+int mase_set_state_dev(mase_ctx* c, const double* vm_dev, const double* va_dev) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  if ((vm_dev == nullptr) != (va_dev == nullptr)) return fail(MASE_ERR_ARG, "give both vm and va or neither");
+  HIPTRY(launch_pack_state(c->d, vm_dev, va_dev, c->d.x, c->stream));
+  HIPTRY(launch_reset_flags(c->d, c->stream));
+  return 0;
+}
+
+int mase_gn_iter(mase_ctx* c, double* max_abs_dx) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  if (!c->have_z) return fail(MASE_ERR_STATE, "no measurements set");
+  const int S = c->plan.n_snap;
+  if (c->opt.batched) {
+    if (c->opt.use_graph) {
+      if (!c->gexec) {
+        HIPTRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        rc = launch_batched_iteration(c, c->stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c->stream, &g);
+        if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+        if (e != hipSuccess) return fail(MASE_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+        c->graph = g;
+        HIPTRY(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+      }
+      HIPTRY(hipGraphLaunch(c->gexec, c->stream));
+    } else {
+      if ((rc = launch_batched_iteration(c, c->stream))) return rc;
+    }
+    if ((rc = read_flags(c))) return rc;
+  } else {
+    // plain schedule: snapshots one after another
+    HIPTRY(hipMemcpyAsync(c->h_active, c->d.active, sizeof(int32_t) * S, hipMemcpyDeviceToHost, c->stream));
+    HIPTRY(hipStreamSynchronize(c->stream));
+    std::vector<int32_t> act(c->h_active, c->h_active + S);
+    for (int s = 0; s < S; ++s) {
+      if (!act[s]) continue;
+      if ((rc = launch_plain_iteration(c, s))) return rc;
+    }
+    if ((rc = read_flags(c))) return rc;
+  }
+  if (max_abs_dx) std::memcpy(max_abs_dx, c->h_maxdx, sizeof(double) * S);
+  for (int s = 0; s < S; ++s)
+    if (snapshot_bad(c, s))
+      return fail(MASE_ERR_NOT_POSDEF, "non-positive pivot in snapshot " + std::to_string(s));
+  return 0;
+}
+
+int mase_solve(mase_ctx* c, double tol, int32_t max_iter, int32_t* iters, int32_t* converged) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  if (!(tol > 0.0) || max_iter < 1) return fail(MASE_ERR_ARG, "need tol > 0 and max_iter >= 1");
+  if (!c->have_z) return fail(MASE_ERR_STATE, "no measurements set");
+  const int S = c->plan.n_snap;
+  c->h_tol[0] = tol;
+  HIPTRY(hipMemcpyAsync(c->dtol, c->h_tol, sizeof(double), hipMemcpyHostToDevice, c->stream));
+  if (c->opt.batched) {
+    HIPTRY(hipMemcpyAsync(c->h_active, c->d.active, sizeof(int32_t) * S, hipMemcpyDeviceToHost, c->stream));
+    HIPTRY(hipStreamSynchronize(c->stream));
+    int nact = 0;
+    for (int s = 0; s < S; ++s) nact += c->h_active[s] != 0;
+    for (int it = 0; it < max_iter && nact > 0; ++it) {
+      rc = mase_gn_iter(c, nullptr);
+      if (rc) return rc;
+      nact = 0;
+      for (int s = 0; s < S; ++s) nact += c->h_active[s] != 0;
+    }
+  } else {
+    // plain schedule: one snapshot at a time, to convergence
+    HIPTRY(hipMemcpyAsync(c->h_active, c->d.active, sizeof(int32_t) * S, hipMemcpyDeviceToHost, c->stream));
+    HIPTRY(hipStreamSynchronize(c->stream));
+    std::vector<int32_t> act(c->h_active, c->h_active + S);
+    for (int s = 0; s < S; ++s) {
+      if (!act[s]) continue;
+      for (int it = 0; it < max_iter; ++it) {
+        if ((rc = launch_plain_iteration(c, s))) return rc;
+        HIPTRY(hipMemcpyAsync(c->h_active + s, c->d.active + s, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+        HIPTRY(hipStreamSynchronize(c->stream));
+        if (!c->h_active[s]) break;
+      }
+    }
+    if ((rc = read_flags(c))) return rc;
+  }
+  HIPTRY(hipMemcpyAsync(c->h_iters, c->d.iters, sizeof(int32_t) * S, hipMemcpyDeviceToHost, c->stream));
+  if ((rc = read_flags(c))) return rc;
+  bool all = true, bad = false;
+  for (int s = 0; s < S; ++s) {
+    const bool b = snapshot_bad(c, s);
+    const bool conv = !c->h_active[s] && !b;
+    bad |= b;
+    all &= conv;
+    if (iters) iters[s] = c->h_iters[s];
+    if (converged) converged[s] = conv ? 1 : 0;
+  }
+  if (bad) return fail(MASE_ERR_NOT_POSDEF, "a snapshot hit a non-positive pivot");
+  return all ? MASE_OK : MASE_NOT_CONVERGED;
+}
+
+int mase_state(mase_ctx* c, double* vm, double* va) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  if (!vm || !va) return fail(MASE_ERR_ARG, "null output");
+  const size_t n = (size_t)c->plan.n_snap * c->plan.n_bus;
+  HIPTRY(launch_unpack_state(c->d, c->stage_vm, c->stage_va, c->stream));
+  HIPTRY(hipMemcpyAsync(vm, c->stage_vm, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+  HIPTRY(hipMemcpyAsync(va, c->stage_va, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+  HIPTRY(hipStreamSynchronize(c->stream));
+  return 0;
+}
+
+int mase_state_dev(mase_ctx* c, double* vm_dev, double* va_dev) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  if (!vm_dev || !va_dev) return fail(MASE_ERR_ARG, "null output");
+  HIPTRY(launch_unpack_state(c->d, vm_dev, va_dev, c->stream));
+  return 0;
+}
+
+int mase_objective(mase_ctx* c, double* J) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  if (!J) return fail(MASE_ERR_ARG, "null output");
+  if (!c->have_z) return fail(MASE_ERR_STATE, "no measurements set");
+  const int K = c->plan.n_area, S = c->plan.n_snap;
+  HIPTRY(launch_assemble(c->d, 0, K, 0, S, MODE_OBJECTIVE, c->lds_asm, c->stream));
+  std::vector<double> jp((size_t)S * K);
+  HIPTRY(hipMemcpyAsync(jp.data(), c->d.jpart, sizeof(double) * jp.size(), hipMemcpyDeviceToHost, c->stream));
+  HIPTRY(hipStreamSynchronize(c->stream));
+  for (int s = 0; s < S; ++s) {
+    double t = 0.0;
+    for (int k = 0; k < K; ++k) t += jp[(size_t)s * K + k];
+    J[s] = t;
+  }
+  return 0;
+}
+
+int mase_eval_h_dev(mase_ctx* c, const double* vm_dev, const double* va_dev, double* h_dev) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  if (!vm_dev || !va_dev || !h_dev) return fail(MASE_ERR_ARG, "null argument");
+  Dev d = c->d;
+  HIPTRY(launch_pack_state(d, vm_dev, va_dev, c->xscratch, c->stream));
+  d.x = c->xscratch;
+  d.hout = h_dev;
+  HIPTRY(launch_assemble(d, 0, c->plan.n_area, 0, c->plan.n_snap, MODE_EVAL_H, c->lds_asm, c->stream));
+  return 0;
+}
+
+int mase_info(const mase_ctx* c, int32_t what, int64_t* value) {
+  if (!c || !value) return fail(MASE_ERR_ARG, "null argument");
+  const Plan& p = c->plan;
+  int64_t v = 0;
+  switch (what) {
+    case MASE_INFO_N_GAMMA: v = p.n_gamma_vars(); break;
+    case MASE_INFO_N_BOUNDARY_BUS: v = (int64_t)p.gamma_bus.size(); break;
+    case MASE_INFO_GAMMA_TAIL: v = p.sys[p.n_area].nt; break;
+    case MASE_INFO_NNZ_FACTOR: v = p.vstride; break;
+    case MASE_INFO_MAX_LEVELS: v = p.max_levels(); break;
+    case MASE_INFO_FLOPS_LOCAL: v = (int64_t)p.flops_local(); break;
+    case MASE_INFO_FLOPS_GAMMA: v = (int64_t)p.flops_gamma(); break;
+    case MASE_INFO_BYTES_ASSEMBLY: v = (int64_t)p.bytes_assembly(); break;
+    case MASE_INFO_N_SNAP: v = p.n_snap; break;
+    case MASE_INFO_N_AREA: v = p.n_area; break;
+    default: return fail(MASE_ERR_ARG, "unknown info key");
+  }
+  *value = v;
+  return 0;
+}
+
+int mase_export_map(const mase_ctx* c, int32_t kind, int32_t area, int32_t* buf, int64_t cap,
+                    int64_t* len) {
+  if (!c || !len) return fail(MASE_ERR_ARG, "null argument");
+  const Plan& p = c->plan;
+  std::vector<int32_t> v;
+  const bool per_area = kind >= MASE_MAP_LOCAL_VARS;
+  if (per_area && (area < 0 || area >= p.n_area)) return fail(MASE_ERR_ARG, "area out of range");
+  switch (kind) {
+    case MASE_MAP_BOUNDARY_FLAG: v.assign(p.is_bnd.begin(), p.is_bnd.end()); break;
+    case MASE_MAP_MEAS_AREA: v = p.meas_area; break;
+    case MASE_MAP_GAMMA_VARS: v = canon_gamma_vars(p); break;
+    case MASE_MAP_LOCAL_VARS: v = canon_local_vars(p, area); break;
+    case MASE_MAP_N_INTERNAL: v.assign(1, canon_n_internal(p, area)); break;
+    case MASE_MAP_E: v = canon_E(p, area); break;
+    default: return fail(MASE_ERR_ARG, "unknown map kind");
+  }
+  *len = (int64_t)v.size();
+  if (!buf || cap < (int64_t)v.size()) return fail(MASE_ERR_ARG, "buffer too small");
+  std::copy(v.begin(), v.end(), buf);
+  return 0;
+}
+
+int mase_export_pattern(const mase_ctx* c, int32_t area, int32_t* rowptr, int32_t* colidx, int64_t cap,
+                        int64_t* nnz) {
+  if (!c || !nnz) return fail(MASE_ERR_ARG, "null argument");
+  if (area < 0 || area >= c->plan.n_area) return fail(MASE_ERR_ARG, "area out of range");
+  std::vector<int32_t> rp, ci;
+  canon_pattern(c->plan, area, rp, ci);
+  *nnz = (int64_t)ci.size();
+  if (!rowptr || !colidx || cap < (int64_t)ci.size()) return fail(MASE_ERR_ARG, "buffer too small");
+  std::copy(rp.begin(), rp.end(), rowptr);
+  std::copy(ci.begin(), ci.end(), colidx);
+  return 0;
+}
+
+int mase_stage_assemble(mase_ctx* c) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  if (!c->have_z) return fail(MASE_ERR_STATE, "no measurements set");
+  HIPTRY(launch_assemble(c->d, 0, c->plan.n_area, 0, c->plan.n_snap, MODE_ASSEMBLE, c->lds_asm, c->stream));
+  HIPTRY(hipStreamSynchronize(c->stream));
+  return 0;
+}
+
+int mase_stage_condense(mase_ctx* c) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  HIPTRY(launch_eliminate(c->d, 0, c->plan.n_area, 0, c->plan.n_snap, c->stream));
+  HIPTRY(hipStreamSynchronize(c->stream));
+  return 0;
+}
+
+int mase_stage_gamma_assemble(mase_ctx* c) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  const SysMeta& g = gsys(c);
+  if (g.nn > 0) HIPTRY(launch_gamma_gather(c->d, 0, c->plan.n_snap, c->nslot_g, g.nn, c->stream));
+  HIPTRY(hipStreamSynchronize(c->stream));
+  return 0;
+}
+
+int mase_stage_gamma_solve(mase_ctx* c) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  const SysMeta& g = gsys(c);
+  const int K = c->plan.n_area, S = c->plan.n_snap;
+  if (g.nn > 0) {
+    if (g.ne > 0) HIPTRY(launch_eliminate(c->d, K, 1, 0, S, c->stream));
+    HIPTRY(launch_dense_chol(c->d, 0, S, g.ld, c->stream));
+    if (g.ne > 0) HIPTRY(launch_backsolve(c->d, K, 1, 0, S, c->stream));
+  }
+  HIPTRY(hipStreamSynchronize(c->stream));
+  return 0;
+}
+
+int mase_stage_update(mase_ctx* c, double* max_abs_dx) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  HIPTRY(launch_backsolve(c->d, 0, c->plan.n_area, 0, c->plan.n_snap, c->stream));
+  HIPTRY(launch_update(c->d, 0, c->plan.n_snap, c->stream));
+  if ((rc = read_flags(c))) return rc;
+  if (max_abs_dx) std::memcpy(max_abs_dx, c->h_maxdx, sizeof(double) * c->plan.n_snap);
+  for (int s = 0; s < c->plan.n_snap; ++s)
+    if (snapshot_bad(c, s)) return fail(MASE_ERR_NOT_POSDEF, "non-positive pivot");
+  return 0;
+}
+
+int mase_read_local_system(mase_ctx* c, int32_t snap, int32_t area, double* G, double* b) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  const Plan& p = c->plan;
+  if (snap < 0 || snap >= p.n_snap || area < 0 || area >= p.n_area || !G || !b)
+    return fail(MASE_ERR_ARG, "bad argument");
+  const SysPlan& s = p.sys[area];
+  std::vector<double> vals(s.nval), rhs(2 * (size_t)s.nn);
+  HIPTRY(hipMemcpy(vals.data(), c->d.vals + (size_t)snap * p.vstride + p.val_off[area],
+                   sizeof(double) * s.nval, hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(rhs.data(), c->d.rhs + (size_t)snap * p.rstride + p.rhs_off[area],
+                   sizeof(double) * rhs.size(), hipMemcpyDeviceToHost));
+  const std::vector<int32_t> ci = canon_index(p, area);
+  int dim = 0;
+  for (int32_t v : ci) dim += v >= 0;
+  std::fill(G, G + (size_t)dim * dim, 0.0);
+  unpack_blocks(p, area, vals, ci, dim, 0, [](int) { return true; }, G);
+  for (int v = 0; v < 2 * s.nn; ++v)
+    if (ci[v] >= 0) b[ci[v]] = rhs[v];
+  return 0;
+}
+
+int mase_read_schur(mase_ctx* c, int32_t snap, int32_t area, double* S, double* bhat) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  const Plan& p = c->plan;
+  if (snap < 0 || snap >= p.n_snap || area < 0 || area >= p.n_area || !S || !bhat)
+    return fail(MASE_ERR_ARG, "bad argument");
+  const SysPlan& s = p.sys[area];
+  std::vector<double> vals(s.nval), rhs(2 * (size_t)s.nn);
+  HIPTRY(hipMemcpy(vals.data(), c->d.vals + (size_t)snap * p.vstride + p.val_off[area],
+                   sizeof(double) * s.nval, hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(rhs.data(), c->d.rhs + (size_t)snap * p.rstride + p.rhs_off[area],
+                   sizeof(double) * rhs.size(), hipMemcpyDeviceToHost));
+  const std::vector<int32_t> ci = canon_index(p, area);
+  const int off = canon_n_internal(p, area);
+  int dim = 0;
+  for (int v = 2 * s.ne; v < 2 * s.nn; ++v) dim += ci[v] >= 0;
+  std::fill(S, S + (size_t)dim * dim, 0.0);
+  const int ne = s.ne;
+  unpack_blocks(p, area, vals, ci, dim, off, [ne](int i) { return i >= ne; }, S);
+  for (int v = 2 * s.ne; v < 2 * s.nn; ++v)
+    if (ci[v] >= 0) bhat[ci[v] - off] = rhs[v];
+  return 0;
+}
+
+int mase_read_gamma_system(mase_ctx* c, int32_t snap, double* S, double* bhat) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  const Plan& p = c->plan;
+  if (snap < 0 || snap >= p.n_snap || !S || !bhat) return fail(MASE_ERR_ARG, "bad argument");
+  const int K = p.n_area;
+  const SysPlan& s = p.sys[K];
+  std::vector<double> vals(std::max(1, s.nval)), rhs(std::max<size_t>(1, 2 * (size_t)s.nn));
+  if (s.nval) HIPTRY(hipMemcpy(vals.data(), c->d.vals + (size_t)snap * p.vstride + p.val_off[K],
+                               sizeof(double) * s.nval, hipMemcpyDeviceToHost));
+  if (s.nn) HIPTRY(hipMemcpy(rhs.data(), c->d.rhs + (size_t)snap * p.rstride + p.rhs_off[K],
+                             sizeof(double) * 2 * s.nn, hipMemcpyDeviceToHost));
+  const std::vector<int32_t> ci = canon_index(p, K);
+  const int dim = p.n_gamma_vars();
+  std::fill(S, S + (size_t)dim * dim, 0.0);
+  unpack_blocks(p, K, vals, ci, dim, 0, [](int) { return true; }, S);
+  for (int v = 0; v < 2 * s.nn; ++v)
+    if (ci[v] >= 0) bhat[ci[v]] = rhs[v];
+  return 0;
+}
+
+int mase_read_step(mase_ctx* c, int32_t snap, double* dx) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  const Plan& p = c->plan;
+  if (snap < 0 || snap >= p.n_snap || !dx) return fail(MASE_ERR_ARG, "bad argument");
+  std::vector<double> rhs(p.rstride);
+  HIPTRY(hipMemcpy(rhs.data(), c->d.rhs + (size_t)snap * p.rstride, sizeof(double) * p.rstride,
+                   hipMemcpyDeviceToHost));
+  for (int b = 0; b < p.n_bus; ++b) {
+    const int src = p.bus_dx_src[b];
+    dx[2 * b] = (b == p.slack) ? 0.0 : rhs[src];
+    dx[2 * b + 1] = rhs[src + 1];
+  }
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,78 @@
+// Device-resident plan and per-iteration buffers shared by the kernels and
+// the host API.  All arrays are flattened over systems (areas 0..K-1, the
+// boundary system K); index fields inside records are already rebased to the
+// flattened arrays.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace mase {
+
+// Per system (area or boundary system).
+struct SysMeta {
+  int32_t nn, ne, nt, ld;         // buses, eliminated, tail, tail leading dim
+  int32_t tail_off, nval, pin_off, nlev;
+  int32_t val_off, rhs_off;       // offsets inside one snapshot's value / rhs block
+  int32_t cd_ptr, up_ptr, rb_ptr, bs_ptr;  // first entry of this system's level pointers
+  int32_t gbus;                   // first entry of local->global bus map
+  int32_t pad;
+};
+
+// Per area templates (Section 4.1).
+struct AreaMeta {
+  int32_t nn, nbr, nrow, nslot;
+  int32_t br, inc_ptr, row, slot;  // first entries in the flattened arrays
+  int32_t rslot, tail_src, slack_local, pad;
+};
+
+enum { MODE_ASSEMBLE = 0, MODE_OBJECTIVE = 1, MODE_EVAL_H = 2 };
+
+struct Dev {
+  // sizes
+  int32_t n_bus, n_meas, n_area, n_snap, slack;
+  int64_t vstride, rstride;
+  // plan
+  const SysMeta* sys;
+  const AreaMeta* area;
+  const int32_t* area_order;
+  const int32_t* gbus;
+  const int32_t *br_lf, *br_lt;
+  const double *br_g, *br_bs, *br_hb;
+  const int32_t *inc_ptr, *inc_end;
+  const int32_t *row_type, *row_loc, *row_meas;
+  const int4* slot;
+  const int2* scon;
+  const int2* rslot;
+  const int2* rcon;
+  const int32_t *cd_ptr, *up_ptr, *rb_ptr, *bs_ptr;
+  const int4* cd_items;
+  const int4* up_tgt;
+  const int2* up_con;
+  const int4* rb_tgt;
+  const int2* rb_con;
+  const int4* bs_items;
+  const int2* bs_con;
+  const int4* g_slot;
+  const int4* g_con;
+  const int2* g_rslot;
+  const int32_t* g_rcon;
+  const int32_t* tail_src;
+  const int32_t* bus_dx_src;
+  // measurements
+  const double* z;  // [n_snap][n_meas]
+  const double* w;  // [n_meas]
+  // state and work buffers
+  double2* x;       // [n_snap][n_bus] (theta, |V|)
+  double* vals;     // [n_snap][vstride]
+  double* rhs;      // [n_snap][rstride]
+  double* jpart;    // [n_snap][n_area]
+  double* hout;     // [n_snap][n_meas] (MODE_EVAL_H)
+  int32_t* active;  // [n_snap]
+  int32_t* iters;   // [n_snap]
+  int32_t* status;  // [n_snap][n_area + 1]: 1 = non-positive pivot
+  double* maxdx;    // [n_snap]
+  const double* tol;  // [1]
+};
+
+}  // namespace mase

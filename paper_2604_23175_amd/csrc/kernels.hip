@@ -1,0 +1,744 @@
+// HIP kernels of one Gauss-Newton iteration of multi-area WLS state
+// estimation for gfx950 (arXiv 2604.23175, Sections 3-4).
+//
+//   k_assemble     fused measurement evaluation + accumulation of each area's
+//                  G^k = H^T W H and b^k = H^T W r (Eq. 4, Eq. 7, Section 4.2)
+//   k_eliminate    level-scheduled sparse Cholesky of the leading block with
+//                  right-looking updates into the dense trailing block
+//                  (Eq. 8-10, Section 4.3); also the sparse part of the
+//                  boundary solve
+//   k_gamma_gather boundary assembly S_Gamma = sum E_k^T S_b^k E_k (Eq. 11,
+//                  Section 4.4), as a gather (no atomics)
+//   k_dense_chol   Cholesky + solve of the boundary system's dense block;
+//                  trailing updates on FP64 MFMA
+//   k_backsolve    scatter-back dx_b^k = E_k dx_Gamma and interior recovery
+//                  dx_i^k = G_ii^-1 (b_i - G_ib dx_b) (Eq. 8)
+//   k_update       x += dx, max |dx| per snapshot, convergence flags
+//
+// Every reduction has a fixed order, so results are bitwise reproducible.
+// All arithmetic is FP64.
+#include "dev.hpp"
+
+namespace mase {
+
+namespace {
+
+constexpr int VM = 0, QINJ = 2, PT = 5, QF = 4, QT = 6;
+constexpr int ROLE_SELF = 0xFFFF, ROLE_OTHER = 0xFFFE;
+
+// Workgroups are handed to the 8 XCDs round-robin by block index.  When the
+// area count is a multiple of 8, all snapshots of one area land on one XCD so
+// that the area's templates are shared through that XCD's L2.
+__device__ inline void area_snap_of_block(int b, int na, int ns, int& ai, int& s) {
+  if ((na & 7) == 0) {
+    const int xcd = b & 7, slot = b >> 3;
+    const int m = slot / ns;
+    s = slot - m * ns;
+    ai = xcd + 8 * m;
+  } else {
+    ai = b / ns;
+    s = b - ai * ns;
+  }
+}
+
+// Flow at end a of a branch (pi model): value and partials with respect to
+// (theta_a, |V|_a) and (theta_o, |V|_o), where c, sn are cos and sin of
+// theta_a - theta_o.  isq selects the reactive flow.
+__device__ inline void flow_end(double g, double bs, double hb, double va, double vo, double c,
+                                double sn, bool isq, double& h, double& dta, double& dva,
+                                double& dto, double& dvo) {
+  const double A = g * c + bs * sn;
+  const double Bq = g * sn - bs * c;
+  if (!isq) {
+    h = g * va * va - va * vo * A;
+    dta = va * vo * Bq;
+    dva = 2.0 * g * va - vo * A;
+    dvo = -va * A;
+  } else {
+    h = -(bs + hb) * va * va - va * vo * Bq;
+    dta = -va * vo * A;
+    dva = -2.0 * (bs + hb) * va - vo * Bq;
+    dvo = -va * Bq;
+  }
+  dto = -dta;
+}
+
+// Value of row r and the partials (dth, dv) of h_r with respect to the bus
+// picked by `role`; returns that bus's local index.
+__device__ inline int row_eval(const Dev& d, const AreaMeta& am, int r, int role, const double2* xs,
+                               const double2* cs, const double* agg, double& h, double& dth,
+                               double& dv) {
+  const int ty = d.row_type[am.row + r];
+  const int loc = d.row_loc[am.row + r];
+  int bus;
+  if (ty == VM) {
+    h = xs[loc].y;
+    dth = 0.0;
+    dv = 1.0;
+    bus = loc;
+  } else if (ty <= QINJ) {
+    const int q = (ty == QINJ) ? 1 : 0;
+    h = agg[6 * loc + q];
+    if (role == ROLE_SELF) {
+      dth = agg[6 * loc + 2 + 2 * q];
+      dv = agg[6 * loc + 3 + 2 * q];
+      bus = loc;
+    } else {
+      const int e = am.br + role;
+      const int lf = d.br_lf[e], lt = d.br_lt[e];
+      const bool from = (lf == loc);
+      const int o = from ? lt : lf;
+      const double2 c = cs[role];
+      double hh, a1, a2, o1, o2;
+      flow_end(d.br_g[e], d.br_bs[e], d.br_hb[e], xs[loc].y, xs[o].y, c.x, from ? c.y : -c.y, q,
+               hh, a1, a2, o1, o2);
+      dth = o1;
+      dv = o2;
+      bus = o;
+    }
+  } else {
+    const int e = am.br + loc;
+    const bool to = (ty >= PT);
+    const bool isq = (ty == QF || ty == QT);
+    const int lf = d.br_lf[e], lt = d.br_lt[e];
+    const int a = to ? lt : lf, o = to ? lf : lt;
+    const double2 c = cs[loc];
+    double ta, tv, to_, vo;
+    flow_end(d.br_g[e], d.br_bs[e], d.br_hb[e], xs[a].y, xs[o].y, c.x, to ? -c.y : c.y, isq, h, ta,
+             tv, to_, vo);
+    if (role == ROLE_SELF) {
+      dth = ta;
+      dv = tv;
+      bus = a;
+    } else {
+      dth = to_;
+      dv = vo;
+      bus = o;
+    }
+  }
+  if (bus == am.slack_local) dth = 0.0;
+  return bus;
+}
+
+__device__ inline double block_sum(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
+  return t;
+}
+
+__device__ inline double nanmax(double m, double v) { return (v > m || v != v) ? v : m; }
+
+__device__ inline double block_max(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v = nanmax(v, __shfl_down(v, off, 64));
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t = nanmax(t, red[i]);
+  return t;
+}
+
+// 2x2 Cholesky of [[a00, .], [a10, a11]]; false on a non-positive pivot.
+__device__ inline bool chol2(double a00, double a10, double a11, double& l00, double& l10,
+                             double& l11) {
+  if (!(a00 > 0.0)) return false;
+  l00 = sqrt(a00);
+  l10 = a10 / l00;
+  const double p = a11 - l10 * l10;
+  if (!(p > 0.0)) return false;
+  l11 = sqrt(p);
+  return true;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Stage 1: fused evaluation and accumulation (one workgroup per area x
+// snapshot).  LDS holds the area's local states, cos/sin of every local
+// branch's angle difference, and every own bus's injection value and
+// self-partials (sums over incident branch ends: Kirchhoff's current law).
+// G slots are visited in packed-storage order and each sums its precomputed,
+// fixed-order contribution list, so the writes are contiguous and the sum is
+// deterministic.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_assemble(Dev d, int a0, int na, int s0, int ns, int mode) {
+  int ai, s;
+  area_snap_of_block(blockIdx.x, na, ns, ai, s);
+  s += s0;
+  const int k = d.area_order[a0 + ai];
+  if (mode == MODE_ASSEMBLE && !d.active[s]) return;
+  const AreaMeta am = d.area[k];
+  const SysMeta sm = d.sys[k];
+  extern __shared__ double2 lds2[];
+  __shared__ double red[16];
+  double2* xs = lds2;
+  double2* cs = xs + am.nn;
+  double* agg = reinterpret_cast<double*>(cs + am.nbr);
+  const double2* xsnap = d.x + (int64_t)s * d.n_bus;
+  const int tid = threadIdx.x, nt = blockDim.x;
+
+  for (int v = tid; v < am.nn; v += nt) xs[v] = xsnap[d.gbus[sm.gbus + v]];
+  __syncthreads();
+  for (int e = tid; e < am.nbr; e += nt) {
+    const int b = am.br + e;
+    double sn, c;
+    sincos(xs[d.br_lf[b]].x - xs[d.br_lt[b]].x, &sn, &c);
+    cs[e] = make_double2(c, sn);
+  }
+  __syncthreads();
+  for (int v = tid; v < am.nn; v += nt) {
+    const int p0 = d.inc_ptr[am.inc_ptr + v], p1 = d.inc_ptr[am.inc_ptr + v + 1];
+    double P = 0, Q = 0, dPt = 0, dPv = 0, dQt = 0, dQv = 0;
+    for (int q = p0; q < p1; ++q) {
+      const int code = d.inc_end[q];
+      const int le = code >> 1, side = code & 1;
+      const int e = am.br + le;
+      const int o = side ? d.br_lf[e] : d.br_lt[e];
+      const double2 c = cs[le];
+      const double sn = side ? -c.y : c.y;
+      double h, ta, tv, to_, vo;
+      flow_end(d.br_g[e], d.br_bs[e], d.br_hb[e], xs[v].y, xs[o].y, c.x, sn, false, h, ta, tv, to_, vo);
+      P += h; dPt += ta; dPv += tv;
+      flow_end(d.br_g[e], d.br_bs[e], d.br_hb[e], xs[v].y, xs[o].y, c.x, sn, true, h, ta, tv, to_, vo);
+      Q += h; dQt += ta; dQv += tv;
+    }
+    double* a = agg + 6 * v;
+    a[0] = P; a[1] = Q; a[2] = dPt; a[3] = dPv; a[4] = dQt; a[5] = dQv;
+  }
+  __syncthreads();
+
+  const double* zs = d.z + (int64_t)s * d.n_meas;
+  if (mode == MODE_EVAL_H) {
+    for (int r = tid; r < am.nrow; r += nt) {
+      double h, a1, a2;
+      row_eval(d, am, r, ROLE_SELF, xs, cs, agg, h, a1, a2);
+      d.hout[(int64_t)s * d.n_meas + d.row_meas[am.row + r]] = h;
+    }
+    return;
+  }
+  // objective J = sum w r^2 over the area's rows (Eq. 2)
+  double jl = 0.0;
+  for (int r = tid; r < am.nrow; r += nt) {
+    const int m = d.row_meas[am.row + r];
+    double h, a1, a2;
+    row_eval(d, am, r, ROLE_SELF, xs, cs, agg, h, a1, a2);
+    const double res = zs[m] - h;
+    jl += d.w[m] * res * res;
+  }
+  const double jt = block_sum(jl, red);
+  if (tid == 0) d.jpart[(int64_t)s * d.n_area + k] = jt;
+  if (mode == MODE_OBJECTIVE) return;
+
+  // G^k slots: slot += w * h_p h_q^T over the slot's contributions
+  double* vals = d.vals + (int64_t)s * d.vstride + sm.val_off;
+  for (int i = tid; i < am.nslot; i += nt) {
+    const int4 sl = d.slot[am.slot + i];
+    double c00 = 0, c10 = 0, c01 = 0, c11 = 0;
+    for (int c = sl.z; c < sl.w; ++c) {
+      const int2 cc = d.scon[c];
+      const int r = cc.x;
+      const double wr = d.w[d.row_meas[am.row + r]];
+      double h, pt, pv, qt, qv;
+      row_eval(d, am, r, cc.y & 0xFFFF, xs, cs, agg, h, pt, pv);
+      row_eval(d, am, r, (cc.y >> 16) & 0xFFFF, xs, cs, agg, h, qt, qv);
+      pt *= wr;
+      pv *= wr;
+      c00 += pt * qt;
+      c10 += pv * qt;
+      c01 += pt * qv;
+      c11 += pv * qv;
+    }
+    const bool diag = sl.y < 0;
+    const int stride = diag ? -sl.y : sl.y;
+    if (diag) c01 = c10;
+    if (sl.x == sm.pin_off) { c00 = 1.0; c10 = 0.0; c01 = 0.0; }
+    double* o = vals + sl.x;
+    o[0] = c00;
+    o[1] = c10;
+    o[stride] = c01;
+    o[stride + 1] = c11;
+  }
+  // b^k = H^T W r
+  double* rhs = d.rhs + (int64_t)s * d.rstride + sm.rhs_off;
+  for (int v = tid; v < am.nn; v += nt) {
+    const int2 rs = d.rslot[am.rslot + v];
+    double b0 = 0, b1 = 0;
+    for (int c = rs.x; c < rs.y; ++c) {
+      const int2 cc = d.rcon[c];
+      const int m = d.row_meas[am.row + cc.x];
+      double h, pt, pv;
+      row_eval(d, am, cc.x, cc.y, xs, cs, agg, h, pt, pv);
+      const double wres = d.w[m] * (zs[m] - h);
+      b0 += pt * wres;
+      b1 += pv * wres;
+    }
+    rhs[2 * v] = b0;
+    rhs[2 * v + 1] = b1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stage 2 (and the sparse part of stage 3): level-scheduled elimination of a
+// system's leading buses.  One workgroup per system x snapshot.  For each
+// elimination-tree level: (a) every column of the level divides by its 2x2
+// pivot (recomputed from the stored, fully updated diagonal block, which is
+// never overwritten) and forms y_j = L_jj^-1 b_j; (b) every update target of
+// the level (a 2x2 block in a later column or in the dense tail) subtracts
+// sum_j L_ij L_pj^T in a fixed order, and every rhs target subtracts
+// sum_j L_ij y_j.  After the last level the tail holds the Schur complement
+// S_b = G_bb - G_bi G_ii^-1 G_ib and the tail rhs holds bhat_b (Eq. 9-10).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_eliminate(Dev d, int sys0, int nsys, int s0, int ns) {
+  int si, s;
+  area_snap_of_block(blockIdx.x, nsys, ns, si, s);
+  s += s0;
+  if (!d.active[s]) return;
+  const int k = (sys0 < d.n_area) ? d.area_order[sys0 + si] : sys0 + si;
+  const SysMeta sm = d.sys[k];
+  double* vals = d.vals + (int64_t)s * d.vstride + sm.val_off;
+  double* rhs = d.rhs + (int64_t)s * d.rstride + sm.rhs_off;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  bool bad = false;
+  for (int lev = 0; lev < sm.nlev; ++lev) {
+    const int c0 = d.cd_ptr[sm.cd_ptr + lev], c1 = d.cd_ptr[sm.cd_ptr + lev + 1];
+    for (int it = c0 + tid; it < c1; it += nt) {
+      const int4 c = d.cd_items[it];
+      const double* D = vals + c.x;
+      double l00, l10, l11;
+      if (!chol2(D[0], D[1], D[3], l00, l10, l11)) { bad = true; l00 = l11 = 1.0; l10 = 0.0; }
+      if (c.y < 0) {
+        const double y0 = rhs[c.z] / l00;
+        rhs[c.z] = y0;
+        rhs[c.z + 1] = (rhs[c.z + 1] - l10 * y0) / l11;
+      } else {
+        double* M = vals + c.y;  // X L^T = M
+        const double x00 = M[0] / l00, x10 = M[1] / l00;
+        M[0] = x00;
+        M[1] = x10;
+        M[2] = (M[2] - x00 * l10) / l11;
+        M[3] = (M[3] - x10 * l10) / l11;
+      }
+    }
+    __syncthreads();
+    const int u0 = d.up_ptr[sm.up_ptr + lev], u1 = d.up_ptr[sm.up_ptr + lev + 1];
+    for (int it = u0 + tid; it < u1; it += nt) {
+      const int4 t = d.up_tgt[it];
+      double a00 = 0, a10 = 0, a01 = 0, a11 = 0;
+      bool sym = false;
+      for (int c = t.z; c < t.w; ++c) {
+        const int2 u = d.up_con[c];
+        const double* L = vals + u.x;
+        const double* P = vals + u.y;
+        a00 += L[0] * P[0] + L[2] * P[2];
+        a10 += L[1] * P[0] + L[3] * P[2];
+        a01 += L[0] * P[1] + L[2] * P[3];
+        a11 += L[1] * P[1] + L[3] * P[3];
+        sym = (u.x == u.y);
+      }
+      if (sym) a01 = a10;
+      double* C = vals + t.x;
+      C[0] -= a00;
+      C[1] -= a10;
+      C[t.y] -= a01;
+      C[t.y + 1] -= a11;
+    }
+    const int r0 = d.rb_ptr[sm.rb_ptr + lev], r1 = d.rb_ptr[sm.rb_ptr + lev + 1];
+    for (int it = r0 + tid; it < r1; it += nt) {
+      const int4 t = d.rb_tgt[it];
+      double b0 = 0, b1 = 0;
+      for (int c = t.y; c < t.z; ++c) {
+        const int2 u = d.rb_con[c];
+        const double* L = vals + u.x;
+        const double y0 = rhs[u.y], y1 = rhs[u.y + 1];
+        b0 += L[0] * y0 + L[2] * y1;
+        b1 += L[1] * y0 + L[3] * y1;
+      }
+      rhs[t.x] -= b0;
+      rhs[t.x + 1] -= b1;
+    }
+    __syncthreads();
+  }
+  if (bad) d.status[(int64_t)s * (d.n_area + 1) + k] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// Stage 3a: boundary assembly (Eq. 11).  Each slot of the boundary system's
+// packed storage pulls the S_b^k blocks that land on it (E_k as index
+// lists); each boundary bus pulls its bhat_b^k entries.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_gamma_gather(Dev d, int s0, int nslot) {
+  const int s = s0 + blockIdx.y;
+  if (!d.active[s]) return;
+  const SysMeta g = d.sys[d.n_area];
+  const double* base = d.vals + (int64_t)s * d.vstride;
+  double* G = d.vals + (int64_t)s * d.vstride + g.val_off;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nslot) {
+    const int4 sl = d.g_slot[i];
+    double c00 = 0, c10 = 0, c01 = 0, c11 = 0;
+    for (int c = sl.z; c < sl.w; ++c) {
+      const int4 cc = d.g_con[c];
+      const double* S = base + cc.x;
+      const double m00 = S[0], m10 = S[1], m01 = S[cc.y], m11 = S[cc.y + 1];
+      c00 += m00;
+      c11 += m11;
+      if (cc.z) { c10 += m01; c01 += m10; }
+      else { c10 += m10; c01 += m01; }
+    }
+    const bool diag = sl.y < 0;
+    const int stride = diag ? -sl.y : sl.y;
+    if (diag) c01 = c10;
+    if (sl.x == g.pin_off) { c00 = 1.0; c10 = 0.0; c01 = 0.0; }
+    double* o = G + sl.x;
+    o[0] = c00;
+    o[1] = c10;
+    o[stride] = c01;
+    o[stride + 1] = c11;
+  }
+  if (i < g.nn) {
+    const double* rb = d.rhs + (int64_t)s * d.rstride;
+    const int2 rs = d.g_rslot[i];
+    double b0 = 0, b1 = 0;
+    for (int c = rs.x; c < rs.y; ++c) {
+      b0 += rb[d.g_rcon[c]];
+      b1 += rb[d.g_rcon[c] + 1];
+    }
+    double* rg = d.rhs + (int64_t)s * d.rstride + g.rhs_off;
+    rg[2 * i] = b0;
+    rg[2 * i + 1] = b1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stage 3b: dense Cholesky and solve of the boundary system's trailing block
+// (the whole S_Gamma in dense mode).  One workgroup per snapshot, blocked
+// right-looking with 16-wide panels; the symmetric trailing update
+// A_ij -= L_ik L_jk^T runs on v_mfma_f64_16x16x4f64.  The block is
+// column-major with leading dimension n (a multiple of 16); rows and columns
+// past the live size are set to the identity first.
+// ---------------------------------------------------------------------------
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(512) k_dense_chol(Dev d, int s0) {
+  const int s = s0 + blockIdx.x;
+  if (!d.active[s]) return;
+  const SysMeta g = d.sys[d.n_area];
+  const int n = g.ld;
+  if (n == 0) return;
+  const int nlive = 2 * g.nt;
+  double* A = d.vals + (int64_t)s * d.vstride + g.val_off + g.tail_off;
+  double* b = d.rhs + (int64_t)s * d.rstride + g.rhs_off + 2 * g.ne;
+  extern __shared__ double bl[];  // [n] rhs, then solution
+  __shared__ double Lk[16 * 17];
+  __shared__ double part[32 * 16];
+  __shared__ int bad;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+  if (tid == 0) bad = 0;
+  for (int i = tid; i < n; i += nt) bl[i] = (i < nlive) ? b[i] : 0.0;
+  // identity padding (lower triangle of the padded rows / columns)
+  for (int c = tid; c < n; c += nt)
+    for (int r = (c > nlive ? c : nlive); r < n; ++r) A[(int64_t)c * n + r] = (r == c) ? 1.0 : 0.0;
+  __syncthreads();
+  const int nb = n / 16;
+  for (int k = 0; k < nb; ++k) {
+    const int c0 = 16 * k;
+    if (tid < 256) {
+      const int r = tid >> 4, c = tid & 15;
+      if (r >= c) Lk[r * 17 + c] = A[(int64_t)(c0 + c) * n + c0 + r];
+    }
+    __syncthreads();
+    for (int c = 0; c < 16; ++c) {
+      if (tid == 0) {
+        const double p = Lk[c * 17 + c];
+        if (!(p > 0.0)) { bad = 1; Lk[c * 17 + c] = 1.0; }
+        else Lk[c * 17 + c] = sqrt(p);
+      }
+      __syncthreads();
+      if (tid > c && tid < 16) Lk[tid * 17 + c] /= Lk[c * 17 + c];
+      __syncthreads();
+      if (tid < 256) {
+        const int r = tid >> 4, m = tid & 15;
+        if (m > c && r >= m) Lk[r * 17 + m] -= Lk[r * 17 + c] * Lk[m * 17 + c];
+      }
+      __syncthreads();
+    }
+    if (tid < 256) {
+      const int r = tid >> 4, c = tid & 15;
+      if (r >= c) A[(int64_t)(c0 + c) * n + c0 + r] = Lk[r * 17 + c];
+    }
+    if (tid == 0) {
+      for (int r = 0; r < 16; ++r) {
+        double y = bl[c0 + r];
+        for (int m = 0; m < r; ++m) y -= Lk[r * 17 + m] * bl[c0 + m];
+        bl[c0 + r] = y / Lk[r * 17 + r];
+      }
+    }
+    __syncthreads();
+    // panel: X L_kk^T = A_ik for every row below the block; rhs update
+    for (int row = c0 + 16 + tid; row < n; row += nt) {
+      double x[16];
+      double acc = 0.0;
+      for (int c = 0; c < 16; ++c) {
+        double a = A[(int64_t)(c0 + c) * n + row];
+        for (int m = 0; m < c; ++m) a -= x[m] * Lk[c * 17 + m];
+        x[c] = a / Lk[c * 17 + c];
+        A[(int64_t)(c0 + c) * n + row] = x[c];
+        acc += x[c] * bl[c0 + c];
+      }
+      bl[row] -= acc;
+    }
+    __syncthreads();
+    // trailing update on MFMA: tiles (I, J), k < J <= I, one tile per wave.
+    // v_mfma_f64_16x16x4f64 operands: lane l holds A[l%16][l/16] and
+    // B[l/16][l%16]; accumulator element q of lane l is D[4q + l/16][l%16].
+    const int m = nb - k - 1;
+    const int ntile = m * (m + 1) / 2;
+    for (int t = wv; t < ntile; t += nw) {
+      int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+      while (I * (I + 1) / 2 > t) --I;
+      while ((I + 1) * (I + 2) / 2 <= t) ++I;
+      const int J = t - I * (I + 1) / 2;
+      const int ri = 16 * (k + 1 + I), rj = 16 * (k + 1 + J);
+      const int li = lane & 15, lk = lane >> 4;
+      d4 acc;
+      for (int q = 0; q < 4; ++q) acc[q] = A[(int64_t)(rj + li) * n + ri + 4 * q + lk];
+      for (int q = 0; q < 4; ++q) {
+        const double a = -A[(int64_t)(c0 + 4 * q + lk) * n + ri + li];
+        const double bb = A[(int64_t)(c0 + 4 * q + lk) * n + rj + li];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+      }
+      for (int q = 0; q < 4; ++q) A[(int64_t)(rj + li) * n + ri + 4 * q + lk] = acc[q];
+    }
+    __syncthreads();
+  }
+  // back substitution L^T x = y, block by block from the bottom
+  for (int k = nb - 1; k >= 0; --k) {
+    const int c0 = 16 * k;
+    {
+      const int c = tid & 15, pp = tid >> 4, np = nt >> 4;
+      double acc = 0.0;
+      for (int r = c0 + 16 + pp; r < n; r += np) acc += A[(int64_t)(c0 + c) * n + r] * bl[r];
+      part[pp * 16 + c] = acc;  // pp < 32 for blockDim <= 512
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const int np = nt >> 4;
+      for (int c = 15; c >= 0; --c) {
+        double t = bl[c0 + c];
+        for (int p = 0; p < np; ++p) t -= part[p * 16 + c];
+        for (int mm = c + 1; mm < 16; ++mm) t -= A[(int64_t)(c0 + c) * n + c0 + mm] * bl[c0 + mm];
+        bl[c0 + c] = t / A[(int64_t)(c0 + c) * n + c0 + c];
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < nlive; i += nt) b[i] = bl[i];
+  if (tid == 0 && bad) d.status[(int64_t)s * (d.n_area + 1) + d.n_area] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// Stage 4a: back substitution.  For an area, first copy dx of its local
+// boundary buses from the boundary solution (dx_b^k = E_k dx_Gamma); then,
+// level by level from the top, dx_j = L_jj^-T (y_j - sum_i L_ij^T dx_i),
+// which is Eq. 8 through the cached factor.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_backsolve(Dev d, int sys0, int nsys, int s0, int ns) {
+  int si, s;
+  area_snap_of_block(blockIdx.x, nsys, ns, si, s);
+  s += s0;
+  if (!d.active[s]) return;
+  const bool is_area = sys0 < d.n_area;
+  const int k = is_area ? d.area_order[sys0 + si] : sys0 + si;
+  const SysMeta sm = d.sys[k];
+  const double* vals = d.vals + (int64_t)s * d.vstride + sm.val_off;
+  double* rb = d.rhs + (int64_t)s * d.rstride;
+  double* rhs = rb + sm.rhs_off;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (is_area) {
+    const AreaMeta am = d.area[k];
+    for (int t = tid; t < sm.nt; t += nt) {
+      const int src = d.tail_src[am.tail_src + t];
+      rhs[2 * (sm.ne + t)] = rb[src];
+      rhs[2 * (sm.ne + t) + 1] = rb[src + 1];
+    }
+  }
+  __syncthreads();
+  for (int lev = sm.nlev - 1; lev >= 0; --lev) {
+    const int b0 = d.bs_ptr[sm.bs_ptr + lev], b1 = d.bs_ptr[sm.bs_ptr + lev + 1];
+    for (int it = b0 + tid; it < b1; it += nt) {
+      const int4 b = d.bs_items[it];
+      double t0 = rhs[b.y], t1 = rhs[b.y + 1];
+      for (int c = b.z; c < b.w; ++c) {
+        const int2 u = d.bs_con[c];
+        const double* L = vals + u.x;
+        const double x0 = rhs[u.y], x1 = rhs[u.y + 1];
+        t0 -= L[0] * x0 + L[1] * x1;
+        t1 -= L[2] * x0 + L[3] * x1;
+      }
+      const double* D = vals + b.x;
+      double l00, l10, l11;
+      if (!chol2(D[0], D[1], D[3], l00, l10, l11)) { l00 = l11 = 1.0; l10 = 0.0; }
+      const double x1 = t1 / l11;
+      rhs[b.y + 1] = x1;
+      rhs[b.y] = (t0 - l10 * x1) / l00;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stage 4b: x += dx for every bus, max |dx| per snapshot, convergence.
+// One workgroup per snapshot.  A snapshot whose factorisation hit a
+// non-positive pivot is frozen without an update.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(512) k_update(Dev d, int s0) {
+  const int s = s0 + blockIdx.x;
+  __shared__ double red[16];
+  __shared__ int bad;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (!d.active[s]) {
+    if (tid == 0) d.maxdx[s] = 0.0;
+    return;
+  }
+  if (tid == 0) {
+    int b = 0;
+    for (int k = 0; k <= d.n_area; ++k) b |= d.status[(int64_t)s * (d.n_area + 1) + k];
+    bad = b;
+  }
+  __syncthreads();
+  double m = 0.0;
+  if (!bad) {
+    const double* rb = d.rhs + (int64_t)s * d.rstride;
+    double2* xs = d.x + (int64_t)s * d.n_bus;
+    for (int bus = tid; bus < d.n_bus; bus += nt) {
+      const int src = d.bus_dx_src[bus];
+      const double dt = (bus == d.slack) ? 0.0 : rb[src];
+      const double dv = rb[src + 1];
+      double2 v = xs[bus];
+      v.x += dt;
+      v.y += dv;
+      xs[bus] = v;
+      m = nanmax(m, fabs(dt));
+      m = nanmax(m, fabs(dv));
+    }
+  }
+  const double mx = block_max(m, red);
+  if (tid == 0) {
+    d.maxdx[s] = mx;
+    d.iters[s] += 1;
+    if (bad || mx < d.tol[0]) d.active[s] = 0;
+  }
+}
+
+// (|V|, theta) arrays <-> interleaved state; flat start when vm == nullptr.
+__global__ void k_pack_state(Dev d, const double* vm, const double* va, double2* xout) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)d.n_snap * d.n_bus;
+  if (i >= n) return;
+  const int bus = (int)(i % d.n_bus);
+  double2 v;
+  v.x = (vm == nullptr || bus == d.slack) ? 0.0 : va[i];
+  v.y = (vm == nullptr) ? 1.0 : vm[i];
+  xout[i] = v;
+}
+
+__global__ void k_unpack_state(Dev d, double* vm, double* va) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)d.n_snap * d.n_bus;
+  if (i >= n) return;
+  const double2 v = d.x[i];
+  vm[i] = v.y;
+  va[i] = v.x;
+}
+
+__global__ void k_reset_flags(Dev d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < d.n_snap) {
+    d.active[i] = 1;
+    d.iters[i] = 0;
+    d.maxdx[i] = 0.0;
+  }
+  if (i < d.n_snap * (d.n_area + 1)) d.status[i] = 0;
+}
+
+}  // namespace mase
+
+// ---------------------------------------------------------------------------
+// Launch wrappers
+// ---------------------------------------------------------------------------
+#include "launch.hpp"
+
+namespace mase {
+
+hipError_t launch_assemble(const Dev& d, int a0, int na, int s0, int ns, int mode, size_t lds,
+                           hipStream_t st) {
+  if (na <= 0 || ns <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_assemble, dim3(na * ns), dim3(256), lds, st, d, a0, na, s0, ns, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_eliminate(const Dev& d, int sys0, int nsys, int s0, int ns, hipStream_t st) {
+  if (nsys <= 0 || ns <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_eliminate, dim3(nsys * ns), dim3(256), 0, st, d, sys0, nsys, s0, ns);
+  return hipGetLastError();
+}
+
+hipError_t launch_gamma_gather(const Dev& d, int s0, int ns, int nslot, int nn, hipStream_t st) {
+  const int work = nslot > nn ? nslot : nn;
+  if (work <= 0 || ns <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gamma_gather, dim3((work + 255) / 256, ns), dim3(256), 0, st, d, s0, nslot);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_chol(const Dev& d, int s0, int ns, int ld, hipStream_t st) {
+  if (ld <= 0 || ns <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dense_chol, dim3(ns), dim3(512), sizeof(double) * (size_t)ld, st, d, s0);
+  return hipGetLastError();
+}
+
+hipError_t launch_backsolve(const Dev& d, int sys0, int nsys, int s0, int ns, hipStream_t st) {
+  if (nsys <= 0 || ns <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_backsolve, dim3(nsys * ns), dim3(256), 0, st, d, sys0, nsys, s0, ns);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(const Dev& d, int s0, int ns, hipStream_t st) {
+  if (ns <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_update, dim3(ns), dim3(512), 0, st, d, s0);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_state(const Dev& d, const double* vm, const double* va, double2* xout,
+                             hipStream_t st) {
+  const int64_t n = (int64_t)d.n_snap * d.n_bus;
+  hipLaunchKernelGGL(k_pack_state, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, d, vm, va, xout);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack_state(const Dev& d, double* vm, double* va, hipStream_t st) {
+  const int64_t n = (int64_t)d.n_snap * d.n_bus;
+  hipLaunchKernelGGL(k_unpack_state, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, d, vm, va);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_flags(const Dev& d, hipStream_t st) {
+  const int n = d.n_snap * (d.n_area + 1);
+  hipLaunchKernelGGL(k_reset_flags, dim3((n + 255) / 256), dim3(256), 0, st, d);
+  return hipGetLastError();
+}
+
+hipError_t allow_assemble_lds(size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_assemble),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+}  // namespace mase

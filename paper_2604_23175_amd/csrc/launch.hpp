@@ -1,0 +1,23 @@
+// Host-side launch wrappers of the kernels in kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dev.hpp"
+
+namespace mase {
+
+hipError_t launch_assemble(const Dev& d, int a0, int na, int s0, int ns, int mode, size_t lds,
+                           hipStream_t st);
+hipError_t launch_eliminate(const Dev& d, int sys0, int nsys, int s0, int ns, hipStream_t st);
+hipError_t launch_gamma_gather(const Dev& d, int s0, int ns, int nslot, int nn, hipStream_t st);
+hipError_t launch_dense_chol(const Dev& d, int s0, int ns, int ld, hipStream_t st);
+hipError_t launch_backsolve(const Dev& d, int sys0, int nsys, int s0, int ns, hipStream_t st);
+hipError_t launch_update(const Dev& d, int s0, int ns, hipStream_t st);
+hipError_t launch_pack_state(const Dev& d, const double* vm, const double* va, double2* xout,
+                             hipStream_t st);
+hipError_t launch_unpack_state(const Dev& d, double* vm, double* va, hipStream_t st);
+hipError_t launch_reset_flags(const Dev& d, hipStream_t st);
+hipError_t allow_assemble_lds(size_t bytes);
+
+}  // namespace mase

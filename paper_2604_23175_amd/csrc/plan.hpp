@@ -1,0 +1,152 @@
+// Host-side setup of the multi-area estimator: maps, orderings, symbolic
+// factorisation, level schedules and contribution lists.  Everything here is
+// integer work done once per topology (arXiv 2604.23175, Section 4.1: the
+// sparsity structure is decoupled from the values and built once; Section
+// 4.3: the factorisation pattern is built once, values are refreshed per
+// iteration).  The result is a Plan that the device side copies to HBM.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace mase {
+
+struct I2 { int32_t x, y; };
+struct I4 { int32_t x, y, z, w; };
+
+// Roles of a support entry of a measurement row (see AreaTemplates).
+constexpr int ROLE_SELF = 0xFFFF;   // the row's own bus (injection bus, flow's measured end, |V| bus)
+constexpr int ROLE_OTHER = 0xFFFE;  // the unmeasured end of a flow row's branch
+constexpr int MAX_LOCAL_BRANCH = 0xFFF0;
+
+// One symmetric positive definite system over "buses" (2x2 blocks: theta, |V|)
+// eliminated by the level-scheduled sparse engine.  Local buses [0, ne) are
+// eliminated in order; [ne, nn) form the dense trailing ("tail") block.
+//
+// Packed value storage (doubles), per snapshot:
+//   for each eliminated bus j: diagonal block (4 doubles, column-major 2x2)
+//   followed by one 2x2 block per row bus i in strct[j] (column-major);
+//   then the tail: a dense column-major matrix with leading dimension ld
+//   (ld = 2*nt rounded up to 16), of which the lower triangle is used.
+// Right-hand side storage: 2 doubles per local bus.
+struct SysPlan {
+  int nn = 0, ne = 0, nt = 0;
+  std::vector<int> gbus;                 // local bus -> global bus
+  std::vector<std::vector<int>> strct;   // eliminated bus j -> sorted local rows i > j
+  std::vector<int32_t> col_off;          // eliminated bus j -> offset of its diagonal block
+  int32_t tail_off = 0;
+  int32_t ld = 0;                        // tail leading dimension (multiple of 16)
+  int32_t nval = 0;                      // doubles of packed storage
+  int32_t pin_off = -1;                  // entry forced to 1 (slack theta pivot), or -1
+  std::vector<int> level;                // eliminated bus -> level (leaves 0)
+  int nlev = 0;
+
+  // Level schedule (all offsets relative to this system's value / rhs base).
+  std::vector<int32_t> cd_ptr;  // [nlev+1] -> cd_items
+  std::vector<I4> cd_items;     // {diag_off, blk_off (-1: the diagonal item), rhs_j, 0}
+  std::vector<int32_t> up_ptr;  // [nlev+1] -> up_tgt
+  std::vector<I4> up_tgt;       // {tgt_off, tgt_stride, cbeg, cend}
+  std::vector<I2> up_con;       // {off L_ij, off L_pj}: target -= L_ij * L_pj^T
+  std::vector<int32_t> rb_ptr;  // [nlev+1] -> rb_tgt
+  std::vector<I4> rb_tgt;       // {rhs_i, cbeg, cend, 0}
+  std::vector<I2> rb_con;       // {off L_ij, rhs_j}: y_i -= L_ij * y_j
+  std::vector<int32_t> bs_ptr;  // [nlev+1] -> bs_items (same levels, run top-down)
+  std::vector<I4> bs_items;     // {diag_off, rhs_j, cbeg, cend}
+  std::vector<I2> bs_con;       // {off L_ij, rhs_i}: t -= L_ij^T * x_i
+
+  int32_t blk_off(int i, int j) const;   // block (i, j), i >= j
+  int32_t blk_stride(int i, int j) const;
+  double elim_flops() const;             // flops of eliminating [0, ne) with rhs
+};
+
+// Measurement templates of one area (Section 4.1): structure-of-arrays rows
+// and the static index maps that let the assembly kernel evaluate residuals
+// and partials and sum their contributions into the packed G^k and b^k.
+struct AreaTemplates {
+  // local branches (at least one end in the area)
+  std::vector<int32_t> br_lf, br_lt;       // local bus of the from / to end
+  std::vector<double> br_g, br_bs, br_hb;  // series conductance, susceptance, half charging
+  std::vector<int32_t> br_gid;             // global branch id
+  // per local bus: incident local branch ends (own buses only), encoded
+  // (branch << 1) | side, side 0 = the bus is the from end
+  std::vector<int32_t> inc_ptr, inc_end;
+  // rows owned by the area
+  std::vector<int32_t> row_type, row_loc, row_meas;  // loc: local bus or local branch
+  // G slots in packed order: {offset, stride, cbeg, cend} (stride < 0 marks a
+  // diagonal block, kept exactly symmetric) and contributions
+  // {row, role_p | role_q << 16}: slot += w * h_p h_q^T
+  std::vector<I4> slot;
+  std::vector<I2> scon;
+  // rhs per local bus: {cbeg, cend} and contributions {row, role}
+  std::vector<I2> rslot;
+  std::vector<I2> rcon;
+  int64_t n_contrib() const { return (int64_t)scon.size() + (int64_t)rcon.size(); }
+};
+
+struct Input {
+  int32_t n_bus, n_branch;
+  const int32_t *br_from, *br_to;
+  const double *br_r, *br_x, *br_b;
+  int32_t slack, n_area;
+  const int32_t* bus_area;
+  int32_t n_meas;
+  const int32_t *meas_type, *meas_at;
+  const double* meas_sigma;
+  int32_t n_snap;
+  int32_t gamma_mode;
+};
+
+struct Plan {
+  int n_bus = 0, n_branch = 0, n_area = 0, n_meas = 0, slack = 0, n_snap = 0;
+  std::vector<int32_t> br_from, br_to;
+  std::vector<double> sigma;
+  std::vector<int32_t> bus_area;
+  std::vector<char> is_bnd;
+  std::vector<int32_t> meas_area;
+  std::vector<int32_t> gamma_bus;         // boundary buses, ascending id (canonical Gamma)
+  std::vector<int32_t> gamma_canon_pos;   // bus -> position in gamma_bus or -1
+
+  // systems 0..n_area-1 are the areas, system n_area is the boundary system
+  std::vector<SysPlan> sys;
+  std::vector<AreaTemplates> tpl;
+  std::vector<std::vector<int32_t>> local_of_bus;  // per area: bus -> local index or -1
+
+  // per-snapshot layout (doubles)
+  std::vector<int32_t> val_off, rhs_off;  // per system
+  int64_t vstride = 0, rstride = 0;
+
+  // boundary assembly (Eq. 11): Gamma slots {offset, stride, cbeg, cend},
+  // contributions {src_off, src_ld, transpose, 0} (offsets relative to the
+  // snapshot's value base); rhs per Gamma local bus {cbeg, cend} with
+  // contributions = source rhs offsets
+  std::vector<I4> g_slot, g_con;
+  std::vector<I2> g_rslot;
+  std::vector<int32_t> g_rcon;
+  // per area tail bus: rhs offset of the same bus in the boundary system
+  std::vector<int32_t> tail_src;      // flattened, per area at tail_src_ptr[k]
+  std::vector<int32_t> tail_src_ptr;  // [n_area+1]
+  // per bus: rhs offset (relative to snapshot rhs base) holding its dx
+  std::vector<int32_t> bus_dx_src;
+  // area order for launches: largest elimination work first
+  std::vector<int32_t> area_order;
+
+  int max_levels() const;
+  double flops_local() const;
+  double flops_gamma() const;
+  double bytes_assembly() const;  // algorithmic HBM bytes per snapshot
+  int n_gamma_vars() const;
+};
+
+// Builds the plan; returns "" on success or an error message (bad input).
+std::string build_plan(const Input& in, Plan& plan);
+
+// Canonical exports (see mase.h).
+std::vector<int32_t> canon_local_vars(const Plan& p, int area);
+int canon_n_internal(const Plan& p, int area);
+std::vector<int32_t> canon_gamma_vars(const Plan& p);
+std::vector<int32_t> canon_E(const Plan& p, int area);
+void canon_pattern(const Plan& p, int area, std::vector<int32_t>& rowptr,
+                   std::vector<int32_t>& colidx);
+
+}  // namespace mase

@@ -1,0 +1,339 @@
+"""Python binding of libmase.so (include/mase.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts numpy arrays
+and device pointers (ints or torch tensors) into C arguments and raises
+MaseError on a non-zero return code.  There is no fallback: if the library
+has not been built, loading it raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmase.so")
+
+MASE_VM, MASE_PINJ, MASE_QINJ, MASE_PF, MASE_QF, MASE_PT, MASE_QT = range(7)
+MASE_OK, MASE_NOT_CONVERGED = 0, 1
+MASE_ERR_ARG, MASE_ERR_STATE, MASE_ERR_NOT_POSDEF = -1, -2, -3
+MASE_ERR_HIP, MASE_ERR_OOM, MASE_ERR_NO_DEVICE = -4, -5, -6
+MASE_GAMMA_SPARSE, MASE_GAMMA_DENSE = 0, 1
+
+INFO = {"n_gamma": 0, "n_boundary_bus": 1, "gamma_tail": 2, "nnz_factor": 3, "max_levels": 4,
+        "flops_local": 5, "flops_gamma": 6, "bytes_assembly": 7, "n_snap": 8, "n_area": 9}
+MAPS = {"boundary_flag": 0, "meas_area": 1, "gamma_vars": 2, "local_vars": 3,
+        "n_internal": 4, "E": 5}
+
+# Every symbol include/mase.h declares (checked by the CPU test suite).
+SYMBOLS = (
+    "mase_default_options", "mase_create", "mase_destroy", "mase_last_error", "mase_strerror",
+    "mase_set_measurements", "mase_set_measurements_dev", "mase_set_state", "mase_set_state_dev",
+    "mase_gn_iter", "mase_solve", "mase_state", "mase_state_dev", "mase_objective",
+    "mase_eval_h_dev", "mase_info", "mase_export_map", "mase_export_pattern",
+    "mase_stage_assemble", "mase_stage_condense", "mase_stage_gamma_assemble",
+    "mase_stage_gamma_solve", "mase_stage_update", "mase_read_local_system", "mase_read_schur",
+    "mase_read_gamma_system", "mase_read_step",
+)
+
+
+class MaseError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("stream", ctypes.c_void_p), ("batched", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("gamma_mode", ctypes.c_int32),
+                ("host_only", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("tune_cache", ctypes.c_char_p)]
+
+
+_lib = None
+
+
+def load():
+    """Load libmase.so (built by __graft_entry__.build()); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    f64p = ctypes.POINTER(ctypes.c_double)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    sig = {
+        "mase_default_options": (None, [ctypes.POINTER(Options)]),
+        "mase_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, i32p, i32p, f64p, f64p, f64p,
+                                       ctypes.c_int32, ctypes.c_int32, i32p, ctypes.c_int32, i32p, i32p,
+                                       f64p, ctypes.c_int32, ctypes.POINTER(Options),
+                                       ctypes.POINTER(P)]),
+        "mase_destroy": (None, [P]),
+        "mase_last_error": (ctypes.c_char_p, []),
+        "mase_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "mase_set_measurements": (ctypes.c_int, [P, f64p, f64p]),
+        "mase_set_measurements_dev": (ctypes.c_int, [P, P, P]),
+        "mase_set_state": (ctypes.c_int, [P, f64p, f64p]),
+        "mase_set_state_dev": (ctypes.c_int, [P, P, P]),
+        "mase_gn_iter": (ctypes.c_int, [P, f64p]),
+        "mase_solve": (ctypes.c_int, [P, ctypes.c_double, ctypes.c_int32, i32p, i32p]),
+        "mase_state": (ctypes.c_int, [P, f64p, f64p]),
+        "mase_state_dev": (ctypes.c_int, [P, P, P]),
+        "mase_objective": (ctypes.c_int, [P, f64p]),
+        "mase_eval_h_dev": (ctypes.c_int, [P, P, P, P]),
+        "mase_info": (ctypes.c_int, [P, ctypes.c_int32, i64p]),
+        "mase_export_map": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int32, i32p, ctypes.c_int64, i64p]),
+        "mase_export_pattern": (ctypes.c_int, [P, ctypes.c_int32, i32p, i32p, ctypes.c_int64, i64p]),
+        "mase_stage_assemble": (ctypes.c_int, [P]),
+        "mase_stage_condense": (ctypes.c_int, [P]),
+        "mase_stage_gamma_assemble": (ctypes.c_int, [P]),
+        "mase_stage_gamma_solve": (ctypes.c_int, [P]),
+        "mase_stage_update": (ctypes.c_int, [P, f64p]),
+        "mase_read_local_system": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int32, f64p, f64p]),
+        "mase_read_schur": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int32, f64p, f64p]),
+        "mase_read_gamma_system": (ctypes.c_int, [P, ctypes.c_int32, f64p, f64p]),
+        "mase_read_step": (ctypes.c_int, [P, ctypes.c_int32, f64p]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _dptr(x):
+    """Device pointer of a torch tensor (or an int)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return ctypes.c_void_p(x)
+    return ctypes.c_void_p(x.data_ptr())
+
+
+def _check(rc, allow=(MASE_OK,)):
+    if rc in allow:
+        return rc
+    msg = load().mase_last_error().decode()
+    raise MaseError(rc, msg)
+
+
+def mase_default_options():
+    o = Options()
+    load().mase_default_options(ctypes.byref(o))
+    return o
+
+
+def mase_create(n_bus, br_from, br_to, br_r, br_x, br_b, slack_bus, n_area, bus_area,
+                meas_type, meas_at, meas_sigma, n_snap, opt=None):
+    lib = load()
+    f, fp = _i32(br_from)
+    t, tp = _i32(br_to)
+    r, rp = _f64(br_r)
+    x, xp = _f64(br_x)
+    b, bp = _f64(br_b)
+    a, ap = _i32(bus_area)
+    mt, mtp = _i32(meas_type)
+    ma, map_ = _i32(meas_at)
+    ms, msp = _f64(meas_sigma)
+    out = ctypes.c_void_p()
+    o = opt if opt is not None else mase_default_options()
+    rc = lib.mase_create(int(n_bus), int(f.size), fp, tp, rp, xp, bp, int(slack_bus), int(n_area), ap,
+                         int(mt.size), mtp, map_, msp, int(n_snap), ctypes.byref(o), ctypes.byref(out))
+    _check(rc)
+    return out
+
+
+class Mase:
+    """One context (mase_ctx*) with the C calls as methods of the same names."""
+
+    def __init__(self, n_bus, br_from, br_to, br_r, br_x, br_b, slack_bus, n_area, bus_area,
+                 meas_type, meas_at, meas_sigma, n_snap, batched=True, use_graph=True,
+                 gamma_mode=MASE_GAMMA_SPARSE, host_only=False, stream=None):
+        self.lib = load()
+        o = mase_default_options()
+        o.batched = int(bool(batched))
+        o.use_graph = int(bool(use_graph))
+        o.gamma_mode = int(gamma_mode)
+        o.host_only = int(bool(host_only))
+        o.stream = stream
+        self.n_bus = int(n_bus)
+        self.n_meas = int(np.asarray(meas_type).size)
+        self.n_snap = int(n_snap)
+        self.n_area = int(n_area)
+        self.slack = int(slack_bus)
+        self.ctx = mase_create(n_bus, br_from, br_to, br_r, br_x, br_b, slack_bus, n_area, bus_area,
+                               meas_type, meas_at, meas_sigma, n_snap, o)
+
+    @classmethod
+    def from_grid(cls, grid, meas_type, meas_at, meas_sigma, n_snap, slack=None, **kw):
+        return cls(grid.n_bus, grid.br_from, grid.br_to, grid.br_r, grid.br_x, grid.br_b,
+                   grid.slack if slack is None else slack, grid.n_area, grid.bus_area,
+                   meas_type, meas_at, meas_sigma, n_snap, **kw)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            self.lib.mase_destroy(self.ctx)
+        self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ---- measurements and state ----
+    def mase_set_measurements(self, z, w=None):
+        z, zp = _f64(z)
+        assert z.size == self.n_snap * self.n_meas
+        if w is not None:
+            w, wp = _f64(w)
+        else:
+            wp = None
+        _check(self.lib.mase_set_measurements(self.ctx, zp, wp))
+
+    def mase_set_measurements_dev(self, z_dev, w_dev=None):
+        _check(self.lib.mase_set_measurements_dev(self.ctx, _dptr(z_dev), _dptr(w_dev)))
+
+    def mase_set_state(self, vm=None, va=None):
+        if vm is None:
+            _check(self.lib.mase_set_state(self.ctx, None, None))
+            return
+        vm, vp = _f64(vm)
+        va, ap = _f64(va)
+        assert vm.size == va.size == self.n_snap * self.n_bus
+        _check(self.lib.mase_set_state(self.ctx, vp, ap))
+
+    def mase_set_state_dev(self, vm_dev=None, va_dev=None):
+        _check(self.lib.mase_set_state_dev(self.ctx, _dptr(vm_dev), _dptr(va_dev)))
+
+    def mase_gn_iter(self):
+        out = np.zeros(self.n_snap)
+        _check(self.lib.mase_gn_iter(self.ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def mase_solve(self, tol=1e-6, max_iter=10):
+        iters = np.zeros(self.n_snap, dtype=np.int32)
+        conv = np.zeros(self.n_snap, dtype=np.int32)
+        rc = self.lib.mase_solve(self.ctx, float(tol), int(max_iter),
+                                 iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                 conv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        _check(rc, allow=(MASE_OK, MASE_NOT_CONVERGED))
+        return iters, conv.astype(bool)
+
+    def mase_state(self):
+        vm = np.zeros((self.n_snap, self.n_bus))
+        va = np.zeros((self.n_snap, self.n_bus))
+        _check(self.lib.mase_state(self.ctx, vm.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   va.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return vm, va
+
+    def mase_state_dev(self, vm_dev, va_dev):
+        _check(self.lib.mase_state_dev(self.ctx, _dptr(vm_dev), _dptr(va_dev)))
+
+    def mase_objective(self):
+        J = np.zeros(self.n_snap)
+        _check(self.lib.mase_objective(self.ctx, J.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return J
+
+    def mase_eval_h_dev(self, vm_dev, va_dev, h_dev):
+        _check(self.lib.mase_eval_h_dev(self.ctx, _dptr(vm_dev), _dptr(va_dev), _dptr(h_dev)))
+
+    # ---- structure ----
+    def mase_info(self, key):
+        v = ctypes.c_int64()
+        _check(self.lib.mase_info(self.ctx, INFO[key] if isinstance(key, str) else int(key),
+                                  ctypes.byref(v)))
+        return int(v.value)
+
+    def mase_export_map(self, kind, area=0):
+        k = MAPS[kind] if isinstance(kind, str) else int(kind)
+        n = ctypes.c_int64()
+        self.lib.mase_export_map(self.ctx, k, int(area), None, 0, ctypes.byref(n))
+        buf = np.zeros(max(1, n.value), dtype=np.int32)
+        _check(self.lib.mase_export_map(self.ctx, k, int(area),
+                                        buf.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                        buf.size, ctypes.byref(n)))
+        return buf[:n.value]
+
+    def mase_export_pattern(self, area):
+        n = ctypes.c_int64()
+        nloc = self.mase_export_map("local_vars", area).size
+        self.lib.mase_export_pattern(self.ctx, int(area), None, None, 0, ctypes.byref(n))
+        rp = np.zeros(nloc + 1, dtype=np.int32)
+        ci = np.zeros(max(1, n.value), dtype=np.int32)
+        _check(self.lib.mase_export_pattern(self.ctx, int(area),
+                                            rp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                            ci.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                            ci.size, ctypes.byref(n)))
+        return rp, ci[:n.value]
+
+    # ---- stages and debug reads ----
+    def mase_stage_assemble(self):
+        _check(self.lib.mase_stage_assemble(self.ctx))
+
+    def mase_stage_condense(self):
+        _check(self.lib.mase_stage_condense(self.ctx))
+
+    def mase_stage_gamma_assemble(self):
+        _check(self.lib.mase_stage_gamma_assemble(self.ctx))
+
+    def mase_stage_gamma_solve(self):
+        _check(self.lib.mase_stage_gamma_solve(self.ctx))
+
+    def mase_stage_update(self):
+        out = np.zeros(self.n_snap)
+        _check(self.lib.mase_stage_update(self.ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def mase_read_local_system(self, snap, area):
+        n = self.mase_export_map("local_vars", area).size
+        G = np.zeros((n, n))
+        b = np.zeros(n)
+        _check(self.lib.mase_read_local_system(self.ctx, int(snap), int(area),
+                                               G.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                               b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return G, b
+
+    def mase_read_schur(self, snap, area):
+        n = self.mase_export_map("E", area).size
+        S = np.zeros((n, n))
+        b = np.zeros(n)
+        _check(self.lib.mase_read_schur(self.ctx, int(snap), int(area),
+                                        S.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return S, b
+
+    def mase_read_gamma_system(self, snap):
+        n = self.mase_info("n_gamma")
+        S = np.zeros((max(n, 1), max(n, 1)))
+        b = np.zeros(max(n, 1))
+        _check(self.lib.mase_read_gamma_system(self.ctx, int(snap),
+                                               S.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                               b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return S[:n, :n], b[:n]
+
+    def mase_read_step(self, snap):
+        dx = np.zeros(2 * self.n_bus)
+        _check(self.lib.mase_read_step(self.ctx, int(snap), dx.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return dx

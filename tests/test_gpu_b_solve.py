@@ -1,0 +1,159 @@
+"""GPU end-to-end solves against the oracle, schedules and failure handling.
+
+* states after mase_solve match the oracle's centralized GN to 1e-8 relative
+  (theta in rad, |V| in p.u.) with the same iteration counts;
+* noise-free measurements return the generating state;
+* the batched, graph-captured schedule, the batched schedule without the
+  graph and the plain per-area/per-snapshot schedule give bitwise identical
+  states (same arithmetic in the same order), and two runs are identical;
+* dense and sparse factorisation of the boundary system agree;
+* a zero weight equals a deleted row;
+* an unobservable area reports MASE_ERR_NOT_POSDEF, max_iter = 1 reports
+  MASE_NOT_CONVERGED.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import Case, assert_state_close, say
+from gridgen import synth
+from oracle import network as nw
+from paper_2604_23175_amd import mase
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("name,n_snap", [("c0", 4), ("k5", 4), ("c1", 3)])
+def test_solve_matches_oracle(name, n_snap):
+    say("solve", name, n_snap)
+    c = Case(name, n_snap, seed=21)
+    m = c.ctx()
+    iters, conv = m.mase_solve(1e-6, 10)
+    vm, va = m.mase_state()
+    for i in range(n_snap):
+        ref = c.oracle_solve(i)
+        assert conv[i] and ref["converged"]
+        assert iters[i] == ref["iters"], (iters[i], ref["iters"])
+        assert_state_close(vm[i], va[i], ref["vm"], ref["va"], 1e-8)
+    J = m.mase_objective()
+    for i in range(n_snap):
+        assert abs(J[i] - c.oracle_solve(i)["J"]) <= 1e-8 * J[i]
+    m.close()
+
+
+def test_noise_free_recovery():
+    say("noise-free")
+    c = Case("c1", 2, seed=2)
+    c.z = np.stack([c.net.h(c.vm_true[i], c.va_true[i]) for i in range(2)])
+    m = c.ctx()
+    iters, conv = m.mase_solve(1e-12, 15)
+    assert conv.all()
+    vm, va = m.mase_state()
+    np.testing.assert_allclose(vm, c.vm_true, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(va, c.va_true, rtol=0, atol=1e-10)
+    m.close()
+
+
+def test_schedules_bitwise_identical():
+    say("schedules")
+    c = Case("k5", 3, seed=4)
+    out = []
+    for kw in (dict(), dict(use_graph=False), dict(batched=False)):
+        m = c.ctx(**kw)
+        iters, conv = m.mase_solve(1e-6, 10)
+        out.append((m.mase_state(), iters))
+        m.close()
+    for (vm, va), it in out[1:]:
+        np.testing.assert_array_equal(vm, out[0][0][0])
+        np.testing.assert_array_equal(va, out[0][0][1])
+        np.testing.assert_array_equal(it, out[0][1])
+
+
+def test_repeat_runs_bitwise_identical():
+    say("determinism")
+    c = Case("c1", 2, seed=8)
+    m = c.ctx()
+    m.mase_solve(1e-6, 10)
+    a = m.mase_state()
+    m.mase_set_state()
+    m.mase_solve(1e-6, 10)
+    b = m.mase_state()
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+    m.close()
+
+
+def test_dense_and_sparse_gamma_agree():
+    say("gamma modes")
+    c = Case("c1", 2, seed=9)
+    res = []
+    for gm in (mase.MASE_GAMMA_SPARSE, mase.MASE_GAMMA_DENSE):
+        m = c.ctx(gamma_mode=gm)
+        m.mase_solve(1e-10, 12)
+        res.append(m.mase_state())
+        m.close()
+    assert_state_close(res[0][0], res[0][1], res[1][0], res[1][1], 1e-10)
+
+
+def test_zero_weight_equals_deleted_row():
+    say("masking")
+    c = Case("k5", 1, seed=6)
+    w = 1.0 / c.s ** 2
+    w[c.t == synth.QT] = 0.0
+    c.w = w
+    m = c.ctx()
+    m.mase_stage_assemble()
+    keep = c.t != synth.QT
+    m2 = mase.Mase.from_grid(c.g, c.t[keep], c.a[keep], c.s[keep], 1)
+    m2.mase_set_measurements(c.z[:, keep])
+    m2.mase_set_state()
+    m2.mase_stage_assemble()
+    for k in range(c.g.n_area):
+        G1, b1 = m.mase_read_local_system(0, k)
+        G2, b2 = m2.mase_read_local_system(0, k)
+        np.testing.assert_array_equal(G1, G2)
+        np.testing.assert_array_equal(b1, b2)
+    m.close()
+    m2.close()
+    m = c.ctx()
+    m.mase_solve(1e-6, 10)
+    vm, va = m.mase_state()
+    ref = c.oracle_solve(0)
+    assert_state_close(vm[0], va[0], ref["vm"], ref["va"], 1e-8)
+    m.close()
+
+
+def test_unobservable_area_reports_not_posdef():
+    say("not posdef")
+    c = Case("k5", 2, seed=1)
+    w = 1.0 / c.s ** 2
+    w[c.A.meas_area == 2] = 0.0
+    c.w = w
+    m = c.ctx()
+    with pytest.raises(mase.MaseError) as e:
+        m.mase_gn_iter()
+    assert e.value.code == mase.MASE_ERR_NOT_POSDEF
+    m.close()
+
+
+def test_iteration_cap_reports_not_converged():
+    say("not converged")
+    c = Case("c0", 2, seed=1)
+    m = c.ctx()
+    iters, conv = m.mase_solve(1e-6, 1)
+    assert not conv.any()
+    assert (iters == 1).all()
+    m.close()
+
+
+def test_slack_on_boundary_solve():
+    say("slack on boundary")
+    from gpu_common import boundary_slack, grid
+    c = Case("k5", 2, seed=12, slack=boundary_slack(grid("k5")))
+    assert c.A.is_boundary[c.slack]
+    m = c.ctx()
+    m.mase_solve(1e-6, 10)
+    vm, va = m.mase_state()
+    for i in range(2):
+        ref = c.oracle_solve(i)
+        assert_state_close(vm[i], va[i], ref["vm"], ref["va"], 1e-8)
+    m.close()

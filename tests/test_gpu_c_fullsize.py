@@ -1,0 +1,49 @@
+"""GPU parity at the benchmark's full sizes, in the launch configuration the
+benchmark times (batched, graph-captured, sparse boundary solve).
+
+The oracle is too slow to solve every snapshot, so each test solves the whole
+batch on the GPU and checks a seeded sample of snapshots against the oracle,
+plus properties that hold for every snapshot (all converge within the
+10-iteration cap; the objective sits near its chi-square expectation m - n).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_common import Case, assert_state_close, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("name,sample", [("c2", (0, 31, 63)), ("c3", (5, 62))])
+def test_full_batch_sampled_parity(name, sample):
+    say("full size", name)
+    c = Case(name, 64, seed=0)
+    m = c.ctx()
+    iters, conv = m.mase_solve(1e-6, 10)
+    assert conv.all(), iters
+    vm, va = m.mase_state()
+    J = m.mase_objective()
+    mn = c.net.m - c.net.n
+    assert np.all(np.abs(J - mn) <= 6 * math.sqrt(2 * mn)), (J.min(), J.max(), mn)
+    for i in sample:
+        say("  oracle snapshot", i)
+        ref = c.oracle_solve(i)
+        assert ref["converged"] and iters[i] == ref["iters"]
+        assert_state_close(vm[i], va[i], ref["vm"], ref["va"], 1e-8)
+    m.close()
+
+
+def test_plain_schedule_matches_batched_c2():
+    say("plain vs batched c2")
+    c = Case("c2", 2, seed=1)
+    res = []
+    for kw in (dict(), dict(batched=False)):
+        m = c.ctx(**kw)
+        it, conv = m.mase_solve(1e-6, 10)
+        assert conv.all()
+        res.append(m.mase_state())
+        m.close()
+    np.testing.assert_array_equal(res[0][0], res[1][0])
+    np.testing.assert_array_equal(res[0][1], res[1][1])
