@@ -1,0 +1,233 @@
+#!/usr/bin/env python3
+"""Benchmark: solved state-estimation snapshots per second on one MI355X.
+
+Workload: the synthetic 9241-bus / 16049-branch grid in 32 areas (stand-in
+for PEGASE-9241), 64 snapshots per batch drifted from the base state (|V|
+jitter N(0, 0.003), theta jitter N(0, 0.005)) with fresh measurement noise,
+full measurement set (|V|, P/Q injections at every bus, P/Q flows at both
+branch ends).  A step solves the whole batch from its starting point to
+max |dx| < 1e-6 (at most 10 Gauss-Newton iterations) and writes the states to
+device memory.  Measurements are resident in HBM before the timed region.
+
+Printed as one JSON line: the batched path (all areas x snapshots per launch,
+hipGraph-captured iteration) as `value`, the plain per-area / per-snapshot
+schedule on the same batch as `plain`, per-kernel times from HIP events
+recorded around each stage kernel inside the timed region, the roofline of the
+dominant kernel, and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "solved SE snapshots/sec at 9.2k-bus (‖Δx‖<1e-6), batched+warm vs plain GN"
+HBM_PEAK = 8.0e12       # B/s, MI355X HBM3E
+FP64_PEAK = 78.6e12     # flop/s, MI355X dense FP64 (vector and matrix)
+TOL, MAX_ITER, N_SNAP = 1e-6, 10, 64
+WORKLOAD = "c2"
+
+
+def make_inputs(n_snap, seed=0):
+    from gridgen import synth
+    g = synth.make_config(WORKLOAD)
+    t, a, s = synth.measurement_set(g.n_bus, g.n_branch)
+    b = synth.make_batch(g, n_snap, seed)
+    va = b.va_true - b.va_true[:, [g.slack]]
+    return g, t, a, s, b.vm_true, va, b.eps
+
+
+def cpu_leg(budget_s):
+    """Oracle (centralized numpy/scipy GN) on a bounded sample, one thread."""
+    from oracle import network as nw
+    from oracle import wls
+    g, t, a, s, vm, va, eps = make_inputs(N_SNAP)
+    net = nw.from_grid(g, t, a, s)
+    done, iters = 0, 0
+    t0 = time.perf_counter()
+    for i in range(N_SNAP):
+        z = nw.measurements(net, vm[i], va[i], eps[i])
+        out = wls.gauss_newton(net, z, tol=TOL, max_iter=MAX_ITER)
+        done += 1
+        iters += out["iters"]
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    print(json.dumps({"snapshots": done, "seconds": dt, "iters": iters}))
+
+
+def run_cpu_baseline(budget_s):
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-leg", str(budget_s)],
+                         capture_output=True, text=True, env=env, check=True)
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    return {"value": r["snapshots"] / r["seconds"], "unit": "snapshots/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {r['snapshots']} of the {N_SNAP} snapshots of the benchmark batch, flat start, "
+                      f"centralized FP64 GN with scipy splu, {r['iters']} GN iterations in {r['seconds']:.1f} s, "
+                      "one thread (OMP/OPENBLAS/MKL_NUM_THREADS=1)"}
+
+
+def traffic_for(kernel):
+    """Counter-measured HBM bytes per launch, if taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    src = open(os.path.join(ROOT, "paper_2604_23175_amd", "csrc", "kernels.hip"), "rb").read()
+    digest = hashlib.sha256(src).hexdigest()[:16]
+    d = json.load(open(path))
+    ent = d.get(kernel)
+    if not ent or ent.get("kernels_sha") != digest:
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--cpu-leg", type=float, default=None, help=argparse.SUPPRESS)
+    args = ap.parse_args()
+    if args.cpu_leg is not None:
+        cpu_leg(args.cpu_leg)
+        return
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(snapshots would shard across GPUs with no exchange; see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2604_23175_amd import mase
+
+    dev = torch.device("cuda:0")
+    g, t, a, s, vm_true, va_true, eps = make_inputs(N_SNAP)
+    ctx = mase.Mase.from_grid(g, t, a, s, N_SNAP)
+    # synthetic measurements z = h(x_true) + sigma * eps, built on the device
+    vmt = torch.tensor(vm_true, device=dev)
+    vat = torch.tensor(va_true, device=dev)
+    h = torch.empty((N_SNAP, t.size), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    ctx.mase_eval_h_dev(vmt, vat, h)
+    torch.cuda.synchronize()
+    z = h + torch.tensor(s, device=dev) * torch.tensor(eps, device=dev)
+    torch.cuda.synchronize()
+    ctx.mase_set_measurements_dev(z)
+    vm_out = torch.empty((N_SNAP, g.n_bus), dtype=torch.float64, device=dev)
+    va_out = torch.empty_like(vm_out)
+    torch.cuda.synchronize()
+
+    def step(c):
+        c.mase_set_state_dev(None, None)
+        iters, conv = c.mase_solve(TOL, MAX_ITER)
+        c.mase_state_dev(vm_out, va_out)
+        return iters, conv
+
+    def timed(c, steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n_it, ok = 0, True
+        for _ in range(steps):
+            iters, conv = step(c)
+            n_it += int(iters.sum())
+            ok &= bool(conv.all())
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, n_it, ok
+
+    for _ in range(args.warmup):
+        step(ctx)
+    # headline: graph-replayed batched iterations
+    dt, tot_iters, all_conv = timed(ctx, args.steps)
+    value = N_SNAP * args.steps / dt
+    # the same steps again with a HIP event pair around every stage kernel
+    # (direct launches: event pairs inside a graph cannot be timed)
+    ctx.mase_profile(True)
+    pdt_prof, _, _ = timed(ctx, args.steps)
+    prof = ctx.mase_profile_read()
+    ctx.mase_profile(False)
+    info = {k: ctx.mase_info(k) for k in mase.INFO}
+    vm_b, va_b = vm_out.cpu().numpy(), va_out.cpu().numpy()
+
+    # plain schedule (per-area launches on per-area streams, one snapshot at a time)
+    plain = None
+    if not args.no_plain:
+        pc = mase.Mase.from_grid(g, t, a, s, N_SNAP, batched=False)
+        pc.mase_set_measurements_dev(z)
+        torch.cuda.synchronize()
+        step(pc)
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        p_iters = 0
+        for _ in range(args.plain_steps):
+            iters, conv = step(pc)
+            p_iters += int(iters.sum())
+        torch.cuda.synchronize()
+        pdt = time.perf_counter() - p0
+        same = bool(np.array_equal(vm_out.cpu().numpy(), vm_b) and np.array_equal(va_out.cpu().numpy(), va_b))
+        plain = {"value": N_SNAP * args.plain_steps / pdt, "unit": "snapshots/s",
+                 "ms_per_step": 1e3 * pdt / args.plain_steps,
+                 "gn_iters_per_s": p_iters / pdt, "states_bitwise_equal_to_batched": same,
+                 "schedule": "one snapshot at a time, flat start, per-area launches on 32 streams, no graph"}
+        pc.close()
+
+    # roofline of the dominant kernel (largest accumulated time in the timed region)
+    per_unit = {"assemble": ("hbm", info["bytes_assembly"]), "condense": ("hbm", info["bytes_condense"]),
+                "backsolve": ("hbm", info["bytes_backsolve"]), "gamma_dense": ("mfma", info["flops_dense"])}
+    stages = {k: v for k, v in prof.items() if v["launches"]}
+    kernel_names = {"assemble": "k_assemble", "condense": "k_eliminate", "backsolve": "k_backsolve",
+                    "gamma_dense": "k_dense_chol"}
+    dom = max((k for k in stages if k in per_unit), key=lambda k: stages[k]["ms"])
+    bound, unit_work = per_unit[dom]
+    st = stages[dom]
+    avg_ms = st["ms"] / st["launches"]
+    units_per_launch = st["units"] / st["launches"]
+    achieved = unit_work * units_per_launch / (avg_ms * 1e-3)
+    peak = HBM_PEAK if bound == "hbm" else FP64_PEAK
+    roofline = {"bound": bound, "kernel": kernel_names[dom], "achieved": achieved / (1e9 if bound == "hbm" else 1e12),
+                "peak": peak / (1e9 if bound == "hbm" else 1e12),
+                "unit": "GB/s" if bound == "hbm" else "TFLOP/s", "frac": achieved / peak,
+                "traffic": traffic_for(kernel_names[dom]), "avg_launch_ms": avg_ms,
+                "per_snapshot_work": unit_work, "snapshots_per_launch": units_per_launch}
+    others = {}
+    for k, (b, w) in per_unit.items():
+        if k in stages and k != dom:
+            sk = stages[k]
+            am = sk["ms"] / sk["launches"]
+            ach = w * (sk["units"] / sk["launches"]) / (am * 1e-3)
+            pk = HBM_PEAK if b == "hbm" else FP64_PEAK
+            others[k] = {"bound": b, "avg_launch_ms": am, "frac": ach / pk}
+
+    cpu = None if args.no_cpu else run_cpu_baseline(args.cpu_budget)
+    out = {
+        "metric": METRIC, "value": value, "unit": "snapshots/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "9241-bus/16049-branch synthetic grid, 32 areas, 64 snapshots per batch, "
+                               "flat start, batched + hipGraph, sparse boundary solve",
+                   "n_bus": g.n_bus, "n_branch": g.n_branch, "n_area": g.n_area, "snapshots": N_SNAP,
+                   "n_meas": int(t.size), "n_gamma": info["n_gamma"], "tol": TOL, "max_iter": MAX_ITER,
+                   "warm_start": False},
+        "gn_iters_per_s": tot_iters / dt, "all_converged": all_conv,
+        "profiled_pass": {"value": N_SNAP * args.steps / pdt_prof, "unit": "snapshots/s",
+                          "note": "same steps, kernels launched directly with HIP events around each"},
+        "mean_iters": tot_iters / (N_SNAP * args.steps),
+        "plain": plain, "speedup_vs_plain": (value / plain["value"]) if plain else None,
+        "stages_ms_per_step": {k: v["ms"] / args.steps for k, v in stages.items()},
+        "roofline": roofline, "roofline_other_kernels": others, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -200,6 +200,38 @@ int mase_objective(mase_ctx* ctx, double* J);
  */
 int mase_eval_h_dev(mase_ctx* ctx, const double* vm_dev, const double* va_dev, double* h_dev);
 
+/* ---- per-stage timing ---- */
+
+/* Kernel stages of one iteration, in launch order. */
+enum {
+  MASE_STAGE_ASSEMBLE = 0,   /* fused evaluation + accumulation (Eq. 7) */
+  MASE_STAGE_CONDENSE,       /* per-area elimination (Eq. 8-10) */
+  MASE_STAGE_GAMMA_GATHER,   /* boundary assembly (Eq. 11) */
+  MASE_STAGE_GAMMA_SPARSE,   /* sparse elimination inside the boundary system */
+  MASE_STAGE_GAMMA_DENSE,    /* dense Cholesky + solve of its trailing block */
+  MASE_STAGE_GAMMA_BACK,     /* back substitution inside the boundary system */
+  MASE_STAGE_BACKSOLVE,      /* scatter-back + interior recovery (Eq. 8) */
+  MASE_STAGE_UPDATE,         /* x += dx, convergence */
+  MASE_N_STAGE
+};
+
+/*
+ * enable != 0: record a pair of HIP events on the context's stream around
+ * every stage kernel of the batched schedule and accumulate their elapsed
+ * times after each iteration; clears the accumulators.  While enabled, the
+ * batched schedule launches its kernels directly instead of replaying the
+ * captured graph (event pairs inside a graph cannot be timed).  enable == 0
+ * stops recording and returns to graph replay.
+ */
+int mase_profile(mase_ctx* ctx, int32_t enable);
+
+/*
+ * Accumulated per-stage kernel time in ms, launch counts and work units (the
+ * number of active snapshots each launch processed), each [MASE_N_STAGE]
+ * (host, any may be NULL).
+ */
+int mase_profile_read(mase_ctx* ctx, double* total_ms, int64_t* launches, int64_t* units);
+
 /* ---- sizes and structure exports (work on host-only contexts too) ---- */
 
 enum {
@@ -212,7 +244,10 @@ enum {
   MASE_INFO_FLOPS_GAMMA,      /* flops per snapshot-iteration, boundary solve */
   MASE_INFO_BYTES_ASSEMBLY,   /* algorithmic HBM bytes per snapshot of assembly */
   MASE_INFO_N_SNAP,
-  MASE_INFO_N_AREA
+  MASE_INFO_N_AREA,
+  MASE_INFO_BYTES_CONDENSE,   /* algorithmic HBM bytes per snapshot of local elimination */
+  MASE_INFO_FLOPS_DENSE,      /* flops per snapshot of the dense boundary block */
+  MASE_INFO_BYTES_BACKSOLVE   /* algorithmic HBM bytes per snapshot of back substitution */
 };
 int mase_info(const mase_ctx* ctx, int32_t what, int64_t* value);
 

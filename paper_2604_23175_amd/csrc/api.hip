@@ -62,6 +62,13 @@ struct mase_ctx {
   double* h_maxdx = nullptr;
   double* h_tol = nullptr;
   std::vector<SysMeta> hsys;
+  // per-stage timing
+  bool prof = false;
+  hipEvent_t pev[2 * MASE_N_STAGE] = {};
+  bool pused[MASE_N_STAGE] = {};
+  double pms[MASE_N_STAGE] = {};
+  int64_t plaunch[MASE_N_STAGE] = {};
+  int64_t punits[MASE_N_STAGE] = {};
 };
 
 namespace {
@@ -233,20 +240,74 @@ int upload_plan(mase_ctx* c) {
 
 const SysMeta& gsys(const mase_ctx* c) { return c->hsys[c->plan.n_area]; }
 
+struct StageMark {
+  mase_ctx* c;
+  hipStream_t st;
+  int stage;
+  StageMark(mase_ctx* c_, hipStream_t st_, int s_) : c(c_), st(st_), stage(s_) {
+    if (c->prof) {
+      (void)hipEventRecord(c->pev[2 * stage], st);
+      c->pused[stage] = true;
+    }
+  }
+  ~StageMark() {
+    if (c->prof) (void)hipEventRecord(c->pev[2 * stage + 1], st);
+  }
+};
+
 int launch_batched_iteration(mase_ctx* c, hipStream_t st) {
   const int K = c->plan.n_area, S = c->plan.n_snap;
   const Dev& d = c->d;
-  HIPTRY(launch_assemble(d, 0, K, 0, S, MODE_ASSEMBLE, c->lds_asm, st));
-  HIPTRY(launch_eliminate(d, 0, K, 0, S, st));
+  for (bool& u : c->pused) u = false;
+  {
+    StageMark m(c, st, MASE_STAGE_ASSEMBLE);
+    HIPTRY(launch_assemble(d, 0, K, 0, S, MODE_ASSEMBLE, c->lds_asm, st));
+  }
+  {
+    StageMark m(c, st, MASE_STAGE_CONDENSE);
+    HIPTRY(launch_eliminate(d, 0, K, 0, S, st));
+  }
   const SysMeta& g = gsys(c);
   if (g.nn > 0) {
-    HIPTRY(launch_gamma_gather(d, 0, S, c->nslot_g, g.nn, st));
-    if (g.ne > 0) HIPTRY(launch_eliminate(d, K, 1, 0, S, st));
-    HIPTRY(launch_dense_chol(d, 0, S, g.ld, st));
-    if (g.ne > 0) HIPTRY(launch_backsolve(d, K, 1, 0, S, st));
+    {
+      StageMark m(c, st, MASE_STAGE_GAMMA_GATHER);
+      HIPTRY(launch_gamma_gather(d, 0, S, c->nslot_g, g.nn, st));
+    }
+    if (g.ne > 0) {
+      StageMark m(c, st, MASE_STAGE_GAMMA_SPARSE);
+      HIPTRY(launch_eliminate(d, K, 1, 0, S, st));
+    }
+    {
+      StageMark m(c, st, MASE_STAGE_GAMMA_DENSE);
+      HIPTRY(launch_dense_chol(d, 0, S, g.ld, st));
+    }
+    if (g.ne > 0) {
+      StageMark m(c, st, MASE_STAGE_GAMMA_BACK);
+      HIPTRY(launch_backsolve(d, K, 1, 0, S, st));
+    }
   }
-  HIPTRY(launch_backsolve(d, 0, K, 0, S, st));
-  HIPTRY(launch_update(d, 0, S, st));
+  {
+    StageMark m(c, st, MASE_STAGE_BACKSOLVE);
+    HIPTRY(launch_backsolve(d, 0, K, 0, S, st));
+  }
+  {
+    StageMark m(c, st, MASE_STAGE_UPDATE);
+    HIPTRY(launch_update(d, 0, S, st));
+  }
+  return 0;
+}
+
+// After a synchronised iteration: add each recorded stage's elapsed time.
+int accumulate_profile(mase_ctx* c, int nactive) {
+  if (!c->prof) return 0;
+  for (int i = 0; i < MASE_N_STAGE; ++i) {
+    if (!c->pused[i]) continue;
+    float ms = 0.f;
+    HIPTRY(hipEventElapsedTime(&ms, c->pev[2 * i], c->pev[2 * i + 1]));
+    c->pms[i] += ms;
+    c->plaunch[i] += 1;
+    c->punits[i] += nactive;
+  }
   return 0;
 }
 
@@ -460,6 +521,7 @@ void mase_destroy(mase_ctx* c) {
     for (auto s : c->astreams) if (s) { (void)hipStreamSynchronize(s); (void)hipStreamDestroy(s); }
     for (auto e : c->aevents) if (e) (void)hipEventDestroy(e);
     if (c->ev_main) (void)hipEventDestroy(c->ev_main);
+    for (auto e : c->pev) if (e) (void)hipEventDestroy(e);
     for (void* p : c->dallocs) (void)hipFree(p);
     if (c->h_active) (void)hipHostFree(c->h_active);
     if (c->h_iters) (void)hipHostFree(c->h_iters);
@@ -516,6 +578,7 @@ int mase_set_state(mase_ctx* c, const double* vm, const double* va) {
   }
   HIPTRY(launch_reset_flags(c->d, c->stream));
   HIPTRY(hipStreamSynchronize(c->stream));
+  for (int s = 0; s < c->plan.n_snap; ++s) c->h_active[s] = 1;
   return 0;
 }
 
@@ -525,6 +588,7 @@ int mase_set_state_dev(mase_ctx* c, const double* vm_dev, const double* va_dev) 
   if ((vm_dev == nullptr) != (va_dev == nullptr)) return fail(MASE_ERR_ARG, "give both vm and va or neither");
   HIPTRY(launch_pack_state(c->d, vm_dev, va_dev, c->d.x, c->stream));
   HIPTRY(launch_reset_flags(c->d, c->stream));
+  for (int s = 0; s < c->plan.n_snap; ++s) c->h_active[s] = 1;
   return 0;
 }
 
@@ -533,8 +597,12 @@ int mase_gn_iter(mase_ctx* c, double* max_abs_dx) {
   if (rc) return rc;
   if (!c->have_z) return fail(MASE_ERR_STATE, "no measurements set");
   const int S = c->plan.n_snap;
+  int nactive_before = 0;
+  for (int s = 0; s < S; ++s) nactive_before += c->h_active[s] != 0;
   if (c->opt.batched) {
-    if (c->opt.use_graph) {
+    // event pairs recorded as graph nodes cannot be timed, so a profiled
+    // iteration launches the same kernels directly on the stream
+    if (c->opt.use_graph && !c->prof) {
       if (!c->gexec) {
         HIPTRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
         rc = launch_batched_iteration(c, c->stream);
@@ -550,6 +618,7 @@ int mase_gn_iter(mase_ctx* c, double* max_abs_dx) {
       if ((rc = launch_batched_iteration(c, c->stream))) return rc;
     }
     if ((rc = read_flags(c))) return rc;
+    if ((rc = accumulate_profile(c, nactive_before))) return rc;
   } else {
     // plain schedule: snapshots one after another
     HIPTRY(hipMemcpyAsync(c->h_active, c->d.active, sizeof(int32_t) * S, hipMemcpyDeviceToHost, c->stream));
@@ -668,6 +737,32 @@ int mase_eval_h_dev(mase_ctx* c, const double* vm_dev, const double* va_dev, dou
   return 0;
 }
 
+int mase_profile(mase_ctx* c, int32_t enable) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  for (int i = 0; i < 2 * MASE_N_STAGE; ++i)
+    if (!c->pev[i]) HIPTRY(hipEventCreate(&c->pev[i]));
+  for (int i = 0; i < MASE_N_STAGE; ++i) {
+    c->pms[i] = 0.0;
+    c->plaunch[i] = 0;
+    c->punits[i] = 0;
+  }
+  HIPTRY(hipStreamSynchronize(c->stream));
+  c->prof = enable != 0;
+  return 0;
+}
+
+int mase_profile_read(mase_ctx* c, double* total_ms, int64_t* launches, int64_t* units) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  for (int i = 0; i < MASE_N_STAGE; ++i) {
+    if (total_ms) total_ms[i] = c->pms[i];
+    if (launches) launches[i] = c->plaunch[i];
+    if (units) units[i] = c->punits[i];
+  }
+  return 0;
+}
+
 int mase_info(const mase_ctx* c, int32_t what, int64_t* value) {
   if (!c || !value) return fail(MASE_ERR_ARG, "null argument");
   const Plan& p = c->plan;
@@ -683,6 +778,9 @@ int mase_info(const mase_ctx* c, int32_t what, int64_t* value) {
     case MASE_INFO_BYTES_ASSEMBLY: v = (int64_t)p.bytes_assembly(); break;
     case MASE_INFO_N_SNAP: v = p.n_snap; break;
     case MASE_INFO_N_AREA: v = p.n_area; break;
+    case MASE_INFO_BYTES_CONDENSE: v = (int64_t)p.bytes_condense(); break;
+    case MASE_INFO_FLOPS_DENSE: v = (int64_t)p.flops_dense(); break;
+    case MASE_INFO_BYTES_BACKSOLVE: v = (int64_t)p.bytes_backsolve(); break;
     default: return fail(MASE_ERR_ARG, "unknown info key");
   }
   *value = v;

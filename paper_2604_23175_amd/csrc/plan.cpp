@@ -260,6 +260,23 @@ double Plan::bytes_assembly() const {
   return b + tmpl / std::max(1, n_snap);
 }
 
+double Plan::bytes_condense() const {
+  double b = 0;
+  for (int k = 0; k < n_area; ++k) b += 2.0 * 8 * sys[k].nval + 2.0 * 16 * sys[k].nn;
+  return b;
+}
+
+double Plan::bytes_backsolve() const {
+  double b = 0;
+  for (int k = 0; k <= n_area; ++k) b += 8.0 * sys[k].tail_off + 2.0 * 16 * sys[k].nn;
+  return b;
+}
+
+double Plan::flops_dense() const {
+  const double nd = sys[n_area].ld;
+  return nd * nd * nd / 3.0 + 2.0 * nd * nd;
+}
+
 int Plan::n_gamma_vars() const {
   int n = 0;
   for (int b : gamma_bus) n += (b == slack) ? 1 : 2;

@@ -135,6 +135,9 @@ struct Plan {
   double flops_local() const;
   double flops_gamma() const;
   double bytes_assembly() const;  // algorithmic HBM bytes per snapshot
+  double bytes_condense() const;  // read G once, write L once (areas), rhs
+  double bytes_backsolve() const; // read L once, rhs read / write
+  double flops_dense() const;     // dense boundary block: n^3/3 + 2 n^2
   int n_gamma_vars() const;
 };
 

@@ -22,7 +22,10 @@ MASE_ERR_HIP, MASE_ERR_OOM, MASE_ERR_NO_DEVICE = -4, -5, -6
 MASE_GAMMA_SPARSE, MASE_GAMMA_DENSE = 0, 1
 
 INFO = {"n_gamma": 0, "n_boundary_bus": 1, "gamma_tail": 2, "nnz_factor": 3, "max_levels": 4,
-        "flops_local": 5, "flops_gamma": 6, "bytes_assembly": 7, "n_snap": 8, "n_area": 9}
+        "flops_local": 5, "flops_gamma": 6, "bytes_assembly": 7, "n_snap": 8, "n_area": 9,
+        "bytes_condense": 10, "flops_dense": 11, "bytes_backsolve": 12}
+STAGES = ("assemble", "condense", "gamma_gather", "gamma_sparse", "gamma_dense", "gamma_back",
+          "backsolve", "update")
 MAPS = {"boundary_flag": 0, "meas_area": 1, "gamma_vars": 2, "local_vars": 3,
         "n_internal": 4, "E": 5}
 
@@ -34,7 +37,7 @@ SYMBOLS = (
     "mase_eval_h_dev", "mase_info", "mase_export_map", "mase_export_pattern",
     "mase_stage_assemble", "mase_stage_condense", "mase_stage_gamma_assemble",
     "mase_stage_gamma_solve", "mase_stage_update", "mase_read_local_system", "mase_read_schur",
-    "mase_read_gamma_system", "mase_read_step",
+    "mase_read_gamma_system", "mase_read_step", "mase_profile", "mase_profile_read",
 )
 
 
@@ -97,6 +100,8 @@ def load():
         "mase_read_schur": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int32, f64p, f64p]),
         "mase_read_gamma_system": (ctypes.c_int, [P, ctypes.c_int32, f64p, f64p]),
         "mase_read_step": (ctypes.c_int, [P, ctypes.c_int32, f64p]),
+        "mase_profile": (ctypes.c_int, [P, ctypes.c_int32]),
+        "mase_profile_read": (ctypes.c_int, [P, f64p, i64p, i64p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -258,6 +263,21 @@ class Mase:
 
     def mase_eval_h_dev(self, vm_dev, va_dev, h_dev):
         _check(self.lib.mase_eval_h_dev(self.ctx, _dptr(vm_dev), _dptr(va_dev), _dptr(h_dev)))
+
+    # ---- per-stage timing ----
+    def mase_profile(self, enable=True):
+        _check(self.lib.mase_profile(self.ctx, int(bool(enable))))
+
+    def mase_profile_read(self):
+        n = len(STAGES)
+        ms = np.zeros(n)
+        la = np.zeros(n, dtype=np.int64)
+        un = np.zeros(n, dtype=np.int64)
+        _check(self.lib.mase_profile_read(self.ctx, ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          la.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                          un.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return {STAGES[i]: {"ms": float(ms[i]), "launches": int(la[i]), "units": int(un[i])}
+                for i in range(n)}
 
     # ---- structure ----
     def mase_info(self, key):
