@@ -181,11 +181,13 @@ def main():
         pc.close()
 
     # roofline of the dominant kernel (largest accumulated time in the timed region)
+    # per-snapshot algorithmic work of each kernel and the roofline that bounds it
     per_unit = {"assemble": ("hbm", info["bytes_assembly"]), "condense": ("hbm", info["bytes_condense"]),
-                "backsolve": ("hbm", info["bytes_backsolve"]), "gamma_dense": ("mfma", info["flops_dense"])}
+                "backsolve": ("hbm", info["bytes_backsolve"]), "gamma_dense": ("mfma", info["flops_dense"]),
+                "gamma_sparse": ("alu", info["flops_gamma_sparse"])}
     stages = {k: v for k, v in prof.items() if v["launches"]}
-    kernel_names = {"assemble": "k_assemble", "condense": "k_eliminate", "backsolve": "k_backsolve",
-                    "gamma_dense": "k_dense_chol"}
+    kernel_names = {"assemble": "k_assemble", "condense": "k_eliminate<256>", "backsolve": "k_backsolve<256>",
+                    "gamma_dense": "k_dense_chol", "gamma_sparse": "k_eliminate<1024>"}
     dom = max((k for k in stages if k in per_unit), key=lambda k: stages[k]["ms"])
     bound, unit_work = per_unit[dom]
     st = stages[dom]
@@ -193,9 +195,9 @@ def main():
     units_per_launch = st["units"] / st["launches"]
     achieved = unit_work * units_per_launch / (avg_ms * 1e-3)
     peak = HBM_PEAK if bound == "hbm" else FP64_PEAK
-    roofline = {"bound": bound, "kernel": kernel_names[dom], "achieved": achieved / (1e9 if bound == "hbm" else 1e12),
-                "peak": peak / (1e9 if bound == "hbm" else 1e12),
-                "unit": "GB/s" if bound == "hbm" else "TFLOP/s", "frac": achieved / peak,
+    scale = 1e9 if bound == "hbm" else 1e12
+    roofline = {"bound": bound, "kernel": kernel_names[dom], "achieved": achieved / scale,
+                "peak": peak / scale, "unit": "GB/s" if bound == "hbm" else "TFLOP/s", "frac": achieved / peak,
                 "traffic": traffic_for(kernel_names[dom]), "avg_launch_ms": avg_ms,
                 "per_snapshot_work": unit_work, "snapshots_per_launch": units_per_launch}
     others = {}

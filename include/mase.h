@@ -247,7 +247,9 @@ enum {
   MASE_INFO_N_AREA,
   MASE_INFO_BYTES_CONDENSE,   /* algorithmic HBM bytes per snapshot of local elimination */
   MASE_INFO_FLOPS_DENSE,      /* flops per snapshot of the dense boundary block */
-  MASE_INFO_BYTES_BACKSOLVE   /* algorithmic HBM bytes per snapshot of back substitution */
+  MASE_INFO_BYTES_BACKSOLVE,  /* algorithmic HBM bytes per snapshot of back substitution */
+  MASE_INFO_FLOPS_GAMMA_SPARSE, /* flops per snapshot, sparse part of the boundary solve */
+  MASE_INFO_GAMMA_LEVELS      /* elimination levels of the boundary system's sparse part */
 };
 int mase_info(const mase_ctx* ctx, int32_t what, int64_t* value);
 

@@ -52,6 +52,7 @@ struct mase_ctx {
   double* stage_va = nullptr;
   double* dtol = nullptr;
   size_t lds_asm = 0;
+  bool br_lds = false;
   int nslot_g = 0;
   bool have_z = false;
   hipGraph_t graph = nullptr;
@@ -136,6 +137,7 @@ int upload_plan(mase_ctx* c) {
     sm[i] = m;
   }
   std::vector<int32_t> br_lf, br_lt, inc_ptr, inc_end, row_type, row_loc, row_meas;
+  std::vector<I4> rowrec;
   std::vector<double> br_g, br_bs, br_hb;
   std::vector<I4> slot;
   std::vector<I2> scon, rslot, rcon;
@@ -160,6 +162,7 @@ int upload_plan(mase_ctx* c) {
     row_type.insert(row_type.end(), t.row_type.begin(), t.row_type.end());
     row_loc.insert(row_loc.end(), t.row_loc.begin(), t.row_loc.end());
     row_meas.insert(row_meas.end(), t.row_meas.begin(), t.row_meas.end());
+    for (size_t r = 0; r < t.row_type.size(); ++r) rowrec.push_back({t.row_type[r], t.row_loc[r], t.row_meas[r], 0});
     a.slot = (int32_t)slot.size();
     for (const I4& s : t.slot)
       slot.push_back({s.x, s.y, s.z + (int32_t)scon.size(), s.w + (int32_t)scon.size()});
@@ -171,8 +174,18 @@ int upload_plan(mase_ctx* c) {
     a.tail_src = p.tail_src_ptr[k];
     a.slack_local = p.local_of_bus[k][p.slack];
     am[k] = a;
-    lds = std::max(lds, (size_t)(16 * a.nn + 16 * a.nbr + 48 * a.nn));
   }
+  int dev = 0, maxlds = 0;
+  HIPTRY(hipGetDevice(&dev));
+  HIPTRY(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  // stage branch records in LDS when every area fits
+  size_t lds_br = 0, lds_nobr = 0;
+  for (int k = 0; k < K; ++k) {
+    lds_br = std::max(lds_br, assemble_lds_bytes(am[k].nn, am[k].nbr, true));
+    lds_nobr = std::max(lds_nobr, assemble_lds_bytes(am[k].nn, am[k].nbr, false));
+  }
+  c->br_lds = lds_br <= (size_t)maxlds;
+  lds = c->br_lds ? lds_br : lds_nobr;
   c->lds_asm = lds;
   c->hsys = sm;
   c->nslot_g = (int)p.g_slot.size();
@@ -185,7 +198,7 @@ int upload_plan(mase_ctx* c) {
   UP(sys, sm); UP(area, am); UP(area_order, p.area_order); UP(gbus, gbus);
   UP(br_lf, br_lf); UP(br_lt, br_lt); UP(br_g, br_g); UP(br_bs, br_bs); UP(br_hb, br_hb);
   UP(inc_ptr, inc_ptr); UP(inc_end, inc_end);
-  UP(row_type, row_type); UP(row_loc, row_loc); UP(row_meas, row_meas);
+  UP(row_type, row_type); UP(row_loc, row_loc); UP(row_meas, row_meas); UP(rowrec, rowrec);
   UP(slot, slot); UP(scon, scon); UP(rslot, rslot); UP(rcon, rcon);
   UP(cd_ptr, cd_ptr); UP(up_ptr, up_ptr); UP(rb_ptr, rb_ptr); UP(bs_ptr, bs_ptr);
   UP(cd_items, cd_items); UP(up_tgt, up_tgt); UP(up_con, up_con);
@@ -227,14 +240,11 @@ int upload_plan(mase_ctx* c) {
   c->h_tol[0] = 1e-6;
   HIPTRY(hipMemcpy(c->dtol, c->h_tol, sizeof(double), hipMemcpyHostToDevice));
 
-  int dev = 0, maxlds = 0;
-  HIPTRY(hipGetDevice(&dev));
-  HIPTRY(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   if (c->lds_asm > (size_t)maxlds)
     return fail(MASE_ERR_ARG, "an area needs " + std::to_string(c->lds_asm) +
                                   " bytes of LDS for assembly; the device allows " +
                                   std::to_string(maxlds));
-  if (c->lds_asm > 65536) HIPTRY(allow_assemble_lds(c->lds_asm));
+  if (c->lds_asm > 65536) HIPTRY(allow_assemble_lds(c->lds_asm, c->br_lds));
   return 0;
 }
 
@@ -261,7 +271,7 @@ int launch_batched_iteration(mase_ctx* c, hipStream_t st) {
   for (bool& u : c->pused) u = false;
   {
     StageMark m(c, st, MASE_STAGE_ASSEMBLE);
-    HIPTRY(launch_assemble(d, 0, K, 0, S, MODE_ASSEMBLE, c->lds_asm, st));
+    HIPTRY(launch_assemble(d, 0, K, 0, S, MODE_ASSEMBLE, c->lds_asm, c->br_lds, st));
   }
   {
     StageMark m(c, st, MASE_STAGE_CONDENSE);
@@ -323,7 +333,7 @@ int launch_plain_iteration(mase_ctx* c, int s) {
   for (int i = 0; i < ns; ++i) HIPTRY(hipStreamWaitEvent(c->astreams[i], c->ev_main, 0));
   for (int ai = 0; ai < K; ++ai) {
     hipStream_t as = c->astreams[ai % ns];
-    HIPTRY(launch_assemble(d, ai, 1, s, 1, MODE_ASSEMBLE, c->lds_asm, as));
+    HIPTRY(launch_assemble(d, ai, 1, s, 1, MODE_ASSEMBLE, c->lds_asm, c->br_lds, as));
     HIPTRY(launch_eliminate(d, ai, 1, s, 1, as));
   }
   for (int i = 0; i < ns; ++i) {
@@ -713,7 +723,7 @@ int mase_objective(mase_ctx* c, double* J) {
   if (!J) return fail(MASE_ERR_ARG, "null output");
   if (!c->have_z) return fail(MASE_ERR_STATE, "no measurements set");
   const int K = c->plan.n_area, S = c->plan.n_snap;
-  HIPTRY(launch_assemble(c->d, 0, K, 0, S, MODE_OBJECTIVE, c->lds_asm, c->stream));
+  HIPTRY(launch_assemble(c->d, 0, K, 0, S, MODE_OBJECTIVE, c->lds_asm, c->br_lds, c->stream));
   std::vector<double> jp((size_t)S * K);
   HIPTRY(hipMemcpyAsync(jp.data(), c->d.jpart, sizeof(double) * jp.size(), hipMemcpyDeviceToHost, c->stream));
   HIPTRY(hipStreamSynchronize(c->stream));
@@ -733,7 +743,7 @@ int mase_eval_h_dev(mase_ctx* c, const double* vm_dev, const double* va_dev, dou
   HIPTRY(launch_pack_state(d, vm_dev, va_dev, c->xscratch, c->stream));
   d.x = c->xscratch;
   d.hout = h_dev;
-  HIPTRY(launch_assemble(d, 0, c->plan.n_area, 0, c->plan.n_snap, MODE_EVAL_H, c->lds_asm, c->stream));
+  HIPTRY(launch_assemble(d, 0, c->plan.n_area, 0, c->plan.n_snap, MODE_EVAL_H, c->lds_asm, c->br_lds, c->stream));
   return 0;
 }
 
@@ -781,6 +791,8 @@ int mase_info(const mase_ctx* c, int32_t what, int64_t* value) {
     case MASE_INFO_BYTES_CONDENSE: v = (int64_t)p.bytes_condense(); break;
     case MASE_INFO_FLOPS_DENSE: v = (int64_t)p.flops_dense(); break;
     case MASE_INFO_BYTES_BACKSOLVE: v = (int64_t)p.bytes_backsolve(); break;
+    case MASE_INFO_FLOPS_GAMMA_SPARSE: v = (int64_t)p.sys[p.n_area].elim_flops(); break;
+    case MASE_INFO_GAMMA_LEVELS: v = p.sys[p.n_area].nlev; break;
     default: return fail(MASE_ERR_ARG, "unknown info key");
   }
   *value = v;
@@ -826,7 +838,7 @@ int mase_stage_assemble(mase_ctx* c) {
   int rc = check_device(c);
   if (rc) return rc;
   if (!c->have_z) return fail(MASE_ERR_STATE, "no measurements set");
-  HIPTRY(launch_assemble(c->d, 0, c->plan.n_area, 0, c->plan.n_snap, MODE_ASSEMBLE, c->lds_asm, c->stream));
+  HIPTRY(launch_assemble(c->d, 0, c->plan.n_area, 0, c->plan.n_snap, MODE_ASSEMBLE, c->lds_asm, c->br_lds, c->stream));
   HIPTRY(hipStreamSynchronize(c->stream));
   return 0;
 }

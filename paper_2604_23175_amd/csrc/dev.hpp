@@ -41,6 +41,7 @@ struct Dev {
   const double *br_g, *br_bs, *br_hb;
   const int32_t *inc_ptr, *inc_end;
   const int32_t *row_type, *row_loc, *row_meas;
+  const int4* rowrec;  // per area row: {type, loc, meas, 0}
   const int4* slot;
   const int2* scon;
   const int2* rslot;

@@ -18,13 +18,14 @@
 // Every reduction has a fixed order, so results are bitwise reproducible.
 // All arithmetic is FP64.
 #include "dev.hpp"
+#include "launch.hpp"
 
 namespace mase {
 
 namespace {
 
 constexpr int VM = 0, QINJ = 2, PT = 5, QF = 4, QT = 6;
-constexpr int ROLE_SELF = 0xFFFF, ROLE_OTHER = 0xFFFE;
+constexpr int ROLE_SELF = 0xFFFF;
 
 // Workgroups are handed to the 8 XCDs round-robin by block index.  When the
 // area count is a multiple of 8, all snapshots of one area land on one XCD so
@@ -63,62 +64,74 @@ __device__ inline void flow_end(double g, double bs, double hb, double va, doubl
   dto = -dta;
 }
 
-// Value of row r and the partials (dth, dv) of h_r with respect to the bus
-// picked by `role`; returns that bus's local index.
-__device__ inline int row_eval(const Dev& d, const AreaMeta& am, int r, int role, const double2* xs,
-                               const double2* cs, const double* agg, double& h, double& dth,
-                               double& dv) {
-  const int ty = d.row_type[am.row + r];
-  const int loc = d.row_loc[am.row + r];
-  int bus;
-  if (ty == VM) {
-    h = xs[loc].y;
-    dth = 0.0;
-    dv = 1.0;
-    bus = loc;
-  } else if (ty <= QINJ) {
-    const int q = (ty == QINJ) ? 1 : 0;
-    h = agg[6 * loc + q];
-    if (role == ROLE_SELF) {
-      dth = agg[6 * loc + 2 + 2 * q];
-      dv = agg[6 * loc + 3 + 2 * q];
-      bus = loc;
-    } else {
-      const int e = am.br + role;
-      const int lf = d.br_lf[e], lt = d.br_lt[e];
-      const bool from = (lf == loc);
-      const int o = from ? lt : lf;
-      const double2 c = cs[role];
-      double hh, a1, a2, o1, o2;
-      flow_end(d.br_g[e], d.br_bs[e], d.br_hb[e], xs[loc].y, xs[o].y, c.x, from ? c.y : -c.y, q,
-               hh, a1, a2, o1, o2);
-      dth = o1;
-      dv = o2;
-      bus = o;
-    }
-  } else {
-    const int e = am.br + loc;
-    const bool to = (ty >= PT);
-    const bool isq = (ty == QF || ty == QT);
-    const int lf = d.br_lf[e], lt = d.br_lt[e];
-    const int a = to ? lt : lf, o = to ? lf : lt;
-    const double2 c = cs[loc];
-    double ta, tv, to_, vo;
-    flow_end(d.br_g[e], d.br_bs[e], d.br_hb[e], xs[a].y, xs[o].y, c.x, to ? -c.y : c.y, isq, h, ta,
-             tv, to_, vo);
-    if (role == ROLE_SELF) {
-      dth = ta;
-      dv = tv;
-      bus = a;
-    } else {
-      dth = to_;
-      dv = vo;
-      bus = o;
-    }
+// Branch record as staged in LDS.
+struct BrL {
+  double g, bs, hb;
+  int lf, lt;
+};
+
+// Area-local evaluation context of the assembly kernel.
+template <bool BR_LDS>
+struct Asm {
+  const Dev* d;
+  int br0, slack_local;
+  const double2* xs;   // local (theta, |V|)
+  const double2* cs;   // cos, sin of theta_f - theta_t per local branch
+  const double* agg;   // per local bus: P, Q, dP/dth, dP/dV, dQ/dth, dQ/dV
+  const BrL* brl;      // branch records (BR_LDS)
+
+  __device__ BrL branch(int e) const {
+    if (BR_LDS) return brl[e];
+    const int b = br0 + e;
+    return BrL{d->br_g[b], d->br_bs[b], d->br_hb[b], d->br_lf[b], d->br_lt[b]};
   }
-  if (bus == am.slack_local) dth = 0.0;
-  return bus;
-}
+
+  // partials of the injection at bus u with respect to the bus across branch e
+  __device__ int inj_nbr(int u, int e, bool q, double& dt, double& dv) const {
+    const BrL B = branch(e);
+    const bool from = (B.lf == u);
+    const int o = from ? B.lt : B.lf;
+    const double2 c = cs[e];
+    double h, a1, a2;
+    flow_end(B.g, B.bs, B.hb, xs[u].y, xs[o].y, c.x, from ? c.y : -c.y, q, h, a1, a2, dt, dv);
+    return o;
+  }
+
+  // Value of the row rec = {type, loc, meas} and its partials with respect to
+  // the buses picked by roles rp and rq.
+  __device__ void eval2(int4 rec, int rp, int rq, double& h, double& pt, double& pv, double& qt,
+                        double& qv) const {
+    const int ty = rec.x, loc = rec.y;
+    int bp, bq;
+    if (ty == VM) {
+      h = xs[loc].y;
+      pt = qt = 0.0;
+      pv = qv = 1.0;
+      bp = bq = loc;
+    } else if (ty <= QINJ) {
+      const int q = (ty == QINJ) ? 1 : 0;
+      const double* a = agg + 6 * loc;
+      h = a[q];
+      if (rp == ROLE_SELF) { pt = a[2 + 2 * q]; pv = a[3 + 2 * q]; bp = loc; }
+      else bp = inj_nbr(loc, rp, q, pt, pv);
+      if (rq == ROLE_SELF) { qt = a[2 + 2 * q]; qv = a[3 + 2 * q]; bq = loc; }
+      else if (rq == rp) { qt = pt; qv = pv; bq = bp; }
+      else bq = inj_nbr(loc, rq, q, qt, qv);
+    } else {
+      const BrL B = branch(loc);
+      const bool to = (ty >= PT);
+      const bool isq = (ty == QF || ty == QT);
+      const int a = to ? B.lt : B.lf, o = to ? B.lf : B.lt;
+      const double2 c = cs[loc];
+      double ta, tv, to_, vo;
+      flow_end(B.g, B.bs, B.hb, xs[a].y, xs[o].y, c.x, to ? -c.y : c.y, isq, h, ta, tv, to_, vo);
+      if (rp == ROLE_SELF) { pt = ta; pv = tv; bp = a; } else { pt = to_; pv = vo; bp = o; }
+      if (rq == ROLE_SELF) { qt = ta; qv = tv; bq = a; } else { qt = to_; qv = vo; bq = o; }
+    }
+    if (bp == slack_local) pt = 0.0;
+    if (bq == slack_local) qt = 0.0;
+  }
+};
 
 __device__ inline double block_sum(double v, double* red) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -163,13 +176,14 @@ __device__ inline bool chol2(double a00, double a10, double a11, double& l00, do
 // ---------------------------------------------------------------------------
 // Stage 1: fused evaluation and accumulation (one workgroup per area x
 // snapshot).  LDS holds the area's local states, cos/sin of every local
-// branch's angle difference, and every own bus's injection value and
-// self-partials (sums over incident branch ends: Kirchhoff's current law).
-// G slots are visited in packed-storage order and each sums its precomputed,
-// fixed-order contribution list, so the writes are contiguous and the sum is
-// deterministic.
+// branch's angle difference, every own bus's injection value and
+// self-partials (sums over incident branch ends: Kirchhoff's current law) and,
+// when it fits, the branch records.  G slots are visited in packed-storage
+// order and each sums its precomputed, fixed-order contribution list, so the
+// writes are contiguous and the sum is deterministic.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_assemble(Dev d, int a0, int na, int s0, int ns, int mode) {
+template <bool BR_LDS>
+__global__ void __launch_bounds__(512) k_assemble(Dev d, int a0, int na, int s0, int ns, int mode) {
   int ai, s;
   area_snap_of_block(blockIdx.x, na, ns, ai, s);
   s += s0;
@@ -182,15 +196,22 @@ __global__ void __launch_bounds__(256) k_assemble(Dev d, int a0, int na, int s0,
   double2* xs = lds2;
   double2* cs = xs + am.nn;
   double* agg = reinterpret_cast<double*>(cs + am.nbr);
+  BrL* brl = reinterpret_cast<BrL*>(agg + 6 * am.nn);
   const double2* xsnap = d.x + (int64_t)s * d.n_bus;
   const int tid = threadIdx.x, nt = blockDim.x;
 
   for (int v = tid; v < am.nn; v += nt) xs[v] = xsnap[d.gbus[sm.gbus + v]];
+  if (BR_LDS)
+    for (int e = tid; e < am.nbr; e += nt) {
+      const int b = am.br + e;
+      brl[e] = BrL{d.br_g[b], d.br_bs[b], d.br_hb[b], d.br_lf[b], d.br_lt[b]};
+    }
   __syncthreads();
+  const Asm<BR_LDS> X{&d, am.br, am.slack_local, xs, cs, agg, brl};
   for (int e = tid; e < am.nbr; e += nt) {
-    const int b = am.br + e;
+    const BrL B = X.branch(e);
     double sn, c;
-    sincos(xs[d.br_lf[b]].x - xs[d.br_lt[b]].x, &sn, &c);
+    sincos(xs[B.lf].x - xs[B.lt].x, &sn, &c);
     cs[e] = make_double2(c, sn);
   }
   __syncthreads();
@@ -200,14 +221,14 @@ __global__ void __launch_bounds__(256) k_assemble(Dev d, int a0, int na, int s0,
     for (int q = p0; q < p1; ++q) {
       const int code = d.inc_end[q];
       const int le = code >> 1, side = code & 1;
-      const int e = am.br + le;
-      const int o = side ? d.br_lf[e] : d.br_lt[e];
+      const BrL B = X.branch(le);
+      const int o = side ? B.lf : B.lt;
       const double2 c = cs[le];
       const double sn = side ? -c.y : c.y;
       double h, ta, tv, to_, vo;
-      flow_end(d.br_g[e], d.br_bs[e], d.br_hb[e], xs[v].y, xs[o].y, c.x, sn, false, h, ta, tv, to_, vo);
+      flow_end(B.g, B.bs, B.hb, xs[v].y, xs[o].y, c.x, sn, false, h, ta, tv, to_, vo);
       P += h; dPt += ta; dPv += tv;
-      flow_end(d.br_g[e], d.br_bs[e], d.br_hb[e], xs[v].y, xs[o].y, c.x, sn, true, h, ta, tv, to_, vo);
+      flow_end(B.g, B.bs, B.hb, xs[v].y, xs[o].y, c.x, sn, true, h, ta, tv, to_, vo);
       Q += h; dQt += ta; dQv += tv;
     }
     double* a = agg + 6 * v;
@@ -218,20 +239,21 @@ __global__ void __launch_bounds__(256) k_assemble(Dev d, int a0, int na, int s0,
   const double* zs = d.z + (int64_t)s * d.n_meas;
   if (mode == MODE_EVAL_H) {
     for (int r = tid; r < am.nrow; r += nt) {
-      double h, a1, a2;
-      row_eval(d, am, r, ROLE_SELF, xs, cs, agg, h, a1, a2);
-      d.hout[(int64_t)s * d.n_meas + d.row_meas[am.row + r]] = h;
+      const int4 rec = d.rowrec[am.row + r];
+      double h, a1, a2, a3, a4;
+      X.eval2(rec, ROLE_SELF, ROLE_SELF, h, a1, a2, a3, a4);
+      d.hout[(int64_t)s * d.n_meas + rec.z] = h;
     }
     return;
   }
   // objective J = sum w r^2 over the area's rows (Eq. 2)
   double jl = 0.0;
   for (int r = tid; r < am.nrow; r += nt) {
-    const int m = d.row_meas[am.row + r];
-    double h, a1, a2;
-    row_eval(d, am, r, ROLE_SELF, xs, cs, agg, h, a1, a2);
-    const double res = zs[m] - h;
-    jl += d.w[m] * res * res;
+    const int4 rec = d.rowrec[am.row + r];
+    double h, a1, a2, a3, a4;
+    X.eval2(rec, ROLE_SELF, ROLE_SELF, h, a1, a2, a3, a4);
+    const double res = zs[rec.z] - h;
+    jl += d.w[rec.z] * res * res;
   }
   const double jt = block_sum(jl, red);
   if (tid == 0) d.jpart[(int64_t)s * d.n_area + k] = jt;
@@ -244,11 +266,10 @@ __global__ void __launch_bounds__(256) k_assemble(Dev d, int a0, int na, int s0,
     double c00 = 0, c10 = 0, c01 = 0, c11 = 0;
     for (int c = sl.z; c < sl.w; ++c) {
       const int2 cc = d.scon[c];
-      const int r = cc.x;
-      const double wr = d.w[d.row_meas[am.row + r]];
+      const int4 rec = d.rowrec[am.row + cc.x];
+      const double wr = d.w[rec.z];
       double h, pt, pv, qt, qv;
-      row_eval(d, am, r, cc.y & 0xFFFF, xs, cs, agg, h, pt, pv);
-      row_eval(d, am, r, (cc.y >> 16) & 0xFFFF, xs, cs, agg, h, qt, qv);
+      X.eval2(rec, cc.y & 0xFFFF, (cc.y >> 16) & 0xFFFF, h, pt, pv, qt, qv);
       pt *= wr;
       pv *= wr;
       c00 += pt * qt;
@@ -273,10 +294,10 @@ __global__ void __launch_bounds__(256) k_assemble(Dev d, int a0, int na, int s0,
     double b0 = 0, b1 = 0;
     for (int c = rs.x; c < rs.y; ++c) {
       const int2 cc = d.rcon[c];
-      const int m = d.row_meas[am.row + cc.x];
-      double h, pt, pv;
-      row_eval(d, am, cc.x, cc.y, xs, cs, agg, h, pt, pv);
-      const double wres = d.w[m] * (zs[m] - h);
+      const int4 rec = d.rowrec[am.row + cc.x];
+      double h, pt, pv, qt, qv;
+      X.eval2(rec, cc.y, cc.y, h, pt, pv, qt, qv);
+      const double wres = d.w[rec.z] * (zs[rec.z] - h);
       b0 += pt * wres;
       b1 += pv * wres;
     }
@@ -296,7 +317,8 @@ __global__ void __launch_bounds__(256) k_assemble(Dev d, int a0, int na, int s0,
 // sum_j L_ij y_j.  After the last level the tail holds the Schur complement
 // S_b = G_bb - G_bi G_ii^-1 G_ib and the tail rhs holds bhat_b (Eq. 9-10).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_eliminate(Dev d, int sys0, int nsys, int s0, int ns) {
+template <int NT>
+__global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int s0, int ns) {
   int si, s;
   area_snap_of_block(blockIdx.x, nsys, ns, si, s);
   s += s0;
@@ -305,11 +327,11 @@ __global__ void __launch_bounds__(256) k_eliminate(Dev d, int sys0, int nsys, in
   const SysMeta sm = d.sys[k];
   double* vals = d.vals + (int64_t)s * d.vstride + sm.val_off;
   double* rhs = d.rhs + (int64_t)s * d.rstride + sm.rhs_off;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x;
   bool bad = false;
   for (int lev = 0; lev < sm.nlev; ++lev) {
     const int c0 = d.cd_ptr[sm.cd_ptr + lev], c1 = d.cd_ptr[sm.cd_ptr + lev + 1];
-    for (int it = c0 + tid; it < c1; it += nt) {
+    for (int it = c0 + tid; it < c1; it += NT) {
       const int4 c = d.cd_items[it];
       const double* D = vals + c.x;
       double l00, l10, l11;
@@ -329,18 +351,20 @@ __global__ void __launch_bounds__(256) k_eliminate(Dev d, int sys0, int nsys, in
     }
     __syncthreads();
     const int u0 = d.up_ptr[sm.up_ptr + lev], u1 = d.up_ptr[sm.up_ptr + lev + 1];
-    for (int it = u0 + tid; it < u1; it += nt) {
+    for (int it = u0 + tid; it < u1; it += NT) {
       const int4 t = d.up_tgt[it];
       double a00 = 0, a10 = 0, a01 = 0, a11 = 0;
       bool sym = false;
       for (int c = t.z; c < t.w; ++c) {
         const int2 u = d.up_con[c];
-        const double* L = vals + u.x;
-        const double* P = vals + u.y;
-        a00 += L[0] * P[0] + L[2] * P[2];
-        a10 += L[1] * P[0] + L[3] * P[2];
-        a01 += L[0] * P[1] + L[2] * P[3];
-        a11 += L[1] * P[1] + L[3] * P[3];
+        const double2 L0 = *reinterpret_cast<const double2*>(vals + u.x);
+        const double2 L1 = *reinterpret_cast<const double2*>(vals + u.x + 2);
+        const double2 P0 = *reinterpret_cast<const double2*>(vals + u.y);
+        const double2 P1 = *reinterpret_cast<const double2*>(vals + u.y + 2);
+        a00 += L0.x * P0.x + L1.x * P1.x;
+        a10 += L0.y * P0.x + L1.y * P1.x;
+        a01 += L0.x * P0.y + L1.x * P1.y;
+        a11 += L0.y * P0.y + L1.y * P1.y;
         sym = (u.x == u.y);
       }
       if (sym) a01 = a10;
@@ -351,7 +375,7 @@ __global__ void __launch_bounds__(256) k_eliminate(Dev d, int sys0, int nsys, in
       C[t.y + 1] -= a11;
     }
     const int r0 = d.rb_ptr[sm.rb_ptr + lev], r1 = d.rb_ptr[sm.rb_ptr + lev + 1];
-    for (int it = r0 + tid; it < r1; it += nt) {
+    for (int it = r0 + tid; it < r1; it += NT) {
       const int4 t = d.rb_tgt[it];
       double b0 = 0, b1 = 0;
       for (int c = t.y; c < t.z; ++c) {
@@ -420,14 +444,19 @@ __global__ void __launch_bounds__(256) k_gamma_gather(Dev d, int s0, int nslot) 
 // ---------------------------------------------------------------------------
 // Stage 3b: dense Cholesky and solve of the boundary system's trailing block
 // (the whole S_Gamma in dense mode).  One workgroup per snapshot, blocked
-// right-looking with 16-wide panels; the symmetric trailing update
-// A_ij -= L_ik L_jk^T runs on v_mfma_f64_16x16x4f64.  The block is
-// column-major with leading dimension n (a multiple of 16); rows and columns
-// past the live size are set to the identity first.
+// right-looking with 16-wide panels: the 16x16 diagonal block is factored in
+// registers by one wave (one row per lane, shuffles), the panel below by
+// row-parallel triangular solves, and the symmetric trailing update
+// A_ij -= L_ik L_jk^T runs on v_mfma_f64_16x16x4f64, one 16x16 tile per wave.
+// The forward solve rides along; the back solve runs block by block from the
+// bottom.  The block is column-major with leading dimension n (a multiple of
+// 16); rows and columns past the live size are set to the identity first.
 // ---------------------------------------------------------------------------
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(512) k_dense_chol(Dev d, int s0) {
+constexpr int DENSE_NT = 512;
+
+__global__ void __launch_bounds__(DENSE_NT) k_dense_chol(Dev d, int s0) {
   const int s = s0 + blockIdx.x;
   if (!d.active[s]) return;
   const SysMeta g = d.sys[d.n_area];
@@ -438,7 +467,7 @@ __global__ void __launch_bounds__(512) k_dense_chol(Dev d, int s0) {
   double* b = d.rhs + (int64_t)s * d.rstride + g.rhs_off + 2 * g.ne;
   extern __shared__ double bl[];  // [n] rhs, then solution
   __shared__ double Lk[16 * 17];
-  __shared__ double part[32 * 16];
+  __shared__ double part[16 * 16];
   __shared__ int bad;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
@@ -451,35 +480,40 @@ __global__ void __launch_bounds__(512) k_dense_chol(Dev d, int s0) {
   const int nb = n / 16;
   for (int k = 0; k < nb; ++k) {
     const int c0 = 16 * k;
-    if (tid < 256) {
-      const int r = tid >> 4, c = tid & 15;
-      if (r >= c) Lk[r * 17 + c] = A[(int64_t)(c0 + c) * n + c0 + r];
-    }
-    __syncthreads();
-    for (int c = 0; c < 16; ++c) {
-      if (tid == 0) {
-        const double p = Lk[c * 17 + c];
-        if (!(p > 0.0)) { bad = 1; Lk[c * 17 + c] = 1.0; }
-        else Lk[c * 17 + c] = sqrt(p);
+    if (wv == 0) {
+      // lane r (mod 16) holds row r of the diagonal block
+      const int r = lane & 15;
+      double a[16];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) a[m] = (m <= r) ? A[(int64_t)(c0 + m) * n + c0 + r] : 0.0;
+      double y = bl[c0 + r];
+      bool badl = false;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        const double piv = __shfl(a[c], c, 64);
+        double dd;
+        if (!(piv > 0.0)) { badl = true; dd = 1.0; }
+        else dd = sqrt(piv);
+        if (r == c) a[c] = dd;
+        else if (r > c) a[c] /= dd;
+        if (r == c) y /= dd;
+        const double yc = __shfl(y, c, 64);
+        if (r > c) y -= a[c] * yc;
+#pragma unroll
+        for (int m = c + 1; m < 16; ++m) {
+          const double lmc = __shfl(a[c], m, 64);
+          if (r >= m) a[m] -= a[c] * lmc;
+        }
       }
-      __syncthreads();
-      if (tid > c && tid < 16) Lk[tid * 17 + c] /= Lk[c * 17 + c];
-      __syncthreads();
-      if (tid < 256) {
-        const int r = tid >> 4, m = tid & 15;
-        if (m > c && r >= m) Lk[r * 17 + m] -= Lk[r * 17 + c] * Lk[m * 17 + c];
-      }
-      __syncthreads();
-    }
-    if (tid < 256) {
-      const int r = tid >> 4, c = tid & 15;
-      if (r >= c) A[(int64_t)(c0 + c) * n + c0 + r] = Lk[r * 17 + c];
-    }
-    if (tid == 0) {
-      for (int r = 0; r < 16; ++r) {
-        double y = bl[c0 + r];
-        for (int m = 0; m < r; ++m) y -= Lk[r * 17 + m] * bl[c0 + m];
-        bl[c0 + r] = y / Lk[r * 17 + r];
+      if (lane < 16) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m)
+          if (m <= r) {
+            Lk[r * 17 + m] = a[m];
+            A[(int64_t)(c0 + m) * n + c0 + r] = a[m];
+          }
+        bl[c0 + r] = y;
+        if (badl && lane == 0) bad = 1;
       }
     }
     __syncthreads();
@@ -487,8 +521,10 @@ __global__ void __launch_bounds__(512) k_dense_chol(Dev d, int s0) {
     for (int row = c0 + 16 + tid; row < n; row += nt) {
       double x[16];
       double acc = 0.0;
+#pragma unroll
       for (int c = 0; c < 16; ++c) {
         double a = A[(int64_t)(c0 + c) * n + row];
+#pragma unroll
         for (int m = 0; m < c; ++m) a -= x[m] * Lk[c * 17 + m];
         x[c] = a / Lk[c * 17 + c];
         A[(int64_t)(c0 + c) * n + row] = x[c];
@@ -523,21 +559,28 @@ __global__ void __launch_bounds__(512) k_dense_chol(Dev d, int s0) {
   // back substitution L^T x = y, block by block from the bottom
   for (int k = nb - 1; k >= 0; --k) {
     const int c0 = 16 * k;
-    {
-      const int c = tid & 15, pp = tid >> 4, np = nt >> 4;
+    if (tid < 256) {
+      const int c = tid & 15, pp = tid >> 4;
       double acc = 0.0;
-      for (int r = c0 + 16 + pp; r < n; r += np) acc += A[(int64_t)(c0 + c) * n + r] * bl[r];
-      part[pp * 16 + c] = acc;  // pp < 32 for blockDim <= 512
+      for (int r = c0 + 16 + pp; r < n; r += 16) acc += A[(int64_t)(c0 + c) * n + r] * bl[r];
+      part[pp * 16 + c] = acc;
     }
     __syncthreads();
-    if (tid == 0) {
-      const int np = nt >> 4;
+    if (wv == 0) {
+      // lane r (mod 16) holds t_r and column r of L_kk
+      const int r = lane & 15;
+      double col[16];
+#pragma unroll
+      for (int mm = 0; mm < 16; ++mm) col[mm] = (mm >= r) ? A[(int64_t)(c0 + r) * n + c0 + mm] : 0.0;
+      double t = bl[c0 + r];
+      for (int pp = 0; pp < 16; ++pp) t -= part[pp * 16 + r];
+#pragma unroll
       for (int c = 15; c >= 0; --c) {
-        double t = bl[c0 + c];
-        for (int p = 0; p < np; ++p) t -= part[p * 16 + c];
-        for (int mm = c + 1; mm < 16; ++mm) t -= A[(int64_t)(c0 + c) * n + c0 + mm] * bl[c0 + mm];
-        bl[c0 + c] = t / A[(int64_t)(c0 + c) * n + c0 + c];
+        if (r == c) t /= col[c];
+        const double xc = __shfl(t, c, 64);
+        if (r < c) t -= col[c] * xc;
       }
+      if (lane < 16) bl[c0 + r] = t;
     }
     __syncthreads();
   }
@@ -549,9 +592,12 @@ __global__ void __launch_bounds__(512) k_dense_chol(Dev d, int s0) {
 // Stage 4a: back substitution.  For an area, first copy dx of its local
 // boundary buses from the boundary solution (dx_b^k = E_k dx_Gamma); then,
 // level by level from the top, dx_j = L_jj^-T (y_j - sum_i L_ij^T dx_i),
-// which is Eq. 8 through the cached factor.
+// which is Eq. 8 through the cached factor.  Each column's sum is split over
+// a group of 8 lanes and combined by a fixed shuffle tree.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_backsolve(Dev d, int sys0, int nsys, int s0, int ns) {
+template <int NT>
+__global__ void __launch_bounds__(NT) k_backsolve(Dev d, int sys0, int nsys, int s0, int ns) {
+  constexpr int G = 8;
   int si, s;
   area_snap_of_block(blockIdx.x, nsys, ns, si, s);
   s += s0;
@@ -562,34 +608,44 @@ __global__ void __launch_bounds__(256) k_backsolve(Dev d, int sys0, int nsys, in
   const double* vals = d.vals + (int64_t)s * d.vstride + sm.val_off;
   double* rb = d.rhs + (int64_t)s * d.rstride;
   double* rhs = rb + sm.rhs_off;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x;
   if (is_area) {
     const AreaMeta am = d.area[k];
-    for (int t = tid; t < sm.nt; t += nt) {
+    for (int t = tid; t < sm.nt; t += NT) {
       const int src = d.tail_src[am.tail_src + t];
       rhs[2 * (sm.ne + t)] = rb[src];
       rhs[2 * (sm.ne + t) + 1] = rb[src + 1];
     }
   }
   __syncthreads();
+  const int grp = tid / G, gl = tid % G;
   for (int lev = sm.nlev - 1; lev >= 0; --lev) {
     const int b0 = d.bs_ptr[sm.bs_ptr + lev], b1 = d.bs_ptr[sm.bs_ptr + lev + 1];
-    for (int it = b0 + tid; it < b1; it += nt) {
+    for (int it = b0 + grp; it < b1; it += NT / G) {
       const int4 b = d.bs_items[it];
-      double t0 = rhs[b.y], t1 = rhs[b.y + 1];
-      for (int c = b.z; c < b.w; ++c) {
+      double t0 = 0.0, t1 = 0.0;
+      for (int c = b.z + gl; c < b.w; c += G) {
         const int2 u = d.bs_con[c];
         const double* L = vals + u.x;
         const double x0 = rhs[u.y], x1 = rhs[u.y + 1];
-        t0 -= L[0] * x0 + L[1] * x1;
-        t1 -= L[2] * x0 + L[3] * x1;
+        t0 += L[0] * x0 + L[1] * x1;
+        t1 += L[2] * x0 + L[3] * x1;
       }
-      const double* D = vals + b.x;
-      double l00, l10, l11;
-      if (!chol2(D[0], D[1], D[3], l00, l10, l11)) { l00 = l11 = 1.0; l10 = 0.0; }
-      const double x1 = t1 / l11;
-      rhs[b.y + 1] = x1;
-      rhs[b.y] = (t0 - l10 * x1) / l00;
+#pragma unroll
+      for (int off = G / 2; off > 0; off >>= 1) {
+        t0 += __shfl_xor(t0, off, G);
+        t1 += __shfl_xor(t1, off, G);
+      }
+      if (gl == 0) {
+        t0 = rhs[b.y] - t0;
+        t1 = rhs[b.y + 1] - t1;
+        const double* D = vals + b.x;
+        double l00, l10, l11;
+        if (!chol2(D[0], D[1], D[3], l00, l10, l11)) { l00 = l11 = 1.0; l10 = 0.0; }
+        const double x1 = t1 / l11;
+        rhs[b.y + 1] = x1;
+        rhs[b.y] = (t0 - l10 * x1) / l00;
+      }
     }
     __syncthreads();
   }
@@ -670,25 +726,32 @@ __global__ void k_reset_flags(Dev d) {
   if (i < d.n_snap * (d.n_area + 1)) d.status[i] = 0;
 }
 
-}  // namespace mase
-
 // ---------------------------------------------------------------------------
 // Launch wrappers
 // ---------------------------------------------------------------------------
-#include "launch.hpp"
+constexpr int AREA_NT = 256;   // level kernels over areas: many workgroups
+constexpr int GAMMA_NT = 1024; // level kernels over the one boundary system
 
-namespace mase {
+size_t assemble_lds_bytes(int nn, int nbr, bool br_lds) {
+  return 16 * (size_t)nn + 16 * (size_t)nbr + 48 * (size_t)nn + (br_lds ? sizeof(BrL) * (size_t)nbr : 0);
+}
 
 hipError_t launch_assemble(const Dev& d, int a0, int na, int s0, int ns, int mode, size_t lds,
-                           hipStream_t st) {
+                           bool br_lds, hipStream_t st) {
   if (na <= 0 || ns <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_assemble, dim3(na * ns), dim3(256), lds, st, d, a0, na, s0, ns, mode);
+  if (br_lds)
+    hipLaunchKernelGGL(k_assemble<true>, dim3(na * ns), dim3(512), lds, st, d, a0, na, s0, ns, mode);
+  else
+    hipLaunchKernelGGL(k_assemble<false>, dim3(na * ns), dim3(512), lds, st, d, a0, na, s0, ns, mode);
   return hipGetLastError();
 }
 
 hipError_t launch_eliminate(const Dev& d, int sys0, int nsys, int s0, int ns, hipStream_t st) {
   if (nsys <= 0 || ns <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_eliminate, dim3(nsys * ns), dim3(256), 0, st, d, sys0, nsys, s0, ns);
+  if (sys0 >= d.n_area)
+    hipLaunchKernelGGL(k_eliminate<GAMMA_NT>, dim3(nsys * ns), dim3(GAMMA_NT), 0, st, d, sys0, nsys, s0, ns);
+  else
+    hipLaunchKernelGGL(k_eliminate<AREA_NT>, dim3(nsys * ns), dim3(AREA_NT), 0, st, d, sys0, nsys, s0, ns);
   return hipGetLastError();
 }
 
@@ -701,13 +764,16 @@ hipError_t launch_gamma_gather(const Dev& d, int s0, int ns, int nslot, int nn, 
 
 hipError_t launch_dense_chol(const Dev& d, int s0, int ns, int ld, hipStream_t st) {
   if (ld <= 0 || ns <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_dense_chol, dim3(ns), dim3(512), sizeof(double) * (size_t)ld, st, d, s0);
+  hipLaunchKernelGGL(k_dense_chol, dim3(ns), dim3(DENSE_NT), sizeof(double) * (size_t)ld, st, d, s0);
   return hipGetLastError();
 }
 
 hipError_t launch_backsolve(const Dev& d, int sys0, int nsys, int s0, int ns, hipStream_t st) {
   if (nsys <= 0 || ns <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_backsolve, dim3(nsys * ns), dim3(256), 0, st, d, sys0, nsys, s0, ns);
+  if (sys0 >= d.n_area)
+    hipLaunchKernelGGL(k_backsolve<GAMMA_NT>, dim3(nsys * ns), dim3(GAMMA_NT), 0, st, d, sys0, nsys, s0, ns);
+  else
+    hipLaunchKernelGGL(k_backsolve<AREA_NT>, dim3(nsys * ns), dim3(AREA_NT), 0, st, d, sys0, nsys, s0, ns);
   return hipGetLastError();
 }
 
@@ -736,8 +802,11 @@ hipError_t launch_reset_flags(const Dev& d, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t allow_assemble_lds(size_t bytes) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_assemble),
+hipError_t allow_assemble_lds(size_t bytes, bool br_lds) {
+  if (br_lds)
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_assemble<true>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_assemble<false>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 

@@ -7,8 +7,11 @@
 
 namespace mase {
 
+// LDS bytes of k_assemble for an area with nn local buses and nbr branches;
+// br_lds: branch records staged in LDS too.
+size_t assemble_lds_bytes(int nn, int nbr, bool br_lds);
 hipError_t launch_assemble(const Dev& d, int a0, int na, int s0, int ns, int mode, size_t lds,
-                           hipStream_t st);
+                           bool br_lds, hipStream_t st);
 hipError_t launch_eliminate(const Dev& d, int sys0, int nsys, int s0, int ns, hipStream_t st);
 hipError_t launch_gamma_gather(const Dev& d, int s0, int ns, int nslot, int nn, hipStream_t st);
 hipError_t launch_dense_chol(const Dev& d, int s0, int ns, int ld, hipStream_t st);
@@ -18,6 +21,6 @@ hipError_t launch_pack_state(const Dev& d, const double* vm, const double* va, d
                              hipStream_t st);
 hipError_t launch_unpack_state(const Dev& d, double* vm, double* va, hipStream_t st);
 hipError_t launch_reset_flags(const Dev& d, hipStream_t st);
-hipError_t allow_assemble_lds(size_t bytes);
+hipError_t allow_assemble_lds(size_t bytes, bool br_lds);
 
 }  // namespace mase

@@ -493,15 +493,42 @@ std::string build_plan(const Input& in, Plan& p) {
       std::vector<int> order;
       std::vector<std::vector<int>> nbrs_at;
       min_degree(nn, nn, adj, order, nbrs_at);
-      relabel(g, gold, nn, order, nbrs_at);
-      // dense trailing block: the root supernode (suffix whose columns are full)
-      int tail = 0;
-      for (int j = nn - 1; j >= 0; --j) {
-        if ((int)g.strct[j].size() == nn - 1 - j) tail++;
-        else break;
+      // Elimination-tree levels of the full minimum-degree elimination.  The
+      // top levels that hold a single column each form a chain (it includes
+      // the root supernode): those columns are eliminated one after another
+      // anyway, so they go to the dense trailing block, factored with dense
+      // kernels.  The chain is closed under ancestors, so moving it to the
+      // end keeps a valid elimination order with the same fill.
+      std::vector<int> pos(nn);
+      for (int q = 0; q < nn; ++q) pos[order[q]] = q;
+      std::vector<int> lev(nn, 0);
+      for (int q = 0; q < nn; ++q) {
+        int par = nn;
+        for (int a : nbrs_at[order[q]]) par = std::min(par, pos[a]);
+        if (par < nn) lev[par] = std::max(lev[par], lev[q] + 1);
       }
-      g.ne = nn - tail;
-      for (int j = g.ne; j < nn; ++j) g.strct[j].clear();
+      int nlev = 0;
+      for (int q = 0; q < nn; ++q) nlev = std::max(nlev, lev[q] + 1);
+      std::vector<int> cnt(nlev, 0);
+      for (int q = 0; q < nn; ++q) cnt[lev[q]]++;
+      int cut = nlev;
+      while (cut > 0 && cnt[cut - 1] == 1) --cut;
+      std::vector<int> elim, tailn;
+      for (int q = 0; q < nn; ++q) (lev[q] >= cut ? tailn : elim).push_back(order[q]);
+      std::vector<int> newof(nn, -1);
+      int c2 = 0;
+      for (int v : elim) newof[v] = c2++;
+      for (int v : tailn) newof[v] = c2++;
+      g.nn = nn;
+      g.ne = (int)elim.size();
+      g.gbus.assign(nn, -1);
+      for (int v = 0; v < nn; ++v) g.gbus[newof[v]] = gold[v];
+      g.strct.assign(nn, {});
+      for (int v : elim) {
+        auto& st = g.strct[newof[v]];
+        for (int a : nbrs_at[v]) st.push_back(newof[a]);
+        std::sort(st.begin(), st.end());
+      }
     } else {
       g.nn = nn;
       g.gbus = gold;
