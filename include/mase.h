@@ -200,6 +200,70 @@ int mase_objective(mase_ctx* ctx, double* J);
  */
 int mase_eval_h_dev(mase_ctx* ctx, const double* vm_dev, const double* va_dev, double* h_dev);
 
+/* ---- learned warm start (an extension of the paper's method) ----
+ *
+ * One MLP per area maps the area's measurements, normalised as
+ * (z - z_mean) / sigma, through two ReLU hidden layers of `hidden` units to
+ * a starting (|V|, theta) for each of the area's own buses (outputs
+ * standardised by y_mean / y_std).  Weights are bfloat16 copies of FP32
+ * master weights; products run on bf16 MFMA with FP32 accumulation; Adam
+ * updates the masters.  Gauss-Newton in FP64 remains the judge: a prediction
+ * is used for a snapshot only if its objective J (Eq. 2) is not worse than
+ * that of the flat start.
+ *
+ * Parameter vector (FP32, host order for set/get): for each area in order,
+ * W1 [m_k x hidden], b1 [hidden], W2 [hidden x hidden], b2 [hidden],
+ * W3 [hidden x o_k], b3 [o_k], row-major ("inputs x outputs").  The inputs of
+ * area k are its measurements and its outputs are the global variable ids of
+ * its own buses (2*bus theta, 2*bus+1 |V|; the slack angle is an output
+ * whose prediction is replaced by 0), both in the order mase_mlp_io_map
+ * returns.
+ */
+typedef struct mase_mlp mase_mlp;
+
+/* Allocate the per-area networks of `ctx` (device), zero-initialised; up to
+ * max_batch samples per training step (and at least n_snap). */
+int mase_mlp_create(mase_ctx* ctx, int32_t hidden, int32_t max_batch, mase_mlp** out);
+void mase_mlp_destroy(mase_mlp* mlp);
+
+/* Sizes: area >= 0 gives that area's input and output counts, area = -1 the
+ * totals; n_param is the length of the parameter vector. */
+int mase_mlp_info(const mase_mlp* mlp, int32_t area, int32_t* n_in, int32_t* n_out, int64_t* n_param);
+
+/* Area k's input measurement ids [n_in] and output variable ids [n_out]. */
+int mase_mlp_io_map(const mase_mlp* mlp, int32_t area, int32_t* in_meas, int32_t* out_var);
+
+/* Parameters (host FP32, n_param); set also clears the Adam moments. */
+int mase_mlp_set_params(mase_mlp* mlp, const float* params);
+int mase_mlp_get_params(mase_mlp* mlp, float* params);
+
+/* Normalisation: z_mean [n_meas]; y_mean, y_std [2 n_bus] by variable id. */
+int mase_mlp_set_norm(mase_mlp* mlp, const double* z_mean, const double* y_mean, const double* y_std);
+
+/* Mean squared error of the standardised outputs over a batch of
+ * measurements z_dev [batch][n_meas] against states vm_dev, va_dev
+ * [batch][n_bus] (device), and its gradient (host FP32 [n_param], may be
+ * NULL).  No update. */
+int mase_mlp_loss_grad(mase_mlp* mlp, const double* z_dev, const double* vm_dev, const double* va_dev,
+                       int32_t batch, double* loss, float* grad);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the same loss; loss
+ * (host, may be NULL) receives the loss before the step. */
+int mase_mlp_train_step(mase_mlp* mlp, const double* z_dev, const double* vm_dev, const double* va_dev,
+                        int32_t batch, float lr, double* loss);
+
+/* Predicted states vm_dev, va_dev [batch][n_bus] (device) for z_dev. */
+int mase_mlp_predict_dev(mase_mlp* mlp, const double* z_dev, int32_t batch, double* vm_dev, double* va_dev);
+
+/*
+ * Warm start for the context's current measurements: predict every
+ * snapshot's state, evaluate J at the prediction and at flat start, keep the
+ * prediction where J(pred) <= J(flat) and flat start elsewhere; accepted
+ * [n_snap] (host, may be NULL) receives 1 where the prediction was kept.
+ * Marks every snapshot active, as mase_set_state does.
+ */
+int mase_warm_start(mase_ctx* ctx, mase_mlp* mlp, int32_t* accepted);
+
 /* ---- per-stage timing ---- */
 
 /* Kernel stages of one iteration, in launch order. */

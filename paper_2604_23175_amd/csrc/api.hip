@@ -15,6 +15,7 @@
 #include "launch.hpp"
 #include "mase.h"
 #include "plan.hpp"
+#include "ctx.hpp"
 
 using namespace mase;
 
@@ -36,41 +37,7 @@ int fail(int code, const std::string& msg) {
 
 }  // namespace
 
-struct mase_ctx {
-  Plan plan;
-  mase_options opt{};
-  bool host_only = false;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  std::vector<hipStream_t> astreams;
-  std::vector<hipEvent_t> aevents;
-  hipEvent_t ev_main = nullptr;
-  Dev d{};
-  std::vector<void*> dallocs;
-  double2* xscratch = nullptr;
-  double* stage_vm = nullptr;
-  double* stage_va = nullptr;
-  double* dtol = nullptr;
-  size_t lds_asm = 0;
-  bool br_lds = false;
-  int nslot_g = 0;
-  bool have_z = false;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  int32_t* h_active = nullptr;
-  int32_t* h_status = nullptr;
-  int32_t* h_iters = nullptr;
-  double* h_maxdx = nullptr;
-  double* h_tol = nullptr;
-  std::vector<SysMeta> hsys;
-  // per-stage timing
-  bool prof = false;
-  hipEvent_t pev[2 * MASE_N_STAGE] = {};
-  bool pused[MASE_N_STAGE] = {};
-  double pms[MASE_N_STAGE] = {};
-  int64_t plaunch[MASE_N_STAGE] = {};
-  int64_t punits[MASE_N_STAGE] = {};
-};
+
 
 namespace {
 
@@ -430,6 +397,21 @@ void unpack_blocks(const Plan& p, int k, const std::vector<double>& vals, const 
 }
 
 }  // namespace
+
+namespace mase {
+
+int set_error(int code, const std::string& msg) { return fail(code, msg); }
+
+int objective_at(mase_ctx* c, double2* x, double* jpart) {
+  Dev d = c->d;
+  d.x = x;
+  d.jpart = jpart;
+  HIPTRY(launch_assemble(d, 0, c->plan.n_area, 0, c->plan.n_snap, MODE_OBJECTIVE, c->lds_asm, c->br_lds,
+                         c->stream));
+  return 0;
+}
+
+}  // namespace mase
 
 extern "C" {
 

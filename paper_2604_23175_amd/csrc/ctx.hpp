@@ -1,0 +1,55 @@
+// Context of the C ABI (mase_ctx), shared by api.hip and mlp.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "dev.hpp"
+#include "mase.h"
+#include "plan.hpp"
+
+struct mase_ctx {
+  mase::Plan plan;
+  mase_options opt{};
+  bool host_only = false;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<hipStream_t> astreams;
+  std::vector<hipEvent_t> aevents;
+  hipEvent_t ev_main = nullptr;
+  mase::Dev d{};
+  std::vector<void*> dallocs;
+  double2* xscratch = nullptr;
+  double* stage_vm = nullptr;
+  double* stage_va = nullptr;
+  double* dtol = nullptr;
+  size_t lds_asm = 0;
+  bool br_lds = false;
+  int nslot_g = 0;
+  bool have_z = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int32_t* h_active = nullptr;
+  int32_t* h_status = nullptr;
+  int32_t* h_iters = nullptr;
+  double* h_maxdx = nullptr;
+  double* h_tol = nullptr;
+  std::vector<mase::SysMeta> hsys;
+  // per-stage timing
+  bool prof = false;
+  hipEvent_t pev[2 * MASE_N_STAGE] = {};
+  bool pused[MASE_N_STAGE] = {};
+  double pms[MASE_N_STAGE] = {};
+  int64_t plaunch[MASE_N_STAGE] = {};
+  int64_t punits[MASE_N_STAGE] = {};
+};
+
+namespace mase {
+// Records msg as the thread's last error and returns code.
+int set_error(int code, const std::string& msg);
+// Launch of the batched objective (J per area and snapshot into jpart) at
+// the state x (device, [n_snap][n_bus]).
+int objective_at(mase_ctx* c, double2* x, double* jpart);
+}  // namespace mase

@@ -39,6 +39,9 @@ SYMBOLS = (
     "mase_stage_assemble", "mase_stage_condense", "mase_stage_gamma_assemble",
     "mase_stage_gamma_solve", "mase_stage_update", "mase_read_local_system", "mase_read_schur",
     "mase_read_gamma_system", "mase_read_step", "mase_profile", "mase_profile_read",
+    "mase_mlp_create", "mase_mlp_destroy", "mase_mlp_info", "mase_mlp_io_map", "mase_mlp_set_params",
+    "mase_mlp_get_params", "mase_mlp_set_norm", "mase_mlp_loss_grad", "mase_mlp_train_step",
+    "mase_mlp_predict_dev", "mase_warm_start",
 )
 
 
@@ -103,6 +106,17 @@ def load():
         "mase_read_step": (ctypes.c_int, [P, ctypes.c_int32, f64p]),
         "mase_profile": (ctypes.c_int, [P, ctypes.c_int32]),
         "mase_profile_read": (ctypes.c_int, [P, f64p, i64p, i64p]),
+        "mase_mlp_create": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(P)]),
+        "mase_mlp_destroy": (None, [P]),
+        "mase_mlp_info": (ctypes.c_int, [P, ctypes.c_int32, i32p, i32p, i64p]),
+        "mase_mlp_io_map": (ctypes.c_int, [P, ctypes.c_int32, i32p, i32p]),
+        "mase_mlp_set_params": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_float)]),
+        "mase_mlp_get_params": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_float)]),
+        "mase_mlp_set_norm": (ctypes.c_int, [P, f64p, f64p, f64p]),
+        "mase_mlp_loss_grad": (ctypes.c_int, [P, P, P, P, ctypes.c_int32, f64p, ctypes.POINTER(ctypes.c_float)]),
+        "mase_mlp_train_step": (ctypes.c_int, [P, P, P, P, ctypes.c_int32, ctypes.c_float, f64p]),
+        "mase_mlp_predict_dev": (ctypes.c_int, [P, P, ctypes.c_int32, P, P]),
+        "mase_warm_start": (ctypes.c_int, [P, P, i32p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -358,3 +372,79 @@ class Mase:
         dx = np.zeros(2 * self.n_bus)
         _check(self.lib.mase_read_step(self.ctx, int(snap), dx.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return dx
+
+
+class Mlp:
+    """Per-area warm-start networks of one context (mase_mlp*)."""
+
+    def __init__(self, ctx: "Mase", hidden=256, max_batch=256):
+        self.lib = load()
+        self.owner = ctx
+        self.hidden = int(hidden)
+        self.h = ctypes.c_void_p()
+        _check(self.lib.mase_mlp_create(ctx.ctx, int(hidden), int(max_batch), ctypes.byref(self.h)))
+        n_in, n_out, n_param = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _check(self.lib.mase_mlp_info(self.h, -1, ctypes.byref(n_in), ctypes.byref(n_out), ctypes.byref(n_param)))
+        self.n_param = int(n_param.value)
+        self.n_out = int(n_out.value)
+        self.shapes, self.in_meas, self.out_var = [], [], []
+        for k in range(ctx.n_area):
+            _check(self.lib.mase_mlp_info(self.h, k, ctypes.byref(n_in), ctypes.byref(n_out), None))
+            mi = np.zeros(n_in.value, dtype=np.int32)
+            ov = np.zeros(n_out.value, dtype=np.int32)
+            _check(self.lib.mase_mlp_io_map(self.h, k, mi.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                            ov.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+            self.in_meas.append(mi)
+            self.out_var.append(ov)
+            self.shapes.append((int(n_in.value), self.hidden, int(n_out.value)))
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.mase_mlp_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def mase_mlp_set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == self.n_param
+        _check(self.lib.mase_mlp_set_params(self.h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def mase_mlp_get_params(self):
+        p = np.zeros(self.n_param, dtype=np.float32)
+        _check(self.lib.mase_mlp_get_params(self.h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return p
+
+    def mase_mlp_set_norm(self, z_mean, y_mean, y_std):
+        zm, zp = _f64(z_mean)
+        ym, yp = _f64(y_mean)
+        ys, sp = _f64(y_std)
+        _check(self.lib.mase_mlp_set_norm(self.h, zp, yp, sp))
+
+    def mase_mlp_loss_grad(self, z_dev, vm_dev, va_dev, batch, want_grad=True):
+        loss = ctypes.c_double()
+        g = np.zeros(self.n_param, dtype=np.float32) if want_grad else None
+        _check(self.lib.mase_mlp_loss_grad(self.h, _dptr(z_dev), _dptr(vm_dev), _dptr(va_dev), int(batch),
+                                           ctypes.byref(loss),
+                                           g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if want_grad else None))
+        return float(loss.value), g
+
+    def mase_mlp_train_step(self, z_dev, vm_dev, va_dev, batch, lr, want_loss=False):
+        loss = ctypes.c_double()
+        _check(self.lib.mase_mlp_train_step(self.h, _dptr(z_dev), _dptr(vm_dev), _dptr(va_dev), int(batch),
+                                            float(lr), ctypes.byref(loss) if want_loss else None))
+        return float(loss.value) if want_loss else None
+
+    def mase_mlp_predict_dev(self, z_dev, batch, vm_dev, va_dev):
+        _check(self.lib.mase_mlp_predict_dev(self.h, _dptr(z_dev), int(batch), _dptr(vm_dev), _dptr(va_dev)))
+
+
+def mase_warm_start(ctx: Mase, mlp: Mlp):
+    """Warm start of ctx's snapshots from mlp; returns the accepted flags."""
+    acc = np.zeros(ctx.n_snap, dtype=np.int32)
+    _check(load().mase_warm_start(ctx.ctx, mlp.h, acc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return acc.astype(bool)

@@ -1,0 +1,146 @@
+"""Learned warm start: training-set generation, training loop, checkpoints.
+
+The networks and every computation on them live in the HIP library (bf16
+MFMA forward/backward and Adam kernels, include/mase.h); this module only
+orchestrates: it draws seeded drift chains (gridgen), lets the library's
+plain flat-start Gauss-Newton converge them to build (z, x_hat) pairs,
+initialises and normalises the networks, and runs minibatch training.
+PyTorch is used for device memory only.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from gridgen import synth
+
+from . import mase
+
+TRAIN_SEED = 10_000
+HELDOUT_SEED = 20_000
+
+
+def measurements_dev(ctx: mase.Mase, vm, va, eps, sigma, device):
+    """z = h(x) + sigma * eps on the device for one batch of ctx.n_snap states."""
+    vm_t = torch.as_tensor(vm, device=device, dtype=torch.float64).contiguous()
+    va_t = torch.as_tensor(va, device=device, dtype=torch.float64).contiguous()
+    h = torch.empty((ctx.n_snap, ctx.n_meas), dtype=torch.float64, device=device)
+    torch.cuda.synchronize()
+    ctx.mase_eval_h_dev(vm_t, va_t, h)
+    torch.cuda.synchronize()
+    z = h + torch.as_tensor(sigma, device=device) * torch.as_tensor(eps, device=device)
+    # the library reads z on its own stream: finish torch's work first
+    torch.cuda.synchronize()
+    return z
+
+
+def solved_set(ctx: mase.Mase, grid, sigma, n_chain, chain_len, seed, device, tol=1e-8, max_iter=15):
+    """(z, vm_hat, va_hat) for n_chain drift chains of chain_len snapshots.
+
+    Each chain starts from the grid's base state (independent seeds seed+c);
+    every snapshot is converged by the plain flat-start Gauss-Newton of the
+    library in batches of ctx.n_snap.  Returns device tensors [n, ...].
+    """
+    vm, va, eps = synth.make_chains(grid, n_chain, chain_len, seed)
+    va = va - va[:, [grid.slack]]
+    n, S = vm.shape[0], ctx.n_snap
+    z_all = torch.empty((n, ctx.n_meas), dtype=torch.float64, device=device)
+    vm_all = torch.empty((n, ctx.n_bus), dtype=torch.float64, device=device)
+    va_all = torch.empty_like(vm_all)
+    out_vm = torch.empty((S, ctx.n_bus), dtype=torch.float64, device=device)
+    out_va = torch.empty_like(out_vm)
+    n_bad = 0
+    for b0 in range(0, n, S):
+        idx = np.arange(b0, b0 + S) % n  # the last batch wraps around
+        z = measurements_dev(ctx, vm[idx], va[idx], eps[idx], sigma, device)
+        ctx.mase_set_measurements_dev(z)
+        ctx.mase_set_state_dev(None, None)
+        iters, conv = ctx.mase_solve(tol, max_iter)
+        n_bad += int((~conv).sum())
+        ctx.mase_state_dev(out_vm, out_va)
+        torch.cuda.synchronize()
+        keep = min(S, n - b0)
+        z_all[b0:b0 + keep] = z[:keep]
+        vm_all[b0:b0 + keep] = out_vm[:keep]
+        va_all[b0:b0 + keep] = out_va[:keep]
+    torch.cuda.synchronize()
+    return z_all, vm_all, va_all, n_bad
+
+
+def input_rms(mlp: mase.Mlp, z, z_mean, sigma):
+    """Per-area RMS of the normalised inputs (z - z_mean) / sigma over z."""
+    zn = (z - torch.as_tensor(z_mean, device=z.device)) / torch.as_tensor(sigma, device=z.device)
+    ms = (zn * zn).mean(0).cpu().numpy()
+    return [float(np.sqrt(ms[im].mean())) for im in mlp.in_meas]
+
+
+def init_params(mlp: mase.Mlp, seed=0, in_rms=None):
+    """He-normal weights (first layer divided by the area's input RMS, since
+    measurements normalised by sigma spread far beyond unit scale), zero
+    biases, a small output layer; in the library's parameter order."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for k, (m, H, O) in enumerate(mlp.shapes):
+        r = 1.0 if in_rms is None else max(in_rms[k], 1e-3)
+        parts += [rng.normal(0, np.sqrt(2.0 / m) / r, m * H), np.zeros(H),
+                  rng.normal(0, np.sqrt(2.0 / H), H * H), np.zeros(H),
+                  rng.normal(0, 0.1 * np.sqrt(1.0 / H), H * O), np.zeros(O)]
+    p = np.concatenate(parts).astype(np.float32)
+    mlp.mase_mlp_set_params(p)
+    return p
+
+
+def set_normalisation(mlp: mase.Mlp, z, vm, va):
+    """z mean per measurement; per-variable mean / std of the targets."""
+    z_mean = z.mean(0).cpu().numpy()
+    n_bus = vm.shape[1]
+    y_mean = np.zeros(2 * n_bus)
+    y_std = np.ones(2 * n_bus)
+    y_mean[0::2] = va.mean(0).cpu().numpy()
+    y_mean[1::2] = vm.mean(0).cpu().numpy()
+    sa = va.std(0).cpu().numpy()
+    sv = vm.std(0).cpu().numpy()
+    y_std[0::2] = np.where(sa > 1e-6, sa, 1.0)
+    y_std[1::2] = np.where(sv > 1e-6, sv, 1.0)
+    mlp.mase_mlp_set_norm(z_mean, y_mean, y_std)
+    return z_mean, y_mean, y_std
+
+
+def train(mlp: mase.Mlp, z, vm, va, epochs=30, batch=256, lr=1e-3, lr_final=1e-5, seed=0, log=None):
+    """Minibatch Adam over shuffled (z, x_hat) pairs with a cosine lr decay."""
+    n = z.shape[0]
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    steps = epochs * (n // batch)
+    step = 0
+    history = []
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=g).to(z.device)
+        zs, vms, vas = z[perm].contiguous(), vm[perm].contiguous(), va[perm].contiguous()
+        torch.cuda.synchronize()
+        losses = []
+        for b0 in range(0, n - batch + 1, batch):
+            t = step / max(1, steps - 1)
+            cur = lr_final + 0.5 * (lr - lr_final) * (1 + np.cos(np.pi * t))
+            want = (b0 == 0)
+            l = mlp.mase_mlp_train_step(zs[b0:], vms[b0:], vas[b0:], batch, cur, want_loss=want)
+            if want:
+                losses.append(l)
+            step += 1
+        history.append(float(np.mean(losses)) if losses else float("nan"))
+        if log:
+            log(f"epoch {ep}: loss {history[-1]:.4g}")
+    torch.cuda.synchronize()
+    return history
+
+
+def save(path, mlp: mase.Mlp, norm):
+    z_mean, y_mean, y_std = norm
+    np.savez(path, params=mlp.mase_mlp_get_params(), z_mean=z_mean, y_mean=y_mean, y_std=y_std,
+             hidden=mlp.hidden)
+
+
+def load_into(path, mlp: mase.Mlp):
+    d = np.load(path)
+    mlp.mase_mlp_set_params(d["params"])
+    mlp.mase_mlp_set_norm(d["z_mean"], d["y_mean"], d["y_std"])
+    return d["z_mean"], d["y_mean"], d["y_std"]
