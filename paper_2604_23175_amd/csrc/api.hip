@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -88,8 +89,11 @@ int upload_plan(mase_ctx* c) {
     cd_items.insert(cd_items.end(), s.cd_items.begin(), s.cd_items.end());
     m.up_ptr = (int32_t)up_ptr.size();
     append_rebased(up_ptr, s.up_ptr, (int32_t)up_tgt.size());
-    for (const I4& t : s.up_tgt)
-      up_tgt.push_back({t.x, t.y, t.z + (int32_t)up_con.size(), t.w + (int32_t)up_con.size()});
+    // a single-contribution target carries its two LDS slots inline: not rebased
+    for (const I4& t : s.up_tgt) {
+      const int32_t base = (t.y & UP_SINGLE) ? 0 : (int32_t)up_con.size();
+      up_tgt.push_back({t.x, t.y, t.z + base, t.w + base});
+    }
     up_con.insert(up_con.end(), s.up_con.begin(), s.up_con.end());
     m.rb_ptr = (int32_t)rb_ptr.size();
     append_rebased(rb_ptr, s.rb_ptr, (int32_t)rb_tgt.size());
@@ -154,6 +158,19 @@ int upload_plan(mase_ctx* c) {
   c->br_lds = lds_br <= (size_t)maxlds;
   lds = c->br_lds ? lds_br : lds_nobr;
   c->lds_asm = lds;
+  c->lds_el_area = 0;
+  for (int k = 0; k < K; ++k) c->lds_el_area = std::max(c->lds_el_area, 8 * (size_t)p.sys[k].lds_doubles);
+  c->lds_el_gamma = 8 * (size_t)p.sys[K].lds_doubles;
+  if (std::max(c->lds_el_area, c->lds_el_gamma) > 65536)
+    HIPTRY(allow_eliminate_lds(std::max(c->lds_el_area, c->lds_el_gamma)));
+  // boundary dense block: stage each panel in LDS when it fits beside the
+  // kernel's static arrays (MASE_DENSE_PANEL=0 forces the global-memory variant)
+  {
+    const size_t pan = dense_lds_bytes(p.sys[K].ld, true);
+    const char* env = getenv("MASE_DENSE_PANEL");
+    c->dense_panel = pan + 8192 <= (size_t)maxlds && !(env && env[0] == '0');
+    if (c->dense_panel && pan > 65536) HIPTRY(allow_dense_lds(pan));
+  }
   c->hsys = sm;
   c->nslot_g = (int)p.g_slot.size();
 
@@ -242,7 +259,7 @@ int launch_batched_iteration(mase_ctx* c, hipStream_t st) {
   }
   {
     StageMark m(c, st, MASE_STAGE_CONDENSE);
-    HIPTRY(launch_eliminate(d, 0, K, 0, S, st));
+    HIPTRY(launch_eliminate(d, 0, K, 0, S, c->lds_el_area, st));
   }
   const SysMeta& g = gsys(c);
   if (g.nn > 0) {
@@ -252,11 +269,11 @@ int launch_batched_iteration(mase_ctx* c, hipStream_t st) {
     }
     if (g.ne > 0) {
       StageMark m(c, st, MASE_STAGE_GAMMA_SPARSE);
-      HIPTRY(launch_eliminate(d, K, 1, 0, S, st));
+      HIPTRY(launch_eliminate(d, K, 1, 0, S, c->lds_el_gamma, st));
     }
     {
       StageMark m(c, st, MASE_STAGE_GAMMA_DENSE);
-      HIPTRY(launch_dense_chol(d, 0, S, g.ld, st));
+      HIPTRY(launch_dense_chol(d, 0, S, g.ld, c->dense_panel, st));
     }
     if (g.ne > 0) {
       StageMark m(c, st, MASE_STAGE_GAMMA_BACK);
@@ -301,7 +318,7 @@ int launch_plain_iteration(mase_ctx* c, int s) {
   for (int ai = 0; ai < K; ++ai) {
     hipStream_t as = c->astreams[ai % ns];
     HIPTRY(launch_assemble(d, ai, 1, s, 1, MODE_ASSEMBLE, c->lds_asm, c->br_lds, as));
-    HIPTRY(launch_eliminate(d, ai, 1, s, 1, as));
+    HIPTRY(launch_eliminate(d, ai, 1, s, 1, c->lds_el_area, as));
   }
   for (int i = 0; i < ns; ++i) {
     HIPTRY(hipEventRecord(c->aevents[i], c->astreams[i]));
@@ -310,8 +327,8 @@ int launch_plain_iteration(mase_ctx* c, int s) {
   const SysMeta& g = gsys(c);
   if (g.nn > 0) {
     HIPTRY(launch_gamma_gather(d, s, 1, c->nslot_g, g.nn, st));
-    if (g.ne > 0) HIPTRY(launch_eliminate(d, K, 1, s, 1, st));
-    HIPTRY(launch_dense_chol(d, s, 1, g.ld, st));
+    if (g.ne > 0) HIPTRY(launch_eliminate(d, K, 1, s, 1, c->lds_el_gamma, st));
+    HIPTRY(launch_dense_chol(d, s, 1, g.ld, c->dense_panel, st));
     if (g.ne > 0) HIPTRY(launch_backsolve(d, K, 1, s, 1, st));
   }
   HIPTRY(hipEventRecord(c->ev_main, st));
@@ -828,7 +845,7 @@ int mase_stage_assemble(mase_ctx* c) {
 int mase_stage_condense(mase_ctx* c) {
   int rc = check_device(c);
   if (rc) return rc;
-  HIPTRY(launch_eliminate(c->d, 0, c->plan.n_area, 0, c->plan.n_snap, c->stream));
+  HIPTRY(launch_eliminate(c->d, 0, c->plan.n_area, 0, c->plan.n_snap, c->lds_el_area, c->stream));
   HIPTRY(hipStreamSynchronize(c->stream));
   return 0;
 }
@@ -848,8 +865,8 @@ int mase_stage_gamma_solve(mase_ctx* c) {
   const SysMeta& g = gsys(c);
   const int K = c->plan.n_area, S = c->plan.n_snap;
   if (g.nn > 0) {
-    if (g.ne > 0) HIPTRY(launch_eliminate(c->d, K, 1, 0, S, c->stream));
-    HIPTRY(launch_dense_chol(c->d, 0, S, g.ld, c->stream));
+    if (g.ne > 0) HIPTRY(launch_eliminate(c->d, K, 1, 0, S, c->lds_el_gamma, c->stream));
+    HIPTRY(launch_dense_chol(c->d, 0, S, g.ld, c->dense_panel, c->stream));
     if (g.ne > 0) HIPTRY(launch_backsolve(c->d, K, 1, 0, S, c->stream));
   }
   HIPTRY(hipStreamSynchronize(c->stream));

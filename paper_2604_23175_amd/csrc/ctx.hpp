@@ -27,6 +27,8 @@ struct mase_ctx {
   double* dtol = nullptr;
   size_t lds_asm = 0;
   bool br_lds = false;
+  size_t lds_el_area = 0, lds_el_gamma = 0;  // elimination staging LDS bytes
+  bool dense_panel = false;                   // dense block panels staged in LDS
   int nslot_g = 0;
   bool have_z = false;
   hipGraph_t graph = nullptr;

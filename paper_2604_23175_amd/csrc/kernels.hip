@@ -26,6 +26,7 @@ namespace {
 
 constexpr int VM = 0, QINJ = 2, PT = 5, QF = 4, QT = 6;
 constexpr int ROLE_SELF = 0xFFFF;
+constexpr int UP_SINGLE_FLAG = 1 << 30;  // update target with one inline contribution
 
 // Workgroups are handed to the 8 XCDs round-robin by block index.  When the
 // area count is a multiple of 8, all snapshots of one area land on one XCD so
@@ -327,6 +328,9 @@ __global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int
   const SysMeta sm = d.sys[k];
   double* vals = d.vals + (int64_t)s * d.vstride + sm.val_off;
   double* rhs = d.rhs + (int64_t)s * d.rstride + sm.rhs_off;
+  // the level's new factor blocks (4 doubles each) and y_j (2 each)
+  extern __shared__ double2 lstage2[];
+  double* lst = reinterpret_cast<double*>(lstage2);
   const int tid = threadIdx.x;
   bool bad = false;
   for (int lev = 0; lev < sm.nlev; ++lev) {
@@ -338,15 +342,21 @@ __global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int
       if (!chol2(D[0], D[1], D[3], l00, l10, l11)) { bad = true; l00 = l11 = 1.0; l10 = 0.0; }
       if (c.y < 0) {
         const double y0 = rhs[c.z] / l00;
+        const double y1 = (rhs[c.z + 1] - l10 * y0) / l11;
         rhs[c.z] = y0;
-        rhs[c.z + 1] = (rhs[c.z + 1] - l10 * y0) / l11;
+        rhs[c.z + 1] = y1;
+        lst[c.w] = y0;
+        lst[c.w + 1] = y1;
       } else {
         double* M = vals + c.y;  // X L^T = M
-        const double x00 = M[0] / l00, x10 = M[1] / l00;
-        M[0] = x00;
-        M[1] = x10;
-        M[2] = (M[2] - x00 * l10) / l11;
-        M[3] = (M[3] - x10 * l10) / l11;
+        const double2 m0 = *reinterpret_cast<const double2*>(M);
+        const double2 m1 = *reinterpret_cast<const double2*>(M + 2);
+        const double x00 = m0.x / l00, x10 = m0.y / l00;
+        const double x01 = (m1.x - x00 * l10) / l11, x11 = (m1.y - x10 * l10) / l11;
+        *reinterpret_cast<double2*>(M) = make_double2(x00, x10);
+        *reinterpret_cast<double2*>(M + 2) = make_double2(x01, x11);
+        *reinterpret_cast<double2*>(lst + c.w) = make_double2(x00, x10);
+        *reinterpret_cast<double2*>(lst + c.w + 2) = make_double2(x01, x11);
       }
     }
     __syncthreads();
@@ -354,13 +364,16 @@ __global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int
     for (int it = u0 + tid; it < u1; it += NT) {
       const int4 t = d.up_tgt[it];
       double a00 = 0, a10 = 0, a01 = 0, a11 = 0;
+      const bool single = (t.y & UP_SINGLE_FLAG) != 0;
+      const int stride = t.y & ~UP_SINGLE_FLAG;
+      const int cb = single ? 0 : t.z, ce = single ? 1 : t.w;
       bool sym = false;
-      for (int c = t.z; c < t.w; ++c) {
-        const int2 u = d.up_con[c];
-        const double2 L0 = *reinterpret_cast<const double2*>(vals + u.x);
-        const double2 L1 = *reinterpret_cast<const double2*>(vals + u.x + 2);
-        const double2 P0 = *reinterpret_cast<const double2*>(vals + u.y);
-        const double2 P1 = *reinterpret_cast<const double2*>(vals + u.y + 2);
+      for (int c = cb; c < ce; ++c) {
+        const int2 u = single ? make_int2(t.z, t.w) : d.up_con[c];
+        const double2 L0 = *reinterpret_cast<const double2*>(lst + u.x);
+        const double2 L1 = *reinterpret_cast<const double2*>(lst + u.x + 2);
+        const double2 P0 = *reinterpret_cast<const double2*>(lst + u.y);
+        const double2 P1 = *reinterpret_cast<const double2*>(lst + u.y + 2);
         a00 += L0.x * P0.x + L1.x * P1.x;
         a10 += L0.y * P0.x + L1.y * P1.x;
         a01 += L0.x * P0.y + L1.x * P1.y;
@@ -371,8 +384,8 @@ __global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int
       double* C = vals + t.x;
       C[0] -= a00;
       C[1] -= a10;
-      C[t.y] -= a01;
-      C[t.y + 1] -= a11;
+      C[stride] -= a01;
+      C[stride + 1] -= a11;
     }
     const int r0 = d.rb_ptr[sm.rb_ptr + lev], r1 = d.rb_ptr[sm.rb_ptr + lev + 1];
     for (int it = r0 + tid; it < r1; it += NT) {
@@ -380,8 +393,8 @@ __global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int
       double b0 = 0, b1 = 0;
       for (int c = t.y; c < t.z; ++c) {
         const int2 u = d.rb_con[c];
-        const double* L = vals + u.x;
-        const double y0 = rhs[u.y], y1 = rhs[u.y + 1];
+        const double* L = lst + u.x;
+        const double y0 = lst[u.y], y1 = lst[u.y + 1];
         b0 += L[0] * y0 + L[2] * y1;
         b1 += L[1] * y0 + L[3] * y1;
       }
@@ -455,7 +468,9 @@ __global__ void __launch_bounds__(256) k_gamma_gather(Dev d, int s0, int nslot) 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int DENSE_NT = 512;
+constexpr int PANEL_PITCH = 17;  // doubles per staged panel row (odd: no LDS bank conflicts)
 
+template <bool LDS_PANEL>
 __global__ void __launch_bounds__(DENSE_NT) k_dense_chol(Dev d, int s0) {
   const int s = s0 + blockIdx.x;
   if (!d.active[s]) return;
@@ -465,7 +480,8 @@ __global__ void __launch_bounds__(DENSE_NT) k_dense_chol(Dev d, int s0) {
   const int nlive = 2 * g.nt;
   double* A = d.vals + (int64_t)s * d.vstride + g.val_off + g.tail_off;
   double* b = d.rhs + (int64_t)s * d.rstride + g.rhs_off + 2 * g.ne;
-  extern __shared__ double bl[];  // [n] rhs, then solution
+  extern __shared__ double bl[];  // [n] rhs, then solution; then the staged panel
+  double* Lp = bl + n;            // [n - 16][PANEL_PITCH]: rows below the diagonal block
   __shared__ double Lk[16 * 17];
   __shared__ double part[16 * 16];
   __shared__ int bad;
@@ -528,6 +544,7 @@ __global__ void __launch_bounds__(DENSE_NT) k_dense_chol(Dev d, int s0) {
         for (int m = 0; m < c; ++m) a -= x[m] * Lk[c * 17 + m];
         x[c] = a / Lk[c * 17 + c];
         A[(int64_t)(c0 + c) * n + row] = x[c];
+        if (LDS_PANEL) Lp[(row - c0 - 16) * PANEL_PITCH + c] = x[c];
         acc += x[c] * bl[c0 + c];
       }
       bl[row] -= acc;
@@ -548,8 +565,14 @@ __global__ void __launch_bounds__(DENSE_NT) k_dense_chol(Dev d, int s0) {
       d4 acc;
       for (int q = 0; q < 4; ++q) acc[q] = A[(int64_t)(rj + li) * n + ri + 4 * q + lk];
       for (int q = 0; q < 4; ++q) {
-        const double a = -A[(int64_t)(c0 + 4 * q + lk) * n + ri + li];
-        const double bb = A[(int64_t)(c0 + 4 * q + lk) * n + rj + li];
+        double a, bb;
+        if (LDS_PANEL) {
+          a = -Lp[(ri - c0 - 16 + li) * PANEL_PITCH + 4 * q + lk];
+          bb = Lp[(rj - c0 - 16 + li) * PANEL_PITCH + 4 * q + lk];
+        } else {
+          a = -A[(int64_t)(c0 + 4 * q + lk) * n + ri + li];
+          bb = A[(int64_t)(c0 + 4 * q + lk) * n + rj + li];
+        }
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
       }
       for (int q = 0; q < 4; ++q) A[(int64_t)(rj + li) * n + ri + 4 * q + lk] = acc[q];
@@ -746,13 +769,21 @@ hipError_t launch_assemble(const Dev& d, int a0, int na, int s0, int ns, int mod
   return hipGetLastError();
 }
 
-hipError_t launch_eliminate(const Dev& d, int sys0, int nsys, int s0, int ns, hipStream_t st) {
+hipError_t launch_eliminate(const Dev& d, int sys0, int nsys, int s0, int ns, size_t lds, hipStream_t st) {
   if (nsys <= 0 || ns <= 0) return hipSuccess;
   if (sys0 >= d.n_area)
-    hipLaunchKernelGGL(k_eliminate<GAMMA_NT>, dim3(nsys * ns), dim3(GAMMA_NT), 0, st, d, sys0, nsys, s0, ns);
+    hipLaunchKernelGGL(k_eliminate<GAMMA_NT>, dim3(nsys * ns), dim3(GAMMA_NT), lds, st, d, sys0, nsys, s0, ns);
   else
-    hipLaunchKernelGGL(k_eliminate<AREA_NT>, dim3(nsys * ns), dim3(AREA_NT), 0, st, d, sys0, nsys, s0, ns);
+    hipLaunchKernelGGL(k_eliminate<AREA_NT>, dim3(nsys * ns), dim3(AREA_NT), lds, st, d, sys0, nsys, s0, ns);
   return hipGetLastError();
+}
+
+hipError_t allow_eliminate_lds(size_t bytes) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eliminate<GAMMA_NT>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eliminate<AREA_NT>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 hipError_t launch_gamma_gather(const Dev& d, int s0, int ns, int nslot, int nn, hipStream_t st) {
@@ -762,10 +793,22 @@ hipError_t launch_gamma_gather(const Dev& d, int s0, int ns, int nslot, int nn, 
   return hipGetLastError();
 }
 
-hipError_t launch_dense_chol(const Dev& d, int s0, int ns, int ld, hipStream_t st) {
+size_t dense_lds_bytes(int ld, bool panel) {
+  return sizeof(double) * ((size_t)ld + (panel ? (size_t)ld * PANEL_PITCH : 0));
+}
+
+hipError_t launch_dense_chol(const Dev& d, int s0, int ns, int ld, bool panel, hipStream_t st) {
   if (ld <= 0 || ns <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_dense_chol, dim3(ns), dim3(DENSE_NT), sizeof(double) * (size_t)ld, st, d, s0);
+  if (panel)
+    hipLaunchKernelGGL(k_dense_chol<true>, dim3(ns), dim3(DENSE_NT), dense_lds_bytes(ld, true), st, d, s0);
+  else
+    hipLaunchKernelGGL(k_dense_chol<false>, dim3(ns), dim3(DENSE_NT), dense_lds_bytes(ld, false), st, d, s0);
   return hipGetLastError();
+}
+
+hipError_t allow_dense_lds(size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dense_chol<true>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 hipError_t launch_backsolve(const Dev& d, int sys0, int nsys, int s0, int ns, hipStream_t st) {

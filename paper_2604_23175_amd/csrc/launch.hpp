@@ -12,9 +12,14 @@ namespace mase {
 size_t assemble_lds_bytes(int nn, int nbr, bool br_lds);
 hipError_t launch_assemble(const Dev& d, int a0, int na, int s0, int ns, int mode, size_t lds,
                            bool br_lds, hipStream_t st);
-hipError_t launch_eliminate(const Dev& d, int sys0, int nsys, int s0, int ns, hipStream_t st);
+// lds: dynamic LDS bytes for the level staging (max over the launched systems)
+hipError_t launch_eliminate(const Dev& d, int sys0, int nsys, int s0, int ns, size_t lds, hipStream_t st);
+hipError_t allow_eliminate_lds(size_t bytes);
 hipError_t launch_gamma_gather(const Dev& d, int s0, int ns, int nslot, int nn, hipStream_t st);
-hipError_t launch_dense_chol(const Dev& d, int s0, int ns, int ld, hipStream_t st);
+// panel: stage each factor panel in LDS (needs dense_lds_bytes(ld, true))
+size_t dense_lds_bytes(int ld, bool panel);
+hipError_t launch_dense_chol(const Dev& d, int s0, int ns, int ld, bool panel, hipStream_t st);
+hipError_t allow_dense_lds(size_t bytes);
 hipError_t launch_backsolve(const Dev& d, int sys0, int nsys, int s0, int ns, hipStream_t st);
 hipError_t launch_update(const Dev& d, int s0, int ns, hipStream_t st);
 hipError_t launch_pack_state(const Dev& d, const double* vm, const double* va, double2* xout,

@@ -99,10 +99,30 @@ void finish_system(SysPlan& s) {
       if (i < s.ne) { par = i; break; }
     if (par >= 0) s.level[par] = std::max(s.level[par], s.level[j] + 1);
   }
-  s.nlev = 0;
-  for (int j = 0; j < s.ne; ++j) s.nlev = std::max(s.nlev, s.level[j] + 1);
-  std::vector<std::vector<int>> bylev(s.nlev);
-  for (int j = 0; j < s.ne; ++j) bylev[s.level[j]].push_back(j);
+  int ntree = 0;
+  for (int j = 0; j < s.ne; ++j) ntree = std::max(ntree, s.level[j] + 1);
+  std::vector<std::vector<int>> tree_lev(ntree);
+  for (int j = 0; j < s.ne; ++j) tree_lev[s.level[j]].push_back(j);
+  // Schedule steps: the columns of one tree level are independent, so a wide
+  // level is split into consecutive steps whose LDS staging (4 doubles per
+  // factor block, 2 per y_j) stays within the budget.
+  std::vector<std::vector<int>> bylev;
+  for (const auto& cols : tree_lev) {
+    std::vector<int> cur;
+    int need = 0;
+    for (int j : cols) {
+      const int add = 4 * (int)s.strct[j].size() + 2;
+      if (!cur.empty() && need + add > LDS_STAGE_DOUBLES) {
+        bylev.push_back(cur);
+        cur.clear();
+        need = 0;
+      }
+      cur.push_back(j);
+      need += add;
+    }
+    if (!cur.empty()) bylev.push_back(cur);
+  }
+  s.nlev = (int)bylev.size();
 
   s.cd_ptr.assign(1, 0);
   s.up_ptr.assign(1, 0);
@@ -112,19 +132,38 @@ void finish_system(SysPlan& s) {
   s.rb_tgt.clear(); s.rb_con.clear(); s.bs_items.clear(); s.bs_con.clear();
   struct UpT { int32_t tgt, stride, lij, lpj, j; };
   struct RbT { int32_t rhs_i, lij, rhs_j, j; };
+  s.lds_doubles = 0;
   for (int lev = 0; lev < s.nlev; ++lev) {
     std::vector<UpT> ups;
     std::vector<RbT> rbs;
-    for (int j : bylev[lev]) {
+    // LDS staging of the level: every off-diagonal factor block L_ij of the
+    // level's columns gets 4 doubles, then every y_j gets 2 doubles
+    int nsrc = 0;
+    for (int j : bylev[lev]) nsrc += (int)s.strct[j].size();
+    std::unordered_map<int32_t, int32_t> slot_of;  // global block offset -> LDS double offset
+    int next_src = 0, next_y = 0;
+    std::vector<int32_t> yslot(bylev[lev].size());
+    for (size_t q = 0; q < bylev[lev].size(); ++q) {
+      const int j = bylev[lev][q];
+      yslot[q] = 4 * nsrc + 2 * next_y++;
+      s.cd_items.push_back({s.col_off[j], -1, 2 * j, yslot[q]});
+      for (int i : s.strct[j]) {
+        const int32_t off = s.blk_off(i, j);
+        slot_of[off] = 4 * next_src++;
+        s.cd_items.push_back({s.col_off[j], off, 0, slot_of[off]});
+      }
+    }
+    s.lds_doubles = std::max(s.lds_doubles, 4 * nsrc + 2 * next_y);
+    for (size_t q = 0; q < bylev[lev].size(); ++q) {
+      const int j = bylev[lev][q];
       const auto& st = s.strct[j];
-      s.cd_items.push_back({s.col_off[j], -1, 2 * j, 0});
-      for (int i : st) s.cd_items.push_back({s.col_off[j], s.blk_off(i, j), 0, 0});
       for (size_t a = 0; a < st.size(); ++a) {
         const int i = st[a];
-        rbs.push_back({2 * i, s.blk_off(i, j), 2 * j, j});
+        rbs.push_back({2 * i, slot_of.at(s.blk_off(i, j)), yslot[q], j});
         for (size_t b = 0; b <= a; ++b) {
           const int p = st[b];  // p <= i
-          ups.push_back({s.blk_off(i, p), s.blk_stride(i, p), s.blk_off(i, j), s.blk_off(p, j), j});
+          ups.push_back({s.blk_off(i, p), s.blk_stride(i, p), slot_of.at(s.blk_off(i, j)),
+                         slot_of.at(s.blk_off(p, j)), j});
         }
       }
       // back-solve item for column j
@@ -138,9 +177,14 @@ void finish_system(SysPlan& s) {
     for (size_t a = 0; a < ups.size();) {
       size_t b = a;
       while (b < ups.size() && ups[b].tgt == ups[a].tgt) ++b;
-      s.up_tgt.push_back({ups[a].tgt, ups[a].stride, (int32_t)s.up_con.size(),
-                          (int32_t)(s.up_con.size() + (b - a))});
-      for (size_t c = a; c < b; ++c) s.up_con.push_back({ups[c].lij, ups[c].lpj});
+      if (b - a == 1) {
+        // one contribution: its two LDS slots ride in the target record
+        s.up_tgt.push_back({ups[a].tgt, ups[a].stride | UP_SINGLE, ups[a].lij, ups[a].lpj});
+      } else {
+        s.up_tgt.push_back({ups[a].tgt, ups[a].stride, (int32_t)s.up_con.size(),
+                            (int32_t)(s.up_con.size() + (b - a))});
+        for (size_t c = a; c < b; ++c) s.up_con.push_back({ups[c].lij, ups[c].lpj});
+      }
       a = b;
     }
     std::stable_sort(rbs.begin(), rbs.end(), [](const RbT& a, const RbT& b) {

@@ -19,6 +19,10 @@ struct I4 { int32_t x, y, z, w; };
 constexpr int ROLE_SELF = 0xFFFF;   // the row's own bus (injection bus, flow's measured end, |V| bus)
 constexpr int ROLE_OTHER = 0xFFFE;  // the unmeasured end of a flow row's branch
 constexpr int MAX_LOCAL_BRANCH = 0xFFF0;
+// Flag in an update target's stride: the target has exactly one contribution.
+constexpr int32_t UP_SINGLE = 1 << 30;
+// LDS budget (doubles) for staging one schedule step of the elimination.
+constexpr int LDS_STAGE_DOUBLES = 6144;
 
 // One symmetric positive definite system over "buses" (2x2 blocks: theta, |V|)
 // eliminated by the level-scheduled sparse engine.  Local buses [0, ne) are
@@ -43,14 +47,18 @@ struct SysPlan {
   int nlev = 0;
 
   // Level schedule (all offsets relative to this system's value / rhs base).
+  // The blocks L_ij a level computes and its y_j are also staged in LDS; the
+  // update lists address them by LDS double offsets ("slots").
   std::vector<int32_t> cd_ptr;  // [nlev+1] -> cd_items
-  std::vector<I4> cd_items;     // {diag_off, blk_off (-1: the diagonal item), rhs_j, 0}
+  std::vector<I4> cd_items;     // {diag_off, blk_off (-1: the diagonal item), rhs_j, LDS slot}
   std::vector<int32_t> up_ptr;  // [nlev+1] -> up_tgt
-  std::vector<I4> up_tgt;       // {tgt_off, tgt_stride, cbeg, cend}
-  std::vector<I2> up_con;       // {off L_ij, off L_pj}: target -= L_ij * L_pj^T
+  std::vector<I4> up_tgt;       // {tgt_off, tgt_stride [| UP_SINGLE], cbeg, cend} or, with
+                                // UP_SINGLE, {tgt_off, stride, slot L_ij, slot L_pj}
+  std::vector<I2> up_con;       // {slot L_ij, slot L_pj}: target -= L_ij * L_pj^T
   std::vector<int32_t> rb_ptr;  // [nlev+1] -> rb_tgt
   std::vector<I4> rb_tgt;       // {rhs_i, cbeg, cend, 0}
-  std::vector<I2> rb_con;       // {off L_ij, rhs_j}: y_i -= L_ij * y_j
+  std::vector<I2> rb_con;       // {slot L_ij, slot y_j}: y_i -= L_ij * y_j
+  int32_t lds_doubles = 0;      // LDS staging needed by the largest level
   std::vector<int32_t> bs_ptr;  // [nlev+1] -> bs_items (same levels, run top-down)
   std::vector<I4> bs_items;     // {diag_off, rhs_j, cbeg, cend}
   std::vector<I2> bs_con;       // {off L_ij, rhs_i}: t -= L_ij^T * x_i

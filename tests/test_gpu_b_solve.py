@@ -94,6 +94,26 @@ def test_dense_and_sparse_gamma_agree():
     assert_state_close(res[0][0], res[0][1], res[1][0], res[1][1], 1e-10)
 
 
+@pytest.mark.parametrize("gm", ["sparse", "dense"])
+def test_dense_block_panel_variants_bitwise_identical(gm, monkeypatch):
+    # The boundary block's Cholesky stages each panel in LDS when it fits;
+    # MASE_DENSE_PANEL=0 selects the variant that reads panels from HBM.
+    # Both do the same arithmetic in the same order.
+    say("dense panel variants", gm)
+    c = Case("c1", 2, seed=11)
+    mode = mase.MASE_GAMMA_SPARSE if gm == "sparse" else mase.MASE_GAMMA_DENSE
+    res = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("MASE_DENSE_PANEL", flag)
+        m = c.ctx(gamma_mode=mode)
+        iters, conv = m.mase_solve(1e-8, 12)
+        res.append((m.mase_state(), iters))
+        m.close()
+    np.testing.assert_array_equal(res[0][0][0], res[1][0][0])
+    np.testing.assert_array_equal(res[0][0][1], res[1][0][1])
+    np.testing.assert_array_equal(res[0][1], res[1][1])
+
+
 def test_zero_weight_equals_deleted_row():
     say("masking")
     c = Case("k5", 1, seed=6)
