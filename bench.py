@@ -145,6 +145,8 @@ def main():
                       "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1], "hidden": 256,
                       "seconds": time.perf_counter() - t_tr}
         del zt, vmt_, vat_
+        # acceptance cap from held-out chains (never the benchmark batch)
+        _, train_info["acceptance_calibration"] = ws.calibrate_accept_cap(ctx, mlp, g, s, dev)
         ctx.mase_set_measurements_dev(z)
         torch.cuda.synchronize()
 

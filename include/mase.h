@@ -264,6 +264,17 @@ int mase_mlp_predict_dev(mase_mlp* mlp, const double* z_dev, int32_t batch, doub
  */
 int mase_warm_start(mase_ctx* ctx, mase_mlp* mlp, int32_t* accepted);
 
+/* Acceptance cap of mase_warm_start: a prediction is kept only if, besides
+ * J(pred) <= J(flat), also J(pred) <= j_cap.  Default +inf (the objective
+ * comparison alone).  A caller calibrates it on held-out snapshots when
+ * predictions that beat flat start on J still cost Gauss-Newton iterations.
+ * j_cap must not be NaN (MASE_ERR_ARG). */
+int mase_mlp_set_accept_cap(mase_mlp* mlp, double j_cap);
+
+/* J(pred) and J(flat) of every snapshot [n_snap] (host) as evaluated by the
+ * last mase_warm_start; MASE_ERR_STATE before the first call. */
+int mase_warm_start_objectives(const mase_mlp* mlp, double* j_pred, double* j_flat);
+
 /* ---- per-stage timing ---- */
 
 /* Kernel stages of one iteration, in launch order. */

@@ -225,8 +225,8 @@ __global__ void k_mlp_compose(const float* Y, int B, int n_out, int n_bus, int s
 // Per snapshot: keep the prediction iff J(pred) <= J(flat) (sums over areas
 // in area order), then copy the chosen state.
 __global__ void __launch_bounds__(256) k_choose(const double* jp, const double* jf, int n_area, int n_bus,
-                                                const double2* xp, const double2* xf, double2* x,
-                                                int* accepted) {
+                                                double j_cap, const double2* xp, const double2* xf,
+                                                double2* x, int* accepted) {
   const int s = blockIdx.x;
   __shared__ int acc;
   if (threadIdx.x == 0) {
@@ -235,7 +235,7 @@ __global__ void __launch_bounds__(256) k_choose(const double* jp, const double* 
       a += jp[(long long)s * n_area + k];
       f += jf[(long long)s * n_area + k];
     }
-    acc = (a <= f) ? 1 : 0;  // false for NaN
+    acc = (a <= f && a <= j_cap) ? 1 : 0;  // false for NaN
     accepted[s] = acc;
   }
   __syncthreads();
@@ -280,6 +280,8 @@ struct mase_mlp {
   double *jpred = nullptr, *jflat = nullptr;
   int* d_accepted = nullptr;
   int step = 0;
+  int last_ws = 0;  // snapshots of the last warm start (0: none yet)
+  double j_cap = INFINITY;
   bool have_norm = false;
   std::map<std::pair<int, int>, std::pair<std::pair<GemmDesc*, int4*>, int>> gcache;
 };
@@ -668,13 +670,41 @@ int mase_warm_start(mase_ctx* c, mase_mlp* m, int32_t* accepted) {
   if ((rc = objective_at(c, m->xpred, m->jpred))) return rc;
   if ((rc = objective_at(c, m->xflat, m->jflat))) return rc;
   hipLaunchKernelGGL(k_choose, dim3(S), dim3(256), 0, st, m->jpred, m->jflat, c->plan.n_area, c->plan.n_bus,
-                     m->xpred, m->xflat, c->d.x, m->d_accepted);
+                     m->j_cap, m->xpred, m->xflat, c->d.x, m->d_accepted);
   HIPTRY(hipGetLastError());
+  m->last_ws = S;
   HIPTRY(launch_reset_flags(c->d, st));
   for (int s = 0; s < S; ++s) c->h_active[s] = 1;
   if (accepted) {
     HIPTRY(hipMemcpyAsync(accepted, m->d_accepted, sizeof(int32_t) * S, hipMemcpyDeviceToHost, st));
     HIPTRY(hipStreamSynchronize(st));
+  }
+  return 0;
+}
+
+int mase_mlp_set_accept_cap(mase_mlp* m, double j_cap) {
+  if (!m) return fail(MASE_ERR_ARG, "null mlp");
+  if (std::isnan(j_cap)) return fail(MASE_ERR_ARG, "j_cap is NaN");
+  m->j_cap = j_cap;
+  return 0;
+}
+
+int mase_warm_start_objectives(const mase_mlp* m, double* j_pred, double* j_flat) {
+  if (!m || !j_pred || !j_flat) return fail(MASE_ERR_ARG, "null argument");
+  if (m->last_ws == 0) return fail(MASE_ERR_STATE, "no warm start evaluated yet");
+  const int S = m->last_ws, K = m->ctx->plan.n_area;
+  std::vector<double> jp((size_t)S * K), jf((size_t)S * K);
+  HIPTRY(hipStreamSynchronize(m->ctx->stream));
+  HIPTRY(hipMemcpy(jp.data(), m->jpred, sizeof(double) * jp.size(), hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(jf.data(), m->jflat, sizeof(double) * jf.size(), hipMemcpyDeviceToHost));
+  for (int s = 0; s < S; ++s) {
+    double a = 0.0, f = 0.0;
+    for (int k = 0; k < K; ++k) {
+      a += jp[(size_t)s * K + k];
+      f += jf[(size_t)s * K + k];
+    }
+    j_pred[s] = a;
+    j_flat[s] = f;
   }
   return 0;
 }

@@ -41,7 +41,7 @@ SYMBOLS = (
     "mase_read_gamma_system", "mase_read_step", "mase_profile", "mase_profile_read",
     "mase_mlp_create", "mase_mlp_destroy", "mase_mlp_info", "mase_mlp_io_map", "mase_mlp_set_params",
     "mase_mlp_get_params", "mase_mlp_set_norm", "mase_mlp_loss_grad", "mase_mlp_train_step",
-    "mase_mlp_predict_dev", "mase_warm_start",
+    "mase_mlp_predict_dev", "mase_warm_start", "mase_mlp_set_accept_cap", "mase_warm_start_objectives",
 )
 
 
@@ -117,6 +117,8 @@ def load():
         "mase_mlp_train_step": (ctypes.c_int, [P, P, P, P, ctypes.c_int32, ctypes.c_float, f64p]),
         "mase_mlp_predict_dev": (ctypes.c_int, [P, P, ctypes.c_int32, P, P]),
         "mase_warm_start": (ctypes.c_int, [P, P, i32p]),
+        "mase_mlp_set_accept_cap": (ctypes.c_int, [P, ctypes.c_double]),
+        "mase_warm_start_objectives": (ctypes.c_int, [P, f64p, f64p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -441,6 +443,16 @@ class Mlp:
 
     def mase_mlp_predict_dev(self, z_dev, batch, vm_dev, va_dev):
         _check(self.lib.mase_mlp_predict_dev(self.h, _dptr(z_dev), int(batch), _dptr(vm_dev), _dptr(va_dev)))
+
+    def mase_mlp_set_accept_cap(self, j_cap):
+        _check(self.lib.mase_mlp_set_accept_cap(self.h, float(j_cap)))
+
+    def mase_warm_start_objectives(self):
+        n = self.owner.n_snap
+        jp, jf = np.zeros(n), np.zeros(n)
+        _check(self.lib.mase_warm_start_objectives(self.h, jp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                   jf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return jp, jf
 
 
 def mase_warm_start(ctx: Mase, mlp: Mlp):

@@ -133,6 +133,55 @@ def train(mlp: mase.Mlp, z, vm, va, epochs=30, batch=256, lr=1e-3, lr_final=1e-5
     return history
 
 
+def calibrate_accept_cap(ctx: mase.Mase, mlp: mase.Mlp, grid, sigma, device, n_chain=2,
+                         seed=HELDOUT_SEED, tol=1e-6, max_iter=10):
+    """Acceptance cap on J(pred) from held-out drift chains.
+
+    Gauss-Newton converges from a prediction only as fast as its error allows
+    at the scale of single branches; a prediction can beat flat start on J and
+    still cost iterations.  For every held-out snapshot this measures the
+    iterations from flat start and from the prediction (forced) and J(pred);
+    sorted by J(pred), the cap is the J that ends the prefix with the largest
+    total saving.  With no saving anywhere the cap is -inf (flat start
+    everywhere).  Sets the cap on mlp and returns (cap, summary).
+    """
+    S = ctx.n_snap
+    vm, va, eps = synth.make_chains(grid, n_chain, S, seed)
+    va = va - va[:, [grid.slack]]
+    pv = torch.empty((S, ctx.n_bus), dtype=torch.float64, device=device)
+    pa = torch.empty_like(pv)
+    mlp.mase_mlp_set_accept_cap(float("inf"))
+    jp_all, it_flat, it_pred, conv_pred = [], [], [], []
+    for b0 in range(0, vm.shape[0], S):
+        idx = np.arange(b0, b0 + S)
+        z = measurements_dev(ctx, vm[idx], va[idx], eps[idx], sigma, device)
+        ctx.mase_set_measurements_dev(z)
+        mase.mase_warm_start(ctx, mlp)
+        jp, _ = mlp.mase_warm_start_objectives()
+        ctx.mase_set_state_dev(None, None)
+        itf, _ = ctx.mase_solve(tol, max_iter)
+        mlp.mase_mlp_predict_dev(z, S, pv, pa)
+        torch.cuda.synchronize()
+        ctx.mase_set_state_dev(pv, pa)
+        itp, cp = ctx.mase_solve(tol, max_iter)
+        jp_all.append(jp)
+        it_flat.append(itf)
+        it_pred.append(np.where(cp, itp, max_iter + 1))
+        conv_pred.append(cp)
+    jp, itf, itp = np.concatenate(jp_all), np.concatenate(it_flat), np.concatenate(it_pred)
+    order = np.argsort(jp, kind="stable")
+    gain = np.cumsum((itf - itp)[order].astype(np.float64))
+    best = int(np.argmax(gain)) if gain.size else -1
+    cap = float(jp[order][best]) if best >= 0 and gain[best] > 0 else float("-inf")
+    mlp.mase_mlp_set_accept_cap(cap)
+    summary = {"snapshots": int(jp.size), "seed": seed, "mean_iters_flat": float(itf.mean()),
+               "mean_iters_forced_prediction": float(itp.mean()),
+               "forced_prediction_converged": int(np.concatenate(conv_pred).sum()),
+               "j_cap": cap, "accepted_under_cap": int((jp <= cap).sum()),
+               "iterations_saved": float(gain[best]) if best >= 0 and gain[best] > 0 else 0.0}
+    return cap, summary
+
+
 def save(path, mlp: mase.Mlp, norm):
     z_mean, y_mean, y_std = norm
     np.savez(path, params=mlp.mase_mlp_get_params(), z_mean=z_mean, y_mean=y_mean, y_std=y_std,

@@ -136,6 +136,19 @@ def test_warm_start_acceptance_rule_and_fallback():
     J_pred = ctx.mase_objective()
     acc = mase.mase_warm_start(ctx, M)
     np.testing.assert_array_equal(acc, J_pred <= J_flat)
+    # the objectives the decision used, and the acceptance cap on J(pred)
+    jp, jf = M.mase_warm_start_objectives()
+    np.testing.assert_allclose(jp, J_pred, rtol=1e-12)
+    np.testing.assert_allclose(jf, J_flat, rtol=1e-12)
+    cap = float(np.median(jp))
+    M.mase_mlp_set_accept_cap(cap)
+    np.testing.assert_array_equal(mase.mase_warm_start(ctx, M), (jp <= jf) & (jp <= cap))
+    M.mase_mlp_set_accept_cap(float("-inf"))
+    assert not mase.mase_warm_start(ctx, M).any()
+    with pytest.raises(mase.MaseError):
+        M.mase_mlp_set_accept_cap(float("nan"))
+    M.mase_mlp_set_accept_cap(float("inf"))
+    acc = mase.mase_warm_start(ctx, M)
     it_warm, conv_w = ctx.mase_solve(1e-6, 10)
     assert conv_f.all() and conv_w.all()
     say("  accepted", int(acc.sum()), "of", S, "| mean GN iterations flat", it_flat.mean(),
