@@ -98,6 +98,8 @@ def main():
     ap.add_argument("--warm-chains", type=int, default=313,
                     help="64-snapshot drift chains solved to train the warm start (0: flat start only)")
     ap.add_argument("--warm-epochs", type=int, default=20)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first copy a buffer of this many MiB 3 times (scale reference for HBM counters)")
     ap.add_argument("--cpu-leg", type=float, default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_leg is not None:
@@ -114,6 +116,15 @@ def main():
     from paper_2604_23175_amd import mase
 
     dev = torch.device("cuda:0")
+    if args.copy_probe_mib > 0:
+        # a plain device copy of known size: reads and writes copy_probe_mib MiB
+        n = args.copy_probe_mib << 17
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     g, t, a, s, vm_true, va_true, eps = make_inputs(N_SNAP)
     ctx = mase.Mase.from_grid(g, t, a, s, N_SNAP)
     # synthetic measurements z = h(x_true) + sigma * eps, built on the device
@@ -186,6 +197,21 @@ def main():
     # the batched flat-start path on the same batch
     fdt, f_iters, f_conv = timed(ctx, args.steps, False)
     vm_b, va_b = vm_out.cpu().numpy(), va_out.cpu().numpy()
+    # the same flat-start steps with host buffers at the boundary: measurements
+    # uploaded and states downloaded through PCIe inside the timed region
+    z_host = z.cpu().numpy()
+    ctx.mase_set_measurements(z_host)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.mase_set_measurements(z_host)
+        ctx.mase_set_state()
+        ctx.mase_solve(TOL, MAX_ITER)
+        ctx.mase_state()
+    torch.cuda.synchronize()
+    hdt = time.perf_counter() - t0
+    ctx.mase_set_measurements_dev(z)
+    torch.cuda.synchronize()
     # the headline steps again with a HIP event pair around every stage kernel
     # (direct launches: event pairs inside a graph cannot be timed)
     ctx.mase_profile(True)
@@ -261,6 +287,10 @@ def main():
         "batched_flat": {"value": N_SNAP * args.steps / fdt, "unit": "snapshots/s",
                          "ms_per_step": 1e3 * fdt / args.steps, "mean_iters": f_iters / (N_SNAP * args.steps),
                          "gn_iters_per_s": f_iters / fdt, "all_converged": f_conv},
+        "batched_flat_host_buffers": {"value": N_SNAP * args.steps / hdt, "unit": "snapshots/s",
+                                      "ms_per_step": 1e3 * hdt / args.steps,
+                                      "note": "z uploaded and states downloaded (pageable host memory) "
+                                              "inside the timed region"},
         "profiled_pass": {"value": N_SNAP * args.steps / pdt_prof, "unit": "snapshots/s",
                           "note": "same steps, kernels launched directly with HIP events around each"},
         "mean_iters": tot_iters / (N_SNAP * args.steps),

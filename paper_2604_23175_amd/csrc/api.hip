@@ -64,6 +64,13 @@ int upload(mase_ctx* c, const std::vector<H>& v, const D** out) {
   return 0;
 }
 
+// Sparse part of the boundary system: supernodal when its panels fit in LDS,
+// else the level-scheduled engine.
+hipError_t launch_gamma_sparse(const mase_ctx* c, int s0, int ns, hipStream_t st) {
+  if (c->gamma_snode) return launch_gamma_snode(c->d, s0, ns, c->lds_sn, st);
+  return launch_eliminate(c->d, c->plan.n_area, 1, s0, ns, c->lds_el_gamma, st);
+}
+
 void append_rebased(std::vector<int32_t>& dst, const std::vector<int32_t>& src, int32_t base) {
   for (int32_t v : src) dst.push_back(v + base);
 }
@@ -111,7 +118,8 @@ int upload_plan(mase_ctx* c) {
   std::vector<I4> rowrec;
   std::vector<double> br_g, br_bs, br_hb;
   std::vector<I4> slot;
-  std::vector<I2> scon, rslot, rcon;
+  std::vector<I2> rslot;
+  std::vector<I4> scon, rcon;  // contributions with their row record inline
   size_t lds = 0;
   for (int k = 0; k < K; ++k) {
     const AreaTemplates& t = p.tpl[k];
@@ -137,11 +145,13 @@ int upload_plan(mase_ctx* c) {
     a.slot = (int32_t)slot.size();
     for (const I4& s : t.slot)
       slot.push_back({s.x, s.y, s.z + (int32_t)scon.size(), s.w + (int32_t)scon.size()});
-    scon.insert(scon.end(), t.scon.begin(), t.scon.end());
+    for (const I2& cc : t.scon)
+      scon.push_back({t.row_type[cc.x], t.row_loc[cc.x], t.row_meas[cc.x], cc.y});
     a.rslot = (int32_t)rslot.size();
     for (const I2& s : t.rslot)
       rslot.push_back({s.x + (int32_t)rcon.size(), s.y + (int32_t)rcon.size()});
-    rcon.insert(rcon.end(), t.rcon.begin(), t.rcon.end());
+    for (const I2& cc : t.rcon)
+      rcon.push_back({t.row_type[cc.x], t.row_loc[cc.x], t.row_meas[cc.x], cc.y});
     a.tail_src = p.tail_src_ptr[k];
     a.slack_local = p.local_of_bus[k][p.slack];
     am[k] = a;
@@ -171,6 +181,13 @@ int upload_plan(mase_ctx* c) {
     c->dense_panel = pan + 8192 <= (size_t)maxlds && !(env && env[0] == '0');
     if (c->dense_panel && pan > 65536) HIPTRY(allow_dense_lds(pan));
   }
+  // supernodal boundary elimination (MASE_GAMMA_SNODE=0 selects the level engine)
+  {
+    const char* env = getenv("MASE_GAMMA_SNODE");
+    c->lds_sn = (size_t)p.sys[K].sn_lds_bytes;
+    c->gamma_snode = !p.sys[K].sn.empty() && c->lds_sn + 4096 <= (size_t)maxlds && !(env && env[0] == '0');
+    if (c->gamma_snode && c->lds_sn > 65536) HIPTRY(allow_gamma_snode_lds(c->lds_sn));
+  }
   c->hsys = sm;
   c->nslot_g = (int)p.g_slot.size();
 
@@ -187,6 +204,11 @@ int upload_plan(mase_ctx* c) {
   UP(cd_ptr, cd_ptr); UP(up_ptr, up_ptr); UP(rb_ptr, rb_ptr); UP(bs_ptr, bs_ptr);
   UP(cd_items, cd_items); UP(up_tgt, up_tgt); UP(up_con, up_con);
   UP(rb_tgt, rb_tgt); UP(rb_con, rb_con); UP(bs_items, bs_items); UP(bs_con, bs_con);
+  {
+    const SysPlan& gs = p.sys[K];
+    d.n_sn = (int32_t)gs.sn.size();
+    UP(sn, gs.sn); UP(sn2, gs.sn2); UP(sn_rows, gs.sn_rows); UP(sn_tgt, gs.sn_tgt);
+  }
   UP(g_slot, p.g_slot); UP(g_con, p.g_con); UP(g_rslot, p.g_rslot); UP(g_rcon, p.g_rcon);
   UP(tail_src, p.tail_src); UP(bus_dx_src, p.bus_dx_src);
 #undef UP
@@ -269,7 +291,7 @@ int launch_batched_iteration(mase_ctx* c, hipStream_t st) {
     }
     if (g.ne > 0) {
       StageMark m(c, st, MASE_STAGE_GAMMA_SPARSE);
-      HIPTRY(launch_eliminate(d, K, 1, 0, S, c->lds_el_gamma, st));
+      HIPTRY(launch_gamma_sparse(c, 0, S, st));
     }
     {
       StageMark m(c, st, MASE_STAGE_GAMMA_DENSE);
@@ -327,7 +349,7 @@ int launch_plain_iteration(mase_ctx* c, int s) {
   const SysMeta& g = gsys(c);
   if (g.nn > 0) {
     HIPTRY(launch_gamma_gather(d, s, 1, c->nslot_g, g.nn, st));
-    if (g.ne > 0) HIPTRY(launch_eliminate(d, K, 1, s, 1, c->lds_el_gamma, st));
+    if (g.ne > 0) HIPTRY(launch_gamma_sparse(c, s, 1, st));
     HIPTRY(launch_dense_chol(d, s, 1, g.ld, c->dense_panel, st));
     if (g.ne > 0) HIPTRY(launch_backsolve(d, K, 1, s, 1, st));
   }
@@ -865,7 +887,7 @@ int mase_stage_gamma_solve(mase_ctx* c) {
   const SysMeta& g = gsys(c);
   const int K = c->plan.n_area, S = c->plan.n_snap;
   if (g.nn > 0) {
-    if (g.ne > 0) HIPTRY(launch_eliminate(c->d, K, 1, 0, S, c->lds_el_gamma, c->stream));
+    if (g.ne > 0) HIPTRY(launch_gamma_sparse(c, 0, S, c->stream));
     HIPTRY(launch_dense_chol(c->d, 0, S, g.ld, c->dense_panel, c->stream));
     if (g.ne > 0) HIPTRY(launch_backsolve(c->d, K, 1, 0, S, c->stream));
   }

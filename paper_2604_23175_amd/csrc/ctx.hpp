@@ -29,6 +29,8 @@ struct mase_ctx {
   bool br_lds = false;
   size_t lds_el_area = 0, lds_el_gamma = 0;  // elimination staging LDS bytes
   bool dense_panel = false;                   // dense block panels staged in LDS
+  bool gamma_snode = false;                   // supernodal boundary elimination
+  size_t lds_sn = 0;                          // its LDS bytes
   int nslot_g = 0;
   bool have_z = false;
   hipGraph_t graph = nullptr;

@@ -43,9 +43,9 @@ struct Dev {
   const int32_t *row_type, *row_loc, *row_meas;
   const int4* rowrec;  // per area row: {type, loc, meas, 0}
   const int4* slot;
-  const int2* scon;
+  const int4* scon;   // per G-slot contribution: {type, loc, meas, role_p | role_q << 16}
   const int2* rslot;
-  const int2* rcon;
+  const int4* rcon;   // per rhs contribution: {type, loc, meas, role}
   const int32_t *cd_ptr, *up_ptr, *rb_ptr, *bs_ptr;
   const int4* cd_items;
   const int4* up_tgt;
@@ -54,6 +54,12 @@ struct Dev {
   const int2* rb_con;
   const int4* bs_items;
   const int2* bs_con;
+  // supernodes of the boundary system (the plan's sn, sn2, sn_rows, sn_tgt)
+  int32_t n_sn;
+  const int4* sn;
+  const int4* sn2;
+  const int32_t* sn_rows;
+  const int32_t* sn_tgt;
   const int4* g_slot;
   const int4* g_con;
   const int2* g_rslot;

@@ -146,6 +146,84 @@ __device__ inline double block_sum(double v, double* red) {
   return t;
 }
 
+// Value of v held by lane src (uniform across the wave) via the scalar unit.
+__device__ inline double bcast_lane(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Cholesky of the 16x16 diagonal block at (cb, cb) of the column-major LDS
+// matrix P (pitch ldp) by one wave, the forward solve of y[cb .. cb+15], and
+// the inverse of the factor: lane r (mod 16) holds row r; each finished column
+// of L is shared through colbuf (16 doubles of LDS; a wave's LDS accesses
+// complete in order).  L goes back to P; Linv (row-major, pitch 17, zero
+// above the diagonal) receives L^-1, which turns the solves against L below
+// the block into products on MFMA.  A non-positive pivot is replaced by 1 and
+// reported by returning false.
+__device__ __attribute__((always_inline)) inline bool wave_chol16_inv(double* P, int ldp, int cb, double* y, double* colbuf,
+                                       double* Linv) {
+  const int lane = threadIdx.x & 63;
+  int rr = lane & 15;
+  asm volatile("" : "+v"(rr));  // per-lane predicates stay here, not hoisted into the caller
+  double a[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) a[m] = (m <= rr) ? P[(cb + m) * ldp + cb + rr] : 0.0;
+  double yr = y[cb + rr];
+  double dinv = 1.0;
+  bool ok = true;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const double piv = bcast_lane(a[c], c);
+    double sd = 1.0;
+    if (piv > 0.0) sd = sqrt(piv);
+    else ok = false;
+    const double inv = 1.0 / sd;
+    if (rr == c) {
+      a[c] = sd;
+      dinv = inv;
+      yr *= inv;
+    } else if (rr > c) {
+      a[c] *= inv;
+    }
+    const double yc = bcast_lane(yr, c);
+    if (rr > c) yr -= a[c] * yc;
+    if (c < 15) {
+      if (lane < 16) colbuf[rr] = a[c];
+      double col[16];
+#pragma unroll
+      for (int m = c + 1; m < 16; ++m) col[m] = colbuf[m];
+#pragma unroll
+      for (int m = c + 1; m < 16; ++m)
+        if (rr >= m) a[m] -= a[c] * col[m];
+    }
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m)
+      if (m <= rr) P[(cb + m) * ldp + cb + rr] = a[m];
+    y[cb + rr] = yr;
+    colbuf[rr] = dinv;
+  }
+  // column j = rr of L^-1: z_j = 1 / L_jj, z_i = -(sum_{j <= m < i} L_im z_m) / L_ii
+  double z[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int m = 0; m < i; ++m)
+      if (m >= rr) t += P[(cb + m) * ldp + cb + i] * z[m];
+    const double di = colbuf[i];
+    z[i] = (i == rr) ? di : (i > rr) ? -t * di : 0.0;
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) Linv[i * 17 + rr] = z[i];
+  }
+  return ok;
+}
+
 __device__ inline double nanmax(double m, double v) { return (v > m || v != v) ? v : m; }
 
 __device__ inline double block_max(double v, double* red) {
@@ -183,8 +261,12 @@ __device__ inline bool chol2(double a00, double a10, double a11, double& l00, do
 // order and each sums its precomputed, fixed-order contribution list, so the
 // writes are contiguous and the sum is deterministic.
 // ---------------------------------------------------------------------------
+// 16 waves per workgroup: the area's LDS staging limits a CU to one or two
+// workgroups, and the gathers are latency-bound, so waves are what hide it.
+constexpr int ASM_NT = 1024;
+
 template <bool BR_LDS>
-__global__ void __launch_bounds__(512) k_assemble(Dev d, int a0, int na, int s0, int ns, int mode) {
+__global__ void __launch_bounds__(ASM_NT) k_assemble(Dev d, int a0, int na, int s0, int ns, int mode) {
   int ai, s;
   area_snap_of_block(blockIdx.x, na, ns, ai, s);
   s += s0;
@@ -265,12 +347,23 @@ __global__ void __launch_bounds__(512) k_assemble(Dev d, int a0, int na, int s0,
   for (int i = tid; i < am.nslot; i += nt) {
     const int4 sl = d.slot[am.slot + i];
     double c00 = 0, c10 = 0, c01 = 0, c11 = 0;
+    // two-stage prefetch: the record of contribution c+2 and the weight of
+    // c+1 are in flight while c is evaluated
+    int4 r0 = make_int4(0, 0, 0, 0), r1 = r0;
+    double w0 = 0.0;
+    if (sl.z < sl.w) {
+      r0 = d.scon[sl.z];
+      w0 = d.w[r0.z];
+    }
+    if (sl.z + 1 < sl.w) r1 = d.scon[sl.z + 1];
     for (int c = sl.z; c < sl.w; ++c) {
-      const int2 cc = d.scon[c];
-      const int4 rec = d.rowrec[am.row + cc.x];
-      const double wr = d.w[rec.z];
+      const int4 cr = r0;
+      const double wr = w0;
+      r0 = r1;
+      if (c + 1 < sl.w) w0 = d.w[r1.z];
+      if (c + 2 < sl.w) r1 = d.scon[c + 2];
       double h, pt, pv, qt, qv;
-      X.eval2(rec, cc.y & 0xFFFF, (cc.y >> 16) & 0xFFFF, h, pt, pv, qt, qv);
+      X.eval2(cr, cr.w & 0xFFFF, (cr.w >> 16) & 0xFFFF, h, pt, pv, qt, qv);
       pt *= wr;
       pv *= wr;
       c00 += pt * qt;
@@ -294,11 +387,10 @@ __global__ void __launch_bounds__(512) k_assemble(Dev d, int a0, int na, int s0,
     const int2 rs = d.rslot[am.rslot + v];
     double b0 = 0, b1 = 0;
     for (int c = rs.x; c < rs.y; ++c) {
-      const int2 cc = d.rcon[c];
-      const int4 rec = d.rowrec[am.row + cc.x];
+      const int4 cr = d.rcon[c];
       double h, pt, pv, qt, qv;
-      X.eval2(rec, cc.y, cc.y, h, pt, pv, qt, qv);
-      const double wres = d.w[rec.z] * (zs[rec.z] - h);
+      X.eval2(cr, cr.w, cr.w, h, pt, pv, qt, qv);
+      const double wres = d.w[cr.z] * (zs[cr.z] - h);
       b0 += pt * wres;
       b1 += pv * wres;
     }
@@ -333,10 +425,34 @@ __global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int
   double* lst = reinterpret_cast<double*>(lstage2);
   const int tid = threadIdx.x;
   bool bad = false;
+  // UB targets per thread and pass: their records, then their current
+  // values, are loaded together so the global round trips overlap.  The
+  // records of a level's first pass and of the next level's first column
+  // item are plan data: they are fetched a phase early, off the critical path.
+  constexpr int UB = (NT >= 1024) ? 4 : 2;
+  const int32_t* cdp = d.cd_ptr + sm.cd_ptr;
+  const int32_t* upp = d.up_ptr + sm.up_ptr;
+  const int32_t* rbp = d.rb_ptr + sm.rb_ptr;
+  int nc0 = 0, nc1 = 0;
+  int4 cpre = make_int4(0, 0, 0, 0);
+  if (sm.nlev > 0) {
+    nc0 = cdp[0];
+    nc1 = cdp[1];
+    if (nc0 + tid < nc1) cpre = d.cd_items[nc0 + tid];
+  }
   for (int lev = 0; lev < sm.nlev; ++lev) {
-    const int c0 = d.cd_ptr[sm.cd_ptr + lev], c1 = d.cd_ptr[sm.cd_ptr + lev + 1];
+    const int c0 = nc0, c1 = nc1;
+    const int u0 = upp[lev], u1 = upp[lev + 1];
+    const int r0 = rbp[lev], r1 = rbp[lev + 1];
+    int4 tpre[UB];
+#pragma unroll
+    for (int q = 0; q < UB; ++q) {
+      const int it = u0 + tid + q * NT;
+      tpre[q] = (it < u1) ? d.up_tgt[it] : make_int4(-1, 0, 0, 0);
+    }
+    const int4 rpre = (r0 + tid < r1) ? d.rb_tgt[r0 + tid] : make_int4(0, 0, 0, 0);
     for (int it = c0 + tid; it < c1; it += NT) {
-      const int4 c = d.cd_items[it];
+      const int4 c = (it == c0 + tid) ? cpre : d.cd_items[it];
       const double* D = vals + c.x;
       double l00, l10, l11;
       if (!chol2(D[0], D[1], D[3], l00, l10, l11)) { bad = true; l00 = l11 = 1.0; l10 = 0.0; }
@@ -360,36 +476,60 @@ __global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int
       }
     }
     __syncthreads();
-    const int u0 = d.up_ptr[sm.up_ptr + lev], u1 = d.up_ptr[sm.up_ptr + lev + 1];
-    for (int it = u0 + tid; it < u1; it += NT) {
-      const int4 t = d.up_tgt[it];
-      double a00 = 0, a10 = 0, a01 = 0, a11 = 0;
-      const bool single = (t.y & UP_SINGLE_FLAG) != 0;
-      const int stride = t.y & ~UP_SINGLE_FLAG;
-      const int cb = single ? 0 : t.z, ce = single ? 1 : t.w;
-      bool sym = false;
-      for (int c = cb; c < ce; ++c) {
-        const int2 u = single ? make_int2(t.z, t.w) : d.up_con[c];
-        const double2 L0 = *reinterpret_cast<const double2*>(lst + u.x);
-        const double2 L1 = *reinterpret_cast<const double2*>(lst + u.x + 2);
-        const double2 P0 = *reinterpret_cast<const double2*>(lst + u.y);
-        const double2 P1 = *reinterpret_cast<const double2*>(lst + u.y + 2);
-        a00 += L0.x * P0.x + L1.x * P1.x;
-        a10 += L0.y * P0.x + L1.y * P1.x;
-        a01 += L0.x * P0.y + L1.x * P1.y;
-        a11 += L0.y * P0.y + L1.y * P1.y;
-        sym = (u.x == u.y);
-      }
-      if (sym) a01 = a10;
-      double* C = vals + t.x;
-      C[0] -= a00;
-      C[1] -= a10;
-      C[stride] -= a01;
-      C[stride + 1] -= a11;
+    if (lev + 1 < sm.nlev) {
+      nc0 = c1;
+      nc1 = cdp[lev + 2];
+      if (nc0 + tid < nc1) cpre = d.cd_items[nc0 + tid];
     }
-    const int r0 = d.rb_ptr[sm.rb_ptr + lev], r1 = d.rb_ptr[sm.rb_ptr + lev + 1];
+    for (int it0 = u0 + tid; it0 < u1; it0 += NT * UB) {
+      int4 t[UB];
+      double c00[UB], c10[UB], c01[UB], c11[UB];
+#pragma unroll
+      for (int q = 0; q < UB; ++q) {
+        const int it = it0 + q * NT;
+        if (it0 == u0 + tid) t[q] = tpre[q];
+        else t[q] = (it < u1) ? d.up_tgt[it] : make_int4(-1, 0, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < UB; ++q) {
+        if (t[q].x < 0) continue;
+        const int stride = t[q].y & ~UP_SINGLE_FLAG;
+        const double* C = vals + t[q].x;
+        c00[q] = C[0];
+        c10[q] = C[1];
+        c01[q] = C[stride];
+        c11[q] = C[stride + 1];
+      }
+#pragma unroll
+      for (int q = 0; q < UB; ++q) {
+        if (t[q].x < 0) continue;
+        double a00 = 0, a10 = 0, a01 = 0, a11 = 0;
+        const bool single = (t[q].y & UP_SINGLE_FLAG) != 0;
+        const int stride = t[q].y & ~UP_SINGLE_FLAG;
+        const int cb = single ? 0 : t[q].z, ce = single ? 1 : t[q].w;
+        bool sym = false;
+        for (int c = cb; c < ce; ++c) {
+          const int2 u = single ? make_int2(t[q].z, t[q].w) : d.up_con[c];
+          const double2 L0 = *reinterpret_cast<const double2*>(lst + u.x);
+          const double2 L1 = *reinterpret_cast<const double2*>(lst + u.x + 2);
+          const double2 P0 = *reinterpret_cast<const double2*>(lst + u.y);
+          const double2 P1 = *reinterpret_cast<const double2*>(lst + u.y + 2);
+          a00 += L0.x * P0.x + L1.x * P1.x;
+          a10 += L0.y * P0.x + L1.y * P1.x;
+          a01 += L0.x * P0.y + L1.x * P1.y;
+          a11 += L0.y * P0.y + L1.y * P1.y;
+          sym = (u.x == u.y);
+        }
+        if (sym) a01 = a10;
+        double* C = vals + t[q].x;
+        C[0] = c00[q] - a00;
+        C[1] = c10[q] - a10;
+        C[stride] = c01[q] - a01;
+        C[stride + 1] = c11[q] - a11;
+      }
+    }
     for (int it = r0 + tid; it < r1; it += NT) {
-      const int4 t = d.rb_tgt[it];
+      const int4 t = (it == r0 + tid) ? rpre : d.rb_tgt[it];
       double b0 = 0, b1 = 0;
       for (int c = t.y; c < t.z; ++c) {
         const int2 u = d.rb_con[c];
@@ -482,11 +622,14 @@ __global__ void __launch_bounds__(DENSE_NT) k_dense_chol(Dev d, int s0) {
   double* b = d.rhs + (int64_t)s * d.rstride + g.rhs_off + 2 * g.ne;
   extern __shared__ double bl[];  // [n] rhs, then solution; then the staged panel
   double* Lp = bl + n;            // [n - 16][PANEL_PITCH]: rows below the diagonal block
-  __shared__ double Lk[16 * 17];
+  __shared__ double Dk[16 * 17];    // diagonal block, column-major, pitch 17
+  __shared__ double Linv[16 * 17];  // its inverse factor, row-major
+  __shared__ double colbuf[16];
   __shared__ double part[16 * 16];
   __shared__ int bad;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+  const int li = lane & 15, lk = lane >> 4;
   if (tid == 0) bad = 0;
   for (int i = tid; i < n; i += nt) bl[i] = (i < nlive) ? b[i] : 0.0;
   // identity padding (lower triangle of the padded rows / columns)
@@ -496,86 +639,92 @@ __global__ void __launch_bounds__(DENSE_NT) k_dense_chol(Dev d, int s0) {
   const int nb = n / 16;
   for (int k = 0; k < nb; ++k) {
     const int c0 = 16 * k;
+    // diagonal block to LDS; wave 0 factors it, solves y and inverts L_kk
+    for (int i = tid; i < 256; i += nt) {
+      const int r = i & 15, m = i >> 4;
+      Dk[m * 17 + r] = (r >= m) ? A[(int64_t)(c0 + m) * n + c0 + r] : 0.0;
+    }
+    __syncthreads();
     if (wv == 0) {
-      // lane r (mod 16) holds row r of the diagonal block
-      const int r = lane & 15;
-      double a[16];
+      const bool ok = wave_chol16_inv(Dk, 17, 0, bl + c0, colbuf, Linv);
+      if (!ok && lane == 0) bad = 1;
+    }
+    __syncthreads();
+    for (int i = tid; i < 256; i += nt) {
+      const int r = i & 15, m = i >> 4;
+      if (r >= m) A[(int64_t)(c0 + m) * n + c0 + r] = Dk[m * 17 + r];
+    }
+    // rows below the block: X^T = L_kk^-1 A^T on MFMA, one 16-row tile per
+    // wave; lane li holds row ri + li, so the accesses run down columns
+    for (int t = wv; t < nb - k - 1; t += nw) {
+      const int ri = c0 + 16 + 16 * t;
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int m = 0; m < 16; ++m) a[m] = (m <= r) ? A[(int64_t)(c0 + m) * n + c0 + r] : 0.0;
-      double y = bl[c0 + r];
-      bool badl = false;
-#pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        const double piv = __shfl(a[c], c, 64);
-        double dd;
-        if (!(piv > 0.0)) { badl = true; dd = 1.0; }
-        else dd = sqrt(piv);
-        if (r == c) a[c] = dd;
-        else if (r > c) a[c] /= dd;
-        if (r == c) y /= dd;
-        const double yc = __shfl(y, c, 64);
-        if (r > c) y -= a[c] * yc;
-#pragma unroll
-        for (int m = c + 1; m < 16; ++m) {
-          const double lmc = __shfl(a[c], m, 64);
-          if (r >= m) a[m] -= a[c] * lmc;
-        }
+      for (int e = 0; e < 4; ++e) {
+        const double a = Linv[li * 17 + 4 * e + lk];
+        const double bb = A[(int64_t)(c0 + 4 * e + lk) * n + ri + li];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
       }
-      if (lane < 16) {
 #pragma unroll
-        for (int m = 0; m < 16; ++m)
-          if (m <= r) {
-            Lk[r * 17 + m] = a[m];
-            A[(int64_t)(c0 + m) * n + c0 + r] = a[m];
-          }
-        bl[c0 + r] = y;
-        if (badl && lane == 0) bad = 1;
+      for (int e = 0; e < 4; ++e) {
+        A[(int64_t)(c0 + 4 * e + lk) * n + ri + li] = acc[e];
+        if (LDS_PANEL) Lp[(ri + li - c0 - 16) * PANEL_PITCH + 4 * e + lk] = acc[e];
       }
     }
     __syncthreads();
-    // panel: X L_kk^T = A_ik for every row below the block; rhs update
     for (int row = c0 + 16 + tid; row < n; row += nt) {
-      double x[16];
       double acc = 0.0;
 #pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        double a = A[(int64_t)(c0 + c) * n + row];
-#pragma unroll
-        for (int m = 0; m < c; ++m) a -= x[m] * Lk[c * 17 + m];
-        x[c] = a / Lk[c * 17 + c];
-        A[(int64_t)(c0 + c) * n + row] = x[c];
-        if (LDS_PANEL) Lp[(row - c0 - 16) * PANEL_PITCH + c] = x[c];
-        acc += x[c] * bl[c0 + c];
-      }
+      for (int c = 0; c < 16; ++c)
+        acc += (LDS_PANEL ? Lp[(row - c0 - 16) * PANEL_PITCH + c] : A[(int64_t)(c0 + c) * n + row]) * bl[c0 + c];
       bl[row] -= acc;
     }
-    __syncthreads();
     // trailing update on MFMA: tiles (I, J), k < J <= I, one tile per wave.
     // v_mfma_f64_16x16x4f64 operands: lane l holds A[l%16][l/16] and
     // B[l/16][l%16]; accumulator element q of lane l is D[4q + l/16][l%16].
+    // Each wave takes TB tiles per pass: their accumulators are loaded
+    // together so the global round trips overlap.
     const int m = nb - k - 1;
     const int ntile = m * (m + 1) / 2;
-    for (int t = wv; t < ntile; t += nw) {
-      int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-      while (I * (I + 1) / 2 > t) --I;
-      while ((I + 1) * (I + 2) / 2 <= t) ++I;
-      const int J = t - I * (I + 1) / 2;
-      const int ri = 16 * (k + 1 + I), rj = 16 * (k + 1 + J);
-      const int li = lane & 15, lk = lane >> 4;
-      d4 acc;
-      for (int q = 0; q < 4; ++q) acc[q] = A[(int64_t)(rj + li) * n + ri + 4 * q + lk];
-      for (int q = 0; q < 4; ++q) {
-        double a, bb;
-        if (LDS_PANEL) {
-          a = -Lp[(ri - c0 - 16 + li) * PANEL_PITCH + 4 * q + lk];
-          bb = Lp[(rj - c0 - 16 + li) * PANEL_PITCH + 4 * q + lk];
-        } else {
-          a = -A[(int64_t)(c0 + 4 * q + lk) * n + ri + li];
-          bb = A[(int64_t)(c0 + 4 * q + lk) * n + rj + li];
+    constexpr int TB = 4;
+    for (int t0 = wv; t0 < ntile; t0 += nw * TB) {
+      int ri[TB], rj[TB];
+      d4 acc[TB];
+#pragma unroll
+      for (int b = 0; b < TB; ++b) {
+        const int t = t0 + b * nw;
+        ri[b] = -1;
+        if (t < ntile) {
+          int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+          while (I * (I + 1) / 2 > t) --I;
+          while ((I + 1) * (I + 2) / 2 <= t) ++I;
+          const int J = t - I * (I + 1) / 2;
+          ri[b] = 16 * (k + 1 + I);
+          rj[b] = 16 * (k + 1 + J);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[b][q] = A[(int64_t)(rj[b] + 4 * q + lk) * n + ri[b] + li];
         }
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
       }
-      for (int q = 0; q < 4; ++q) A[(int64_t)(rj + li) * n + ri + 4 * q + lk] = acc[q];
+#pragma unroll
+      for (int b = 0; b < TB; ++b) {
+        if (ri[b] < 0) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          double a, bb;
+          // computed transposed (rows J x rows I): lane li holds row ri + li,
+          // so the accumulator's global accesses run down a column
+          if (LDS_PANEL) {
+            a = -Lp[(rj[b] - c0 - 16 + li) * PANEL_PITCH + 4 * q + lk];
+            bb = Lp[(ri[b] - c0 - 16 + li) * PANEL_PITCH + 4 * q + lk];
+          } else {
+            a = -A[(int64_t)(c0 + 4 * q + lk) * n + rj[b] + li];
+            bb = A[(int64_t)(c0 + 4 * q + lk) * n + ri[b] + li];
+          }
+          acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc[b], 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) A[(int64_t)(rj[b] + 4 * q + lk) * n + ri[b] + li] = acc[b][q];
+      }
     }
     __syncthreads();
   }
@@ -583,7 +732,7 @@ __global__ void __launch_bounds__(DENSE_NT) k_dense_chol(Dev d, int s0) {
   for (int k = nb - 1; k >= 0; --k) {
     const int c0 = 16 * k;
     if (tid < 256) {
-      const int c = tid & 15, pp = tid >> 4;
+      const int c = tid >> 4, pp = tid & 15;  // 16 lanes read 16 consecutive rows of column c
       double acc = 0.0;
       for (int r = c0 + 16 + pp; r < n; r += 16) acc += A[(int64_t)(c0 + c) * n + r] * bl[r];
       part[pp * 16 + c] = acc;
@@ -600,7 +749,7 @@ __global__ void __launch_bounds__(DENSE_NT) k_dense_chol(Dev d, int s0) {
 #pragma unroll
       for (int c = 15; c >= 0; --c) {
         if (r == c) t /= col[c];
-        const double xc = __shfl(t, c, 64);
+        const double xc = bcast_lane(t, c);
         if (r < c) t -= col[c] * xc;
       }
       if (lane < 16) bl[c0 + r] = t;
@@ -608,6 +757,220 @@ __global__ void __launch_bounds__(DENSE_NT) k_dense_chol(Dev d, int s0) {
     __syncthreads();
   }
   for (int i = tid; i < nlive; i += nt) b[i] = bl[i];
+  if (tid == 0 && bad) d.status[(int64_t)s * (d.n_area + 1) + d.n_area] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// Stage 3b (sparse part, supernodal): elimination of the boundary system's
+// leading buses one supernode at a time (one workgroup per snapshot).  A
+// supernode is a run of buses whose factor columns share the row list R below
+// their diagonal block, so the run is one dense panel: its 2w own variables
+// (padded to a multiple of 16 with an identity) and the 2r variables of R.
+// Per supernode: (1) the panel's columns, which are contiguous in the packed
+// storage, its rhs and its target offsets are staged in LDS; (2) blocked
+// Cholesky of the panel in 16-column steps (wave 0 factors the 16x16
+// diagonal block in registers, every thread solves one row of the blocks
+// below, the remaining panel columns are updated on FP64 MFMA) together with
+// the forward solve of the rhs; (3) the Schur update L_R L_R^T of the R x R
+// blocks, on FP64 MFMA, is subtracted from the packed storage, whose blocks
+// (R[a], R[c]) the plan lists; (4) the factor is written back.  Diagonal 2x2
+// blocks are written as L_jj L_jj^T, the fully updated pivot block, which is
+// the form the level-scheduled back substitution reads (Eq. 8-11).
+// ---------------------------------------------------------------------------
+constexpr int SN_NT = 512;
+
+// Panel coordinates of element i of a supernode's packed columns: column bus
+// b of w, block kk of that column (0: the diagonal block, then the own buses
+// below it, then R), element e of the column-major 2x2 block.
+// Column b starts at f(b) = 4 b (w + r) - 2 b (b - 1) = b (B - 2 b) with
+// B = 4 (w + r) + 2; b is the largest root bound of f(b) <= i, refined by one
+// step each way after the floating-point estimate.
+__device__ inline void sn_coords(int i, int w, int r, int Wp, int& rowv, int& colv, int& kk, int& e,
+                                 int& bb) {
+  const int B = 4 * (w + r) + 2;
+  const double disc = (double)B * B - 8.0 * i;
+  bb = (int)((B - sqrt(disc > 0.0 ? disc : 0.0)) * 0.25);
+  if (bb < 0) bb = 0;
+  if (bb > w - 1) bb = w - 1;
+  while (bb > 0 && bb * (B - 2 * bb) > i) --bb;
+  while (bb < w - 1 && (bb + 1) * (B - 2 * (bb + 1)) <= i) ++bb;
+  const int st = bb * (B - 2 * bb);
+  kk = (i - st) >> 2;
+  e = (i - st) & 3;
+  const int u = e & 1, v = e >> 1;
+  rowv = (kk <= w - 1 - bb) ? 2 * (bb + kk) + u : Wp + 2 * (kk - (w - bb)) + u;
+  colv = 2 * bb + v;
+}
+
+__global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
+  const int s = s0 + blockIdx.x;
+  if (!d.active[s]) return;
+  const SysMeta g = d.sys[d.n_area];
+  double* vals = d.vals + (int64_t)s * d.vstride + g.val_off;
+  double* rhs = d.rhs + (int64_t)s * d.rstride + g.rhs_off;
+  extern __shared__ double sl[];
+  __shared__ double Linv[16 * 17];
+  __shared__ double colbuf[16];
+  __shared__ int bad;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr int NW = SN_NT / 64, UL = 8, TB = 4;
+  const int li = lane & 15, lk = lane >> 4;
+  if (tid == 0) bad = 0;
+  for (int q = 0; q < d.n_sn; ++q) {
+    const int4 sn = d.sn[q];
+    const int4 sn2 = d.sn2[q];
+    const int c0 = sn.x, w = sn.y, r = sn.z, rb = sn.w;
+    const int W = 2 * w, Wp = (W + 15) & ~15, M = Wp + ((2 * r + 15) & ~15);
+    const int T = sn2.y, ntg = r * (r + 1) / 2;
+    double* P = sl;            // [Wp columns][M rows]
+    double* yv = sl + M * Wp;  // [M]
+    int* tg = reinterpret_cast<int*>(yv + M);
+    for (int i = tid; i < M * Wp; i += SN_NT) P[i] = 0.0;
+    for (int i = tid; i < M; i += SN_NT) yv[i] = 0.0;
+    __syncthreads();
+    // (1) staging: UL loads in flight per thread; identity on the padding
+    if (tid < Wp - W) P[(W + tid) * M + W + tid] = 1.0;
+    for (int i0 = tid; i0 < T; i0 += UL * SN_NT) {
+      double v[UL];
+#pragma unroll
+      for (int u = 0; u < UL; ++u) {
+        const int i = i0 + u * SN_NT;
+        v[u] = (i < T) ? vals[sn2.x + i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < UL; ++u) {
+        const int i = i0 + u * SN_NT;
+        if (i >= T) break;
+        int rowv, colv, kk, e, bb;
+        sn_coords(i, w, r, Wp, rowv, colv, kk, e, bb);
+        if (kk == 0 && e == 2) continue;  // upper entry of the diagonal block
+        P[colv * M + rowv] = v[u];
+      }
+    }
+    for (int i = tid; i < W; i += SN_NT) yv[i] = rhs[2 * c0 + i];
+    for (int i = tid; i < 2 * r; i += SN_NT) yv[Wp + i] = rhs[2 * d.sn_rows[rb + (i >> 1)] + (i & 1)];
+    for (int i = tid; i < ntg; i += SN_NT) tg[i] = d.sn_tgt[sn2.z + i];
+    __syncthreads();
+    // (2) blocked Cholesky of the panel and forward solve
+    for (int cb = 0; cb < Wp; cb += 16) {
+      if (wv == 0) {
+        const bool ok = wave_chol16_inv(P, M, cb, yv, colbuf, Linv);
+        if (!ok && lane == 0) bad = 1;
+      }
+      __syncthreads();
+      // rows below the block: X = A L^-T, one 16-row tile per wave, on MFMA
+      const int rt0 = cb / 16 + 1, nrt = M / 16 - rt0;
+      for (int t = wv; t < nrt; t += NW) {
+        const int ri = 16 * (rt0 + t);
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const double a = P[(cb + 4 * e + lk) * M + ri + li];
+          const double bb = Linv[li * 17 + 4 * e + lk];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) P[(cb + li) * M + ri + 4 * e + lk] = acc[e];
+      }
+      __syncthreads();
+      // rhs of the rows below, and the remaining panel columns: tiles
+      // (row tile ic >= column tile jc > cb / 16)
+      for (int row = cb + 16 + tid; row < M; row += SN_NT) {
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) acc += P[(cb + c) * M + row] * yv[cb + c];
+        yv[row] -= acc;
+      }
+      const int jt0 = cb / 16 + 1, njt = Wp / 16 - jt0, nrt2 = M / 16;
+      int ntile = 0;
+      for (int j = 0; j < njt; ++j) ntile += nrt2 - (jt0 + j);
+      for (int t = wv; t < ntile; t += NW) {
+        int j = 0, tt = t;
+        while (tt >= nrt2 - (jt0 + j)) {
+          tt -= nrt2 - (jt0 + j);
+          ++j;
+        }
+        const int rj = 16 * (jt0 + j), ri = rj + 16 * tt;
+        d4 acc;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] = P[(rj + li) * M + ri + 4 * e + lk];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const double a = -P[(cb + 4 * e + lk) * M + ri + li];
+          const double bb = P[(cb + 4 * e + lk) * M + rj + li];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) P[(rj + li) * M + ri + 4 * e + lk] = acc[e];
+      }
+      __syncthreads();
+    }
+    // (3) Schur update of the R x R blocks: tiles (I >= J) of the R rows.  A
+    // wave computes TB tiles, then loads all their targets, then stores, so
+    // the read-modify-write round trips overlap.
+    const int nr = (M - Wp) / 16, nt3 = nr * (nr + 1) / 2;
+    for (int t0 = wv; t0 < nt3; t0 += NW * TB) {
+      d4 acc[TB];
+      int idx[TB][4];
+#pragma unroll
+      for (int b = 0; b < TB; ++b) {
+        const int t = t0 + b * NW;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) idx[b][e] = -1;
+        if (t >= nt3) continue;
+        int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+        while (I * (I + 1) / 2 > t) --I;
+        while ((I + 1) * (I + 2) / 2 <= t) ++I;
+        const int J = t - I * (I + 1) / 2;
+        // the tile is computed transposed (D = rows J x rows I): lane li then
+        // holds row 16 I + li, so lanes run down a column of the target
+        const int ri = Wp + 16 * I, rj = Wp + 16 * J;
+        acc[b] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int k4 = 0; k4 < Wp; k4 += 4) {
+          const double a = P[(k4 + lk) * M + rj + li];
+          const double bb = P[(k4 + lk) * M + ri + li];
+          acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc[b], 0, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int xv = 16 * I + li, yc = 16 * J + 4 * e + lk;
+          const int ab = xv >> 1, cb2 = yc >> 1;
+          if (xv < 2 * r && yc < 2 * r && ab >= cb2) {
+            const int off = tg[ab * (ab + 1) / 2 + cb2];
+            const int stride = off >= g.tail_off ? g.ld : 2;
+            idx[b][e] = off + (xv & 1) + stride * (yc & 1);
+          }
+        }
+      }
+      double old[TB][4];
+#pragma unroll
+      for (int b = 0; b < TB; ++b)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) old[b][e] = (idx[b][e] >= 0) ? vals[idx[b][e]] : 0.0;
+#pragma unroll
+      for (int b = 0; b < TB; ++b)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (idx[b][e] >= 0) vals[idx[b][e]] = old[b][e] - acc[b][e];
+    }
+    // (4) factor and forward-solved rhs back to HBM
+    for (int i = tid; i < T; i += SN_NT) {
+      int rowv, colv, kk, e, bb;
+      sn_coords(i, w, r, Wp, rowv, colv, kk, e, bb);
+      double val;
+      if (kk == 0) {
+        const double l00 = P[(2 * bb) * M + 2 * bb], l10 = P[(2 * bb) * M + 2 * bb + 1];
+        const double l11 = P[(2 * bb + 1) * M + 2 * bb + 1];
+        val = (e == 0) ? l00 * l00 : (e == 3) ? l10 * l10 + l11 * l11 : l10 * l00;
+      } else {
+        val = P[colv * M + rowv];
+      }
+      vals[sn2.x + i] = val;
+    }
+    for (int i = tid; i < W; i += SN_NT) rhs[2 * c0 + i] = yv[i];
+    for (int i = tid; i < 2 * r; i += SN_NT) rhs[2 * d.sn_rows[rb + (i >> 1)] + (i & 1)] = yv[Wp + i];
+    __syncthreads();
+  }
   if (tid == 0 && bad) d.status[(int64_t)s * (d.n_area + 1) + d.n_area] = 1;
 }
 
@@ -620,7 +983,9 @@ __global__ void __launch_bounds__(DENSE_NT) k_dense_chol(Dev d, int s0) {
 // ---------------------------------------------------------------------------
 template <int NT>
 __global__ void __launch_bounds__(NT) k_backsolve(Dev d, int sys0, int nsys, int s0, int ns) {
-  constexpr int G = 8;
+  // lanes per column: the boundary system's levels hold a few wide columns,
+  // an area's levels many narrow ones
+  constexpr int G = (NT >= 1024) ? 64 : 8;
   int si, s;
   area_snap_of_block(blockIdx.x, nsys, ns, si, s);
   s += s0;
@@ -763,9 +1128,9 @@ hipError_t launch_assemble(const Dev& d, int a0, int na, int s0, int ns, int mod
                            bool br_lds, hipStream_t st) {
   if (na <= 0 || ns <= 0) return hipSuccess;
   if (br_lds)
-    hipLaunchKernelGGL(k_assemble<true>, dim3(na * ns), dim3(512), lds, st, d, a0, na, s0, ns, mode);
+    hipLaunchKernelGGL(k_assemble<true>, dim3(na * ns), dim3(ASM_NT), lds, st, d, a0, na, s0, ns, mode);
   else
-    hipLaunchKernelGGL(k_assemble<false>, dim3(na * ns), dim3(512), lds, st, d, a0, na, s0, ns, mode);
+    hipLaunchKernelGGL(k_assemble<false>, dim3(na * ns), dim3(ASM_NT), lds, st, d, a0, na, s0, ns, mode);
   return hipGetLastError();
 }
 
@@ -791,6 +1156,17 @@ hipError_t launch_gamma_gather(const Dev& d, int s0, int ns, int nslot, int nn, 
   if (work <= 0 || ns <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_gamma_gather, dim3((work + 255) / 256, ns), dim3(256), 0, st, d, s0, nslot);
   return hipGetLastError();
+}
+
+hipError_t launch_gamma_snode(const Dev& d, int s0, int ns, size_t lds, hipStream_t st) {
+  if (ns <= 0 || d.n_sn <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gamma_snode, dim3(ns), dim3(SN_NT), lds, st, d, s0);
+  return hipGetLastError();
+}
+
+hipError_t allow_gamma_snode_lds(size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gamma_snode),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 size_t dense_lds_bytes(int ld, bool panel) {

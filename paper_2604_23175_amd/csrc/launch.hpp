@@ -15,6 +15,10 @@ hipError_t launch_assemble(const Dev& d, int a0, int na, int s0, int ns, int mod
 // lds: dynamic LDS bytes for the level staging (max over the launched systems)
 hipError_t launch_eliminate(const Dev& d, int sys0, int nsys, int s0, int ns, size_t lds, hipStream_t st);
 hipError_t allow_eliminate_lds(size_t bytes);
+// supernodal elimination of the boundary system's leading buses; lds: the
+// plan's sn_lds_bytes
+hipError_t launch_gamma_snode(const Dev& d, int s0, int ns, size_t lds, hipStream_t st);
+hipError_t allow_gamma_snode_lds(size_t bytes);
 hipError_t launch_gamma_gather(const Dev& d, int s0, int ns, int nslot, int nn, hipStream_t st);
 // panel: stage each factor panel in LDS (needs dense_lds_bytes(ld, true))
 size_t dense_lds_bytes(int ld, bool panel);

@@ -261,6 +261,36 @@ int32_t SysPlan::blk_off(int i, int j) const {
 
 int32_t SysPlan::blk_stride(int /*i*/, int j) const { return j < ne ? 2 : ld; }
 
+void SysPlan::build_supernodes() {
+  sn.clear();
+  sn2.clear();
+  sn_rows.clear();
+  sn_tgt.clear();
+  sn_tbase.assign(1, 0);
+  sn_lds_bytes = 0;
+  int j = 0;
+  while (j < ne) {
+    int w = 1;
+    while (j + w < ne && w < SN_MAX_W) {
+      const auto& a = strct[j + w - 1];
+      const auto& c = strct[j + w];
+      if (a.empty() || a[0] != j + w || a.size() != c.size() + 1) break;
+      if (!std::equal(c.begin(), c.end(), a.begin() + 1)) break;
+      ++w;
+    }
+    const auto& R = strct[j + w - 1];
+    const int r = (int)R.size();
+    sn.push_back({j, w, r, (int32_t)sn_rows.size()});
+    sn2.push_back({col_off[j], col_off[j + w - 1] + 4 * (1 + r) - col_off[j], (int32_t)sn_tgt.size(), 0});
+    sn_rows.insert(sn_rows.end(), R.begin(), R.end());
+    for (int a = 0; a < r; ++a)
+      for (int c = 0; c <= a; ++c) sn_tgt.push_back(blk_off(R[a], R[c]));
+    sn_tbase.push_back((int32_t)sn_tgt.size());
+    sn_lds_bytes = std::max(sn_lds_bytes, sn_lds_bytes_of(w, r));
+    j += w;
+  }
+}
+
 double SysPlan::elim_flops() const {
   double f = 0;
   for (int j = 0; j < ne; ++j) {
@@ -579,7 +609,10 @@ std::string build_plan(const Input& in, Plan& p) {
       g.strct.assign(nn, {});
       g.ne = 0;
     }
-    try { finish_system(g); } catch (std::exception& ex) { return ex.what(); }
+    try {
+      finish_system(g);
+      g.build_supernodes();
+    } catch (std::exception& ex) { return ex.what(); }
     std::vector<int> gpos(N, -1);  // bus -> Gamma local index
     for (int v = 0; v < nn; ++v) gpos[g.gbus[v]] = v;
     if (p.is_bnd[p.slack]) g.pin_off = g.blk_off(gpos[p.slack], gpos[p.slack]);

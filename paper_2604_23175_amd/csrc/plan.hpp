@@ -23,6 +23,19 @@ constexpr int MAX_LOCAL_BRANCH = 0xFFF0;
 constexpr int32_t UP_SINGLE = 1 << 30;
 // LDS budget (doubles) for staging one schedule step of the elimination.
 constexpr int LDS_STAGE_DOUBLES = 6144;
+// Widest supernode (buses): its panel is at most 64 variables wide.
+constexpr int SN_MAX_W = 32;
+
+// Panel geometry of a supernode of w buses with r row buses below: the LDS
+// panel has sn_rows_padded() rows (the 2w own variables padded to a multiple
+// of 16, then the 2r row variables padded likewise) and sn_cols_padded()
+// columns, column-major.
+inline int sn_cols_padded(int w) { return (2 * w + 15) / 16 * 16; }
+inline int sn_rows_padded(int w, int r) { return sn_cols_padded(w) + (2 * r + 15) / 16 * 16; }
+inline int sn_lds_bytes_of(int w, int r) {
+  const int M = sn_rows_padded(w, r);
+  return 8 * (M * sn_cols_padded(w) + M) + 4 * (r * (r + 1) / 2);
+}
 
 // One symmetric positive definite system over "buses" (2x2 blocks: theta, |V|)
 // eliminated by the level-scheduled sparse engine.  Local buses [0, ne) are
@@ -59,10 +72,25 @@ struct SysPlan {
   std::vector<I4> rb_tgt;       // {rhs_i, cbeg, cend, 0}
   std::vector<I2> rb_con;       // {slot L_ij, slot y_j}: y_i -= L_ij * y_j
   int32_t lds_doubles = 0;      // LDS staging needed by the largest level
+  // Supernodes of the eliminated buses (built for the boundary system): runs
+  // of consecutive buses j, j+1, ... in which each bus is the elimination-tree
+  // parent of the previous one and the structures nest, strct[j] = {j+1} U
+  // strct[j+1], at most SN_MAX_W buses wide.  Such a run is one dense panel:
+  // its columns are contiguous in the packed storage, and its rows below the
+  // diagonal block are the same bus list R for every column.
+  std::vector<I4> sn;             // {first bus c0, width w, |R| = r, base of R in sn_rows}
+  std::vector<I4> sn2;            // {offset of column c0's diagonal block, doubles of the
+                                  // panel's columns (contiguous), base in sn_tgt, 0}
+  std::vector<int32_t> sn_tbase;  // [nsn+1] -> sn_tgt
+  std::vector<int32_t> sn_rows;   // R of each supernode, ascending local bus ids
+  std::vector<int32_t> sn_tgt;    // per supernode, for a >= c in R: offset of block (R[a], R[c])
+                                  // at a(a+1)/2 + c (in the dense tail when >= tail_off)
+  int32_t sn_lds_bytes = 0;       // LDS of the largest panel (values, rhs, target offsets)
   std::vector<int32_t> bs_ptr;  // [nlev+1] -> bs_items (same levels, run top-down)
   std::vector<I4> bs_items;     // {diag_off, rhs_j, cbeg, cend}
   std::vector<I2> bs_con;       // {off L_ij, rhs_i}: t -= L_ij^T * x_i
 
+  void build_supernodes();               // fills sn*, after the schedule
   int32_t blk_off(int i, int j) const;   // block (i, j), i >= j
   int32_t blk_stride(int i, int j) const;
   double elim_flops() const;             // flops of eliminating [0, ne) with rhs

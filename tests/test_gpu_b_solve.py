@@ -114,6 +114,27 @@ def test_dense_block_panel_variants_bitwise_identical(gm, monkeypatch):
     np.testing.assert_array_equal(res[0][1], res[1][1])
 
 
+@pytest.mark.parametrize("name", ["c1", "k8"])
+def test_supernodal_and_level_boundary_elimination_agree(name, monkeypatch):
+    # The boundary system's sparse part runs supernodal (LDS panels, MFMA
+    # updates) by default; MASE_GAMMA_SNODE=0 selects the level-scheduled
+    # engine.  Different summation order, same factorisation.
+    say("boundary supernodes vs levels", name)
+    c = Case(name, 3, seed=12)
+    res = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("MASE_GAMMA_SNODE", flag)
+        m = c.ctx()
+        iters, conv = m.mase_solve(1e-10, 12)
+        assert conv.all()
+        res.append((m.mase_state(), iters))
+        m.close()
+    assert_state_close(res[0][0][0], res[0][0][1], res[1][0][0], res[1][0][1], 1e-10)
+    for i in range(c.n_snap):
+        o = c.oracle_solve(i, tol=1e-10, max_iter=12)
+        assert_state_close(res[0][0][0][i], res[0][0][1][i], o["vm"], o["va"], 1e-8)
+
+
 def test_zero_weight_equals_deleted_row():
     say("masking")
     c = Case("k5", 1, seed=6)
