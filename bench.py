@@ -20,6 +20,7 @@ import hashlib
 import json
 import os
 import subprocess
+import tempfile
 import sys
 import time
 
@@ -126,7 +127,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     g, t, a, s, vm_true, va_true, eps = make_inputs(N_SNAP)
-    ctx = mase.Mase.from_grid(g, t, a, s, N_SNAP)
+    # the schedule (pipeline groups, boundary elimination variant) is picked by
+    # the library's autotuner on the first solve, outside the timed region
+    tune_cache = os.path.join(tempfile.gettempdir(), "mase_autotune.txt")
+    ctx = mase.Mase.from_grid(g, t, a, s, N_SNAP, autotune=True, tune_cache=tune_cache)
     # synthetic measurements z = h(x_true) + sigma * eps, built on the device
     vmt = torch.tensor(vm_true, device=dev)
     vat = torch.tensor(va_true, device=dev)
@@ -249,7 +253,8 @@ def main():
                 "gamma_sparse": ("alu", info["flops_gamma_sparse"])}
     stages = {k: v for k, v in prof.items() if v["launches"]}
     kernel_names = {"assemble": "k_assemble", "condense": "k_eliminate<256>", "backsolve": "k_backsolve<256>",
-                    "gamma_dense": "k_dense_chol", "gamma_sparse": "k_eliminate<1024>"}
+                    "gamma_dense": "k_dense_chol",
+                    "gamma_sparse": "k_gamma_snode" if info["gamma_supernodal"] else "k_eliminate<1024>"}
     dom = max((k for k in stages if k in per_unit), key=lambda k: stages[k]["ms"])
     bound, unit_work = per_unit[dom]
     st = stages[dom]
@@ -281,7 +286,10 @@ def main():
                                + "batched + hipGraph, sparse boundary solve",
                    "n_bus": g.n_bus, "n_branch": g.n_branch, "n_area": g.n_area, "snapshots": N_SNAP,
                    "n_meas": int(t.size), "n_gamma": info["n_gamma"], "tol": TOL, "max_iter": MAX_ITER,
-                   "warm_start": warm},
+                   "warm_start": warm,
+                   "schedule": {"pipeline_groups": info["pipeline_groups"],
+                                "boundary_elimination": "supernodal" if info["gamma_supernodal"] else "levels",
+                                "chosen_by": "autotuner"}},
         "gn_iters_per_s": tot_iters / dt, "all_converged": all_conv,
         "warm_start": None if not warm else {"accepted_fraction": acc_frac, "training": train_info},
         "batched_flat": {"value": N_SNAP * args.steps / fdt, "unit": "snapshots/s",

@@ -106,9 +106,22 @@ typedef struct {
   int32_t host_only;     /* 1: build the maps and symbolic structures only,
                             touch no GPU (exports work, solves return
                             MASE_ERR_NO_DEVICE) */
-  int32_t autotune;      /* 1: time candidate launch shapes at create and
-                            keep the fastest (cached in tune_cache) */
-  const char* tune_cache;/* path of the autotune cache file, or NULL */
+  int32_t autotune;      /* 1: the first mase_solve times the candidate
+                            schedules (pipeline groups 1/2/4/8, supernodal or
+                            level-scheduled boundary elimination) for two GN
+                            iterations on the current measurements, keeps the
+                            fastest and restores the state; results are then
+                            the chosen schedule's */
+  const char* tune_cache;/* path of a text file caching that choice per grid
+                            structure, batch size and device (read before
+                            tuning, appended after), or NULL */
+  int32_t pipeline_groups;/* mase_solve in the batched graph mode: split the
+                            snapshots into this many groups that iterate on
+                            their own streams, so that one group's boundary
+                            solve (latency-bound, few CUs) overlaps the next
+                            group's area stages.  0 (default) or 1: off;
+                            the autotuner also tries 2, 4 and 8.  Results
+                            are bitwise identical for every value */
 } mase_options;
 
 /* Fill `opt` with the defaults listed above. */
@@ -324,7 +337,11 @@ enum {
   MASE_INFO_FLOPS_DENSE,      /* flops per snapshot of the dense boundary block */
   MASE_INFO_BYTES_BACKSOLVE,  /* algorithmic HBM bytes per snapshot of back substitution */
   MASE_INFO_FLOPS_GAMMA_SPARSE, /* flops per snapshot, sparse part of the boundary solve */
-  MASE_INFO_GAMMA_LEVELS      /* elimination levels of the boundary system's sparse part */
+  MASE_INFO_GAMMA_LEVELS,     /* elimination levels of the boundary system's sparse part */
+  MASE_INFO_GAMMA_SUPERNODES, /* supernodes of the boundary system's sparse part */
+  MASE_INFO_GAMMA_SUPERNODAL, /* 1 if the boundary elimination runs supernodal (else the
+                                 level schedule) */
+  MASE_INFO_PIPELINE_GROUPS   /* snapshot groups of mase_solve's pipelined schedule */
 };
 int mase_info(const mase_ctx* ctx, int32_t what, int64_t* value);
 

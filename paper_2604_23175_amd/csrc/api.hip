@@ -185,7 +185,8 @@ int upload_plan(mase_ctx* c) {
   {
     const char* env = getenv("MASE_GAMMA_SNODE");
     c->lds_sn = (size_t)p.sys[K].sn_lds_bytes;
-    c->gamma_snode = !p.sys[K].sn.empty() && c->lds_sn + 4096 <= (size_t)maxlds && !(env && env[0] == '0');
+    c->snode_possible = !p.sys[K].sn.empty() && c->lds_sn + 4096 <= (size_t)maxlds;
+    c->gamma_snode = c->snode_possible && !(env && env[0] == '0');
     if (c->gamma_snode && c->lds_sn > 65536) HIPTRY(allow_gamma_snode_lds(c->lds_sn));
   }
   c->hsys = sm;
@@ -271,45 +272,172 @@ struct StageMark {
   }
 };
 
-int launch_batched_iteration(mase_ctx* c, hipStream_t st) {
-  const int K = c->plan.n_area, S = c->plan.n_snap;
+bool snapshot_bad(const mase_ctx* c, int s);
+
+// Stages 1-2 (assembly, condensation) for snapshots [s0, s0 + ns).
+int launch_area_part(mase_ctx* c, hipStream_t st, int s0, int ns) {
+  const int K = c->plan.n_area;
   const Dev& d = c->d;
-  for (bool& u : c->pused) u = false;
   {
     StageMark m(c, st, MASE_STAGE_ASSEMBLE);
-    HIPTRY(launch_assemble(d, 0, K, 0, S, MODE_ASSEMBLE, c->lds_asm, c->br_lds, st));
+    HIPTRY(launch_assemble(d, 0, K, s0, ns, MODE_ASSEMBLE, c->lds_asm, c->br_lds, st));
   }
   {
     StageMark m(c, st, MASE_STAGE_CONDENSE);
-    HIPTRY(launch_eliminate(d, 0, K, 0, S, c->lds_el_area, st));
+    HIPTRY(launch_eliminate(d, 0, K, s0, ns, c->lds_el_area, st));
   }
+  return 0;
+}
+
+// Stages 3-4 (boundary assembly and solve, back substitution, update) for
+// snapshots [s0, s0 + ns).
+int launch_gamma_part(mase_ctx* c, hipStream_t st, int s0, int ns) {
+  const int K = c->plan.n_area;
+  const Dev& d = c->d;
   const SysMeta& g = gsys(c);
   if (g.nn > 0) {
     {
       StageMark m(c, st, MASE_STAGE_GAMMA_GATHER);
-      HIPTRY(launch_gamma_gather(d, 0, S, c->nslot_g, g.nn, st));
+      HIPTRY(launch_gamma_gather(d, s0, ns, c->nslot_g, g.nn, st));
     }
     if (g.ne > 0) {
       StageMark m(c, st, MASE_STAGE_GAMMA_SPARSE);
-      HIPTRY(launch_gamma_sparse(c, 0, S, st));
+      HIPTRY(launch_gamma_sparse(c, s0, ns, st));
     }
     {
       StageMark m(c, st, MASE_STAGE_GAMMA_DENSE);
-      HIPTRY(launch_dense_chol(d, 0, S, g.ld, c->dense_panel, st));
+      HIPTRY(launch_dense_chol(d, s0, ns, g.ld, c->dense_panel, st));
     }
     if (g.ne > 0) {
       StageMark m(c, st, MASE_STAGE_GAMMA_BACK);
-      HIPTRY(launch_backsolve(d, K, 1, 0, S, st));
+      HIPTRY(launch_backsolve(d, K, 1, s0, ns, st));
     }
   }
   {
     StageMark m(c, st, MASE_STAGE_BACKSOLVE);
-    HIPTRY(launch_backsolve(d, 0, K, 0, S, st));
+    HIPTRY(launch_backsolve(d, 0, K, s0, ns, st));
   }
   {
     StageMark m(c, st, MASE_STAGE_UPDATE);
-    HIPTRY(launch_update(d, 0, S, st));
+    HIPTRY(launch_update(d, s0, ns, st));
   }
+  return 0;
+}
+
+int launch_batched_iteration(mase_ctx* c, hipStream_t st) {
+  const int S = c->plan.n_snap;
+  for (bool& u : c->pused) u = false;
+  int rc = launch_area_part(c, st, 0, S);
+  if (rc) return rc;
+  return launch_gamma_part(c, st, 0, S);
+}
+
+// Captures fn(c, st, s0, ns) on stream st as an executable graph.
+int capture_part(mase_ctx* c, hipStream_t st, int (*fn)(mase_ctx*, hipStream_t, int, int), int s0, int ns,
+                 hipGraphExec_t* out) {
+  HIPTRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  int rc = fn(c, st, s0, ns);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(st, &g);
+  if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+  if (e != hipSuccess) return fail(MASE_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+  c->pgraphs.push_back(g);
+  HIPTRY(hipGraphInstantiate(out, g, nullptr, nullptr, 0));
+  return 0;
+}
+
+// Streams, events and the two graphs per group of the pipelined solve.
+int setup_pipeline(mase_ctx* c) {
+  if (!c->pgA.empty()) return 0;
+  const int G = c->npipe, S = c->plan.n_snap;
+  c->pg_s0.resize(G + 1);
+  for (int g = 0; g <= G; ++g) c->pg_s0[g] = (int)((int64_t)S * g / G);
+  HIPTRY(hipStreamCreateWithFlags(&c->pstream_area, hipStreamNonBlocking));
+  c->pstream.assign(G, nullptr);
+  c->pev_a.assign(G, nullptr);
+  c->pev_b.assign(G, nullptr);
+  c->pgA.assign(G, nullptr);
+  c->pgB.assign(G, nullptr);
+  for (int g = 0; g < G; ++g) {
+    HIPTRY(hipStreamCreateWithFlags(&c->pstream[g], hipStreamNonBlocking));
+    HIPTRY(hipEventCreateWithFlags(&c->pev_a[g], hipEventDisableTiming));
+    HIPTRY(hipEventCreateWithFlags(&c->pev_b[g], hipEventDisableTiming));
+  }
+  for (int g = 0; g < G; ++g) {
+    const int s0 = c->pg_s0[g], ns = c->pg_s0[g + 1] - s0;
+    int rc = capture_part(c, c->pstream_area, launch_area_part, s0, ns, &c->pgA[g]);
+    if (rc) return rc;
+    rc = capture_part(c, c->pstream[g], launch_gamma_part, s0, ns, &c->pgB[g]);
+    if (rc) return rc;
+  }
+  return 0;
+}
+
+// One iteration of group g: area stages on the shared area stream, then the
+// boundary solve and update on the group's stream, then its flags to host.
+int launch_group_iteration(mase_ctx* c, int g) {
+  const int K = c->plan.n_area;
+  const int s0 = c->pg_s0[g], ns = c->pg_s0[g + 1] - s0;
+  HIPTRY(hipStreamWaitEvent(c->pstream_area, c->pev_b[g], 0));
+  HIPTRY(hipGraphLaunch(c->pgA[g], c->pstream_area));
+  HIPTRY(hipEventRecord(c->pev_a[g], c->pstream_area));
+  hipStream_t st = c->pstream[g];
+  HIPTRY(hipStreamWaitEvent(st, c->pev_a[g], 0));
+  HIPTRY(hipGraphLaunch(c->pgB[g], st));
+  HIPTRY(hipMemcpyAsync(c->h_active + s0, c->d.active + s0, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st));
+  HIPTRY(hipMemcpyAsync(c->h_maxdx + s0, c->d.maxdx + s0, sizeof(double) * ns, hipMemcpyDeviceToHost, st));
+  HIPTRY(hipMemcpyAsync(c->h_status + (size_t)s0 * (K + 1), c->d.status + (size_t)s0 * (K + 1),
+                        sizeof(int32_t) * ns * (K + 1), hipMemcpyDeviceToHost, st));
+  HIPTRY(hipEventRecord(c->pev_b[g], st));
+  return 0;
+}
+
+// mase_solve's batched graph schedule with snapshot groups that iterate
+// independently: the host waits for the groups round-robin and relaunches
+// each one that still has active snapshots, so a group's boundary solve runs
+// while the next group's area stages occupy the chip.  Each snapshot goes
+// through exactly the kernels and arithmetic of the one-group schedule.
+int pipelined_solve(mase_ctx* c, int max_iter) {
+  int rc = setup_pipeline(c);
+  if (rc) return rc;
+  const int G = c->npipe;
+  HIPTRY(hipEventRecord(c->ev_main, c->stream));
+  HIPTRY(hipStreamWaitEvent(c->pstream_area, c->ev_main, 0));
+  for (int g = 0; g < G; ++g) {
+    HIPTRY(hipStreamWaitEvent(c->pstream[g], c->ev_main, 0));
+    HIPTRY(hipEventRecord(c->pev_b[g], c->pstream[g]));
+  }
+  std::vector<int> done(G, 0), iters(G, 0);
+  auto group_active = [&](int g) {
+    for (int s = c->pg_s0[g]; s < c->pg_s0[g + 1]; ++s)
+      if (c->h_active[s]) return true;
+    return false;
+  };
+  int pending = 0;
+  for (int g = 0; g < G; ++g) {
+    if (!group_active(g)) { done[g] = 1; continue; }
+    if ((rc = launch_group_iteration(c, g))) return rc;
+    ++pending;
+  }
+  while (pending > 0) {
+    for (int g = 0; g < G; ++g) {
+      if (done[g]) continue;
+      HIPTRY(hipEventSynchronize(c->pev_b[g]));
+      ++iters[g];
+      bool bad = false;
+      for (int s = c->pg_s0[g]; s < c->pg_s0[g + 1]; ++s) bad |= snapshot_bad(c, s);
+      if (bad || !group_active(g) || iters[g] >= max_iter) {
+        done[g] = 1;
+        --pending;
+        continue;
+      }
+      if ((rc = launch_group_iteration(c, g))) return rc;
+    }
+  }
+  // later work on the context's stream follows every group
+  HIPTRY(hipEventRecord(c->ev_main, c->pstream_area));
+  HIPTRY(hipStreamWaitEvent(c->stream, c->ev_main, 0));
+  for (int g = 0; g < G; ++g) HIPTRY(hipStreamWaitEvent(c->stream, c->pev_b[g], 0));
   return 0;
 }
 
@@ -490,9 +618,14 @@ int mase_create(int32_t n_bus, int32_t n_branch, const int32_t* br_from, const i
   if (opt) o = *opt;
   Input in{n_bus, n_branch, br_from, br_to, br_r, br_x, br_b, slack_bus, n_area, bus_area,
            n_meas, meas_type, meas_at, meas_sigma, n_snap, o.gamma_mode};
+  if (o.pipeline_groups < 0) return fail(MASE_ERR_ARG, "pipeline_groups must be >= 0");
   mase_ctx* c = new (std::nothrow) mase_ctx();
   if (!c) return fail(MASE_ERR_OOM, "host allocation failed");
   c->opt = o;
+  c->npipe = o.pipeline_groups > 0 ? o.pipeline_groups : 1;
+  c->npipe = std::max(1, std::min(c->npipe, std::max(1, n_snap)));
+  if (o.tune_cache) c->tune_path = o.tune_cache;
+  c->opt.tune_cache = nullptr;  // the caller's string is not kept
   c->host_only = o.host_only != 0;
   std::string err;
   try {
@@ -525,9 +658,9 @@ int mase_create(int32_t n_bus, int32_t n_branch, const int32_t* br_from, const i
           hipEventCreateWithFlags(&c->aevents[i], hipEventDisableTiming) != hipSuccess)
         rc = fail(MASE_ERR_HIP, "stream creation failed");
     }
-    if (!rc && hipEventCreateWithFlags(&c->ev_main, hipEventDisableTiming) != hipSuccess)
-      rc = fail(MASE_ERR_HIP, "event creation failed");
   }
+  if (!rc && hipEventCreateWithFlags(&c->ev_main, hipEventDisableTiming) != hipSuccess)
+    rc = fail(MASE_ERR_HIP, "event creation failed");
   if (!rc) rc = upload_plan(c);
   if (!rc) {
     hipError_t e = launch_pack_state(c->d, nullptr, nullptr, c->d.x, c->stream);
@@ -549,6 +682,15 @@ void mase_destroy(mase_ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->pstream_area) (void)hipStreamSynchronize(c->pstream_area);
+    for (auto s : c->pstream) if (s) (void)hipStreamSynchronize(s);
+    for (auto e : c->pgA) if (e) (void)hipGraphExecDestroy(e);
+    for (auto e : c->pgB) if (e) (void)hipGraphExecDestroy(e);
+    for (auto g : c->pgraphs) if (g) (void)hipGraphDestroy(g);
+    for (auto e : c->pev_a) if (e) (void)hipEventDestroy(e);
+    for (auto e : c->pev_b) if (e) (void)hipEventDestroy(e);
+    for (auto s : c->pstream) if (s) (void)hipStreamDestroy(s);
+    if (c->pstream_area) (void)hipStreamDestroy(c->pstream_area);
     for (auto s : c->astreams) if (s) { (void)hipStreamSynchronize(s); (void)hipStreamDestroy(s); }
     for (auto e : c->aevents) if (e) (void)hipEventDestroy(e);
     if (c->ev_main) (void)hipEventDestroy(c->ev_main);
@@ -668,6 +810,193 @@ int mase_gn_iter(mase_ctx* c, double* max_abs_dx) {
   return 0;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Autotuner: candidate schedules timed on the context's own measurements.
+// ---------------------------------------------------------------------------
+namespace {
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+  const unsigned char* b = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+// Key of the tuning cache: the grid structure, partition, measurement set,
+// batch size, boundary mode and the device.
+std::string make_tune_key(const mase_ctx* c) {
+  const Plan& p = c->plan;
+  uint64_t h = 1469598103934665603ull;
+  const int32_t dims[6] = {p.n_bus, p.n_branch, p.n_area, p.n_meas, p.n_snap, c->opt.gamma_mode};
+  h = fnv1a(h, dims, sizeof(dims));
+  h = fnv1a(h, p.br_from.data(), p.br_from.size() * sizeof(int32_t));
+  h = fnv1a(h, p.br_to.data(), p.br_to.size() * sizeof(int32_t));
+  h = fnv1a(h, p.bus_area.data(), p.bus_area.size() * sizeof(int32_t));
+  h = fnv1a(h, p.meas_area.data(), p.meas_area.size() * sizeof(int32_t));
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipGetDeviceProperties(&prop, dev);
+  char buf[64];
+  std::snprintf(buf, sizeof(buf), "%016llx", (unsigned long long)h);
+  std::string arch(prop.gcnArchName);
+  for (char& ch : arch)
+    if (ch == ' ' || ch == '\n') ch = '_';
+  return std::string(buf) + "/" + (arch.empty() ? "unknown" : arch);
+}
+
+bool read_tune_cache(const mase_ctx* c, int& npipe, int& snode) {
+  if (c->tune_path.empty()) return false;
+  FILE* f = std::fopen(c->tune_path.c_str(), "r");
+  if (!f) return false;
+  char key[256];
+  int a = 0, b = 0;
+  bool found = false;
+  while (std::fscanf(f, "%255s %d %d", key, &a, &b) == 3)
+    if (c->tune_key == key && a >= 1 && (b == 0 || b == 1)) {
+      npipe = a;
+      snode = b;
+      found = true;  // the last matching line wins
+    }
+  std::fclose(f);
+  return found;
+}
+
+void write_tune_cache(const mase_ctx* c, int npipe, int snode) {
+  if (c->tune_path.empty()) return;
+  FILE* f = std::fopen(c->tune_path.c_str(), "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d %d\n", c->tune_key.c_str(), npipe, snode);
+  std::fclose(f);
+}
+
+// Drops every captured graph (they bake in the schedule choices).
+int reset_graphs(mase_ctx* c) {
+  HIPTRY(hipStreamSynchronize(c->stream));
+  if (c->pstream_area) HIPTRY(hipStreamSynchronize(c->pstream_area));
+  for (auto st : c->pstream) HIPTRY(hipStreamSynchronize(st));
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+  for (auto e : c->pgA) if (e) (void)hipGraphExecDestroy(e);
+  for (auto e : c->pgB) if (e) (void)hipGraphExecDestroy(e);
+  for (auto g : c->pgraphs) if (g) (void)hipGraphDestroy(g);
+  for (auto e : c->pev_a) if (e) (void)hipEventDestroy(e);
+  for (auto e : c->pev_b) if (e) (void)hipEventDestroy(e);
+  for (auto st : c->pstream) if (st) (void)hipStreamDestroy(st);
+  if (c->pstream_area) (void)hipStreamDestroy(c->pstream_area);
+  c->pgA.clear();
+  c->pgB.clear();
+  c->pgraphs.clear();
+  c->pev_a.clear();
+  c->pev_b.clear();
+  c->pstream.clear();
+  c->pstream_area = nullptr;
+  return 0;
+}
+
+// The batched iteration loop of mase_solve (pipelined when npipe > 1).
+int solve_batched(mase_ctx* c, int max_iter) {
+  const int S = c->plan.n_snap;
+  int rc = 0;
+  HIPTRY(hipMemcpyAsync(c->h_active, c->d.active, sizeof(int32_t) * S, hipMemcpyDeviceToHost, c->stream));
+  HIPTRY(hipMemcpyAsync(c->h_status, c->d.status, sizeof(int32_t) * S * (c->plan.n_area + 1),
+                        hipMemcpyDeviceToHost, c->stream));
+  HIPTRY(hipStreamSynchronize(c->stream));
+  if (c->opt.use_graph && !c->prof && c->npipe > 1) return pipelined_solve(c, max_iter);
+  int nact = 0;
+  for (int s = 0; s < S; ++s) nact += c->h_active[s] != 0;
+  for (int it = 0; it < max_iter && nact > 0; ++it) {
+    if ((rc = mase_gn_iter(c, nullptr))) return rc;
+    nact = 0;
+    for (int s = 0; s < S; ++s) nact += c->h_active[s] != 0;
+  }
+  return 0;
+}
+
+// Times two GN iterations of every candidate from the current state, keeps
+// the fastest, restores the state.
+int autotune(mase_ctx* c) {
+  c->tuned = true;
+  if (c->tune_key.empty()) c->tune_key = make_tune_key(c);
+  int np = 0, sn = 0;
+  if (read_tune_cache(c, np, sn)) {
+    int rc = reset_graphs(c);
+    if (rc) return rc;
+    c->npipe = std::max(1, std::min(np, c->plan.n_snap));
+    c->gamma_snode = sn && c->snode_possible;
+    return 0;
+  }
+  const int S = c->plan.n_snap, K = c->plan.n_area;
+  double2* sx = nullptr;
+  int32_t* sflags = nullptr;
+  double* smax = nullptr;
+  const size_t nx = (size_t)S * c->plan.n_bus, nf = (size_t)S * (3 + K);
+  int rc = dalloc(c, nx, &sx);
+  if (!rc) rc = dalloc(c, nf, &sflags);
+  if (!rc) rc = dalloc(c, (size_t)S, &smax);
+  if (rc) return rc;
+  auto save_restore = [&](bool save) -> int {
+    const size_t bf = sizeof(int32_t) * S;
+    double2* x = c->d.x;
+    if (save) {
+      HIPTRY(hipMemcpyAsync(sx, x, sizeof(double2) * nx, hipMemcpyDeviceToDevice, c->stream));
+      HIPTRY(hipMemcpyAsync(sflags, c->d.active, bf, hipMemcpyDeviceToDevice, c->stream));
+      HIPTRY(hipMemcpyAsync(sflags + S, c->d.iters, bf, hipMemcpyDeviceToDevice, c->stream));
+      HIPTRY(hipMemcpyAsync(sflags + 2 * S, c->d.status, bf * (K + 1), hipMemcpyDeviceToDevice, c->stream));
+      HIPTRY(hipMemcpyAsync(smax, c->d.maxdx, sizeof(double) * S, hipMemcpyDeviceToDevice, c->stream));
+    } else {
+      HIPTRY(hipMemcpyAsync(x, sx, sizeof(double2) * nx, hipMemcpyDeviceToDevice, c->stream));
+      HIPTRY(hipMemcpyAsync(c->d.active, sflags, bf, hipMemcpyDeviceToDevice, c->stream));
+      HIPTRY(hipMemcpyAsync(c->d.iters, sflags + S, bf, hipMemcpyDeviceToDevice, c->stream));
+      HIPTRY(hipMemcpyAsync(c->d.status, sflags + 2 * S, bf * (K + 1), hipMemcpyDeviceToDevice, c->stream));
+      HIPTRY(hipMemcpyAsync(c->d.maxdx, smax, sizeof(double) * S, hipMemcpyDeviceToDevice, c->stream));
+    }
+    HIPTRY(hipStreamSynchronize(c->stream));
+    return 0;
+  };
+  if ((rc = save_restore(true))) return rc;
+  const bool snode0 = c->gamma_snode;
+  double best = 1e300;
+  int best_np = c->npipe, best_sn = snode0 ? 1 : 0;
+  for (int snc = 1; snc >= 0; --snc) {
+    if (snc == 1 && !c->snode_possible) continue;
+    for (int npc : {1, 2, 4, 8}) {
+      if (npc > S) continue;
+      if ((rc = reset_graphs(c))) return rc;
+      c->npipe = npc;
+      c->gamma_snode = snc == 1;
+      double t = 0.0;
+      for (int rep = 0; rep < 2; ++rep) {  // the first run captures the graphs
+        if ((rc = save_restore(false))) return rc;
+        const auto t0 = std::chrono::steady_clock::now();
+        if ((rc = solve_batched(c, 2))) return rc;
+        HIPTRY(hipStreamSynchronize(c->stream));
+        t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      }
+      if (t < best) {
+        best = t;
+        best_np = npc;
+        best_sn = snc;
+      }
+    }
+  }
+  if ((rc = reset_graphs(c))) return rc;
+  c->npipe = best_np;
+  c->gamma_snode = best_sn == 1;
+  if ((rc = save_restore(false))) return rc;
+  write_tune_cache(c, best_np, best_sn);
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
 int mase_solve(mase_ctx* c, double tol, int32_t max_iter, int32_t* iters, int32_t* converged) {
   int rc = check_device(c);
   if (rc) return rc;
@@ -677,16 +1006,9 @@ int mase_solve(mase_ctx* c, double tol, int32_t max_iter, int32_t* iters, int32_
   c->h_tol[0] = tol;
   HIPTRY(hipMemcpyAsync(c->dtol, c->h_tol, sizeof(double), hipMemcpyHostToDevice, c->stream));
   if (c->opt.batched) {
-    HIPTRY(hipMemcpyAsync(c->h_active, c->d.active, sizeof(int32_t) * S, hipMemcpyDeviceToHost, c->stream));
-    HIPTRY(hipStreamSynchronize(c->stream));
-    int nact = 0;
-    for (int s = 0; s < S; ++s) nact += c->h_active[s] != 0;
-    for (int it = 0; it < max_iter && nact > 0; ++it) {
-      rc = mase_gn_iter(c, nullptr);
-      if (rc) return rc;
-      nact = 0;
-      for (int s = 0; s < S; ++s) nact += c->h_active[s] != 0;
-    }
+    if (c->opt.autotune && !c->tuned && c->opt.use_graph && !c->prof)
+      if ((rc = autotune(c))) return rc;
+    if ((rc = solve_batched(c, max_iter))) return rc;
   } else {
     // plain schedule: one snapshot at a time, to convergence
     HIPTRY(hipMemcpyAsync(c->h_active, c->d.active, sizeof(int32_t) * S, hipMemcpyDeviceToHost, c->stream));
@@ -814,6 +1136,9 @@ int mase_info(const mase_ctx* c, int32_t what, int64_t* value) {
     case MASE_INFO_BYTES_BACKSOLVE: v = (int64_t)p.bytes_backsolve(); break;
     case MASE_INFO_FLOPS_GAMMA_SPARSE: v = (int64_t)p.sys[p.n_area].elim_flops(); break;
     case MASE_INFO_GAMMA_LEVELS: v = p.sys[p.n_area].nlev; break;
+    case MASE_INFO_GAMMA_SUPERNODES: v = (int64_t)p.sys[p.n_area].sn.size(); break;
+    case MASE_INFO_GAMMA_SUPERNODAL: v = c->gamma_snode ? 1 : 0; break;
+    case MASE_INFO_PIPELINE_GROUPS: v = c->npipe; break;
     default: return fail(MASE_ERR_ARG, "unknown info key");
   }
   *value = v;

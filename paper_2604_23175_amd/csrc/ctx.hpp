@@ -35,6 +35,20 @@ struct mase_ctx {
   bool have_z = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  // pipelined solve: snapshot groups [pg_s0[g], pg_s0[g+1]) iterate on their
+  // own streams; area stages of all groups share pstream_area
+  int npipe = 1;
+  std::vector<int> pg_s0;
+  hipStream_t pstream_area = nullptr;
+  std::vector<hipStream_t> pstream;
+  std::vector<hipEvent_t> pev_a, pev_b;
+  std::vector<hipGraph_t> pgraphs;
+  std::vector<hipGraphExec_t> pgA, pgB;
+  // autotuner
+  bool tuned = false;
+  bool snode_possible = false;
+  std::string tune_path;
+  std::string tune_key;
   int32_t* h_active = nullptr;
   int32_t* h_status = nullptr;
   int32_t* h_iters = nullptr;

@@ -146,6 +146,16 @@ __device__ inline double block_sum(double v, double* red) {
   return t;
 }
 
+// Orders one wave's LDS writes before its following LDS reads across lanes.
+// Lanes exchanging values through LDS is a data race in the language's model,
+// so without this the compiler may, for instance, run the reading lanes of a
+// divergent branch before the writing ones.
+__device__ __attribute__((always_inline)) inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Value of v held by lane src (uniform across the wave) via the scalar unit.
 __device__ inline double bcast_lane(double v, int src) {
   const long long b = __double_as_longlong(v);
@@ -155,71 +165,69 @@ __device__ inline double bcast_lane(double v, int src) {
 }
 
 // Cholesky of the 16x16 diagonal block at (cb, cb) of the column-major LDS
-// matrix P (pitch ldp) by one wave, the forward solve of y[cb .. cb+15], and
-// the inverse of the factor: lane r (mod 16) holds row r; each finished column
-// of L is shared through colbuf (16 doubles of LDS; a wave's LDS accesses
-// complete in order).  L goes back to P; Linv (row-major, pitch 17, zero
-// above the diagonal) receives L^-1, which turns the solves against L below
-// the block into products on MFMA.  A non-positive pivot is replaced by 1 and
-// reported by returning false.
-__device__ __attribute__((always_inline)) inline bool wave_chol16_inv(double* P, int ldp, int cb, double* y, double* colbuf,
-                                       double* Linv) {
+// matrix P (pitch ldp) by one wave, with the forward solve of y[cb .. cb+15]
+// and the inverse X = L^-1 built alongside: lane r (mod 16) holds row r of L
+// and row r of X.  At step c, column c of L and row c of X are final; both are
+// shared through LDS (xbuf: 16 + 16 doubles) and every lower row subtracts its
+// multiple of them.  The step is branch-free: entries above the diagonal of a
+// lane's row of L pick up values that are never read or stored, and a
+// row's factor is zero where it must not change.  1/sqrt of the pivot comes
+// from the hardware estimate refined by two Newton steps.  L goes back to P;
+// Linv (row-major, pitch 17, zero above the diagonal) receives X, which turns
+// the solves against L below the block into products on MFMA.  A non-positive
+// pivot is replaced by 1 and reported by returning false.
+__device__ __attribute__((always_inline)) inline bool wave_chol16_inv(double* P, int ldp, int cb, double* y,
+                                                                      double* xbuf, double* Linv) {
   const int lane = threadIdx.x & 63;
   int rr = lane & 15;
   asm volatile("" : "+v"(rr));  // per-lane predicates stay here, not hoisted into the caller
-  double a[16];
+  double a[16], x[16];
 #pragma unroll
-  for (int m = 0; m < 16; ++m) a[m] = (m <= rr) ? P[(cb + m) * ldp + cb + rr] : 0.0;
+  for (int m = 0; m < 16; ++m) {
+    a[m] = (m <= rr) ? P[(cb + m) * ldp + cb + rr] : 0.0;
+    x[m] = (m == rr) ? 1.0 : 0.0;
+  }
   double yr = y[cb + rr];
-  double dinv = 1.0;
   bool ok = true;
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
-    const double piv = bcast_lane(a[c], c);
-    double sd = 1.0;
-    if (piv > 0.0) sd = sqrt(piv);
-    else ok = false;
-    const double inv = 1.0 / sd;
-    if (rr == c) {
-      a[c] = sd;
-      dinv = inv;
-      yr *= inv;
-    } else if (rr > c) {
-      a[c] *= inv;
+    double piv = bcast_lane(a[c], c);
+    if (!(piv > 0.0)) {
+      ok = false;
+      piv = 1.0;
     }
+    double inv = __builtin_amdgcn_rsq(piv);
+    inv = inv * (1.5 - 0.5 * piv * inv * inv);
+    inv = inv * (1.5 - 0.5 * piv * inv * inv);
+    const bool own = (rr == c), below = (rr > c);
+    const double scale = own ? inv : 1.0;
+    a[c] = own ? piv * inv : (below ? a[c] * inv : a[c]);
+    yr *= scale;
+#pragma unroll
+    for (int m = 0; m <= c; ++m) x[m] *= scale;
     const double yc = bcast_lane(yr, c);
-    if (rr > c) yr -= a[c] * yc;
-    if (c < 15) {
-      if (lane < 16) colbuf[rr] = a[c];
-      double col[16];
+    const double f = below ? a[c] : 0.0;  // L[r][c] for the rows that update
+    yr -= f * yc;
+    // column c of L (entries below c) and row c of X
+    wave_lds_sync();  // the previous step's reads are done
+    if (lane < 16) xbuf[rr] = a[c];
+    if (lane == c) {
 #pragma unroll
-      for (int m = c + 1; m < 16; ++m) col[m] = colbuf[m];
-#pragma unroll
-      for (int m = c + 1; m < 16; ++m)
-        if (rr >= m) a[m] -= a[c] * col[m];
+      for (int m = 0; m <= c; ++m) xbuf[16 + m] = x[m];
     }
+    wave_lds_sync();
+#pragma unroll
+    for (int m = c + 1; m < 16; ++m) a[m] -= a[c] * xbuf[m];
+#pragma unroll
+    for (int m = 0; m <= c; ++m) x[m] -= f * xbuf[16 + m];
   }
   if (lane < 16) {
 #pragma unroll
-    for (int m = 0; m < 16; ++m)
+    for (int m = 0; m < 16; ++m) {
       if (m <= rr) P[(cb + m) * ldp + cb + rr] = a[m];
+      Linv[rr * 17 + m] = x[m];
+    }
     y[cb + rr] = yr;
-    colbuf[rr] = dinv;
-  }
-  // column j = rr of L^-1: z_j = 1 / L_jj, z_i = -(sum_{j <= m < i} L_im z_m) / L_ii
-  double z[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    double t = 0.0;
-#pragma unroll
-    for (int m = 0; m < i; ++m)
-      if (m >= rr) t += P[(cb + m) * ldp + cb + i] * z[m];
-    const double di = colbuf[i];
-    z[i] = (i == rr) ? di : (i > rr) ? -t * di : 0.0;
-  }
-  if (lane < 16) {
-#pragma unroll
-    for (int i = 0; i < 16; ++i) Linv[i * 17 + rr] = z[i];
   }
   return ok;
 }
@@ -624,7 +632,7 @@ __global__ void __launch_bounds__(DENSE_NT) k_dense_chol(Dev d, int s0) {
   double* Lp = bl + n;            // [n - 16][PANEL_PITCH]: rows below the diagonal block
   __shared__ double Dk[16 * 17];    // diagonal block, column-major, pitch 17
   __shared__ double Linv[16 * 17];  // its inverse factor, row-major
-  __shared__ double colbuf[16];
+  __shared__ double xbuf[32];
   __shared__ double part[16 * 16];
   __shared__ int bad;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -646,7 +654,7 @@ __global__ void __launch_bounds__(DENSE_NT) k_dense_chol(Dev d, int s0) {
     }
     __syncthreads();
     if (wv == 0) {
-      const bool ok = wave_chol16_inv(Dk, 17, 0, bl + c0, colbuf, Linv);
+      const bool ok = wave_chol16_inv(Dk, 17, 0, bl + c0, xbuf, Linv);
       if (!ok && lane == 0) bad = 1;
     }
     __syncthreads();
@@ -810,7 +818,7 @@ __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
   double* rhs = d.rhs + (int64_t)s * d.rstride + g.rhs_off;
   extern __shared__ double sl[];
   __shared__ double Linv[16 * 17];
-  __shared__ double colbuf[16];
+  __shared__ double xbuf[32];
   __shared__ int bad;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   constexpr int NW = SN_NT / 64, UL = 8, TB = 4;
@@ -854,7 +862,7 @@ __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
     // (2) blocked Cholesky of the panel and forward solve
     for (int cb = 0; cb < Wp; cb += 16) {
       if (wv == 0) {
-        const bool ok = wave_chol16_inv(P, M, cb, yv, colbuf, Linv);
+        const bool ok = wave_chol16_inv(P, M, cb, yv, xbuf, Linv);
         if (!ok && lane == 0) bad = 1;
       }
       __syncthreads();

@@ -24,7 +24,7 @@ MASE_GAMMA_SPARSE, MASE_GAMMA_DENSE = 0, 1
 INFO = {"n_gamma": 0, "n_boundary_bus": 1, "gamma_tail": 2, "nnz_factor": 3, "max_levels": 4,
         "flops_local": 5, "flops_gamma": 6, "bytes_assembly": 7, "n_snap": 8, "n_area": 9,
         "bytes_condense": 10, "flops_dense": 11, "bytes_backsolve": 12, "flops_gamma_sparse": 13,
-        "gamma_levels": 14}
+        "gamma_levels": 14, "gamma_supernodes": 15, "gamma_supernodal": 16, "pipeline_groups": 17}
 STAGES = ("assemble", "condense", "gamma_gather", "gamma_sparse", "gamma_dense", "gamma_back",
           "backsolve", "update")
 MAPS = {"boundary_flag": 0, "meas_area": 1, "gamma_vars": 2, "local_vars": 3,
@@ -55,7 +55,7 @@ class Options(ctypes.Structure):
     _fields_ = [("stream", ctypes.c_void_p), ("batched", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("gamma_mode", ctypes.c_int32),
                 ("host_only", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("tune_cache", ctypes.c_char_p)]
+                ("tune_cache", ctypes.c_char_p), ("pipeline_groups", ctypes.c_int32)]
 
 
 _lib = None
@@ -185,13 +185,18 @@ class Mase:
 
     def __init__(self, n_bus, br_from, br_to, br_r, br_x, br_b, slack_bus, n_area, bus_area,
                  meas_type, meas_at, meas_sigma, n_snap, batched=True, use_graph=True,
-                 gamma_mode=MASE_GAMMA_SPARSE, host_only=False, stream=None):
+                 gamma_mode=MASE_GAMMA_SPARSE, host_only=False, stream=None, pipeline_groups=0,
+                 autotune=False, tune_cache=None):
         self.lib = load()
         o = mase_default_options()
         o.batched = int(bool(batched))
         o.use_graph = int(bool(use_graph))
         o.gamma_mode = int(gamma_mode)
         o.host_only = int(bool(host_only))
+        o.pipeline_groups = int(pipeline_groups)
+        o.autotune = int(bool(autotune))
+        self._tune_cache = None if tune_cache is None else str(tune_cache).encode()
+        o.tune_cache = self._tune_cache
         o.stream = stream
         self.n_bus = int(n_bus)
         self.n_meas = int(np.asarray(meas_type).size)

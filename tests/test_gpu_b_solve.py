@@ -68,6 +68,57 @@ def test_schedules_bitwise_identical():
         np.testing.assert_array_equal(it, out[0][1])
 
 
+@pytest.mark.parametrize("name,n_snap,groups", [("k5", 3, 3), ("c1", 8, 4), ("c1", 7, 2)])
+def test_pipelined_groups_bitwise_identical(name, n_snap, groups):
+    # mase_solve with snapshot groups iterating on their own streams runs the
+    # same kernels per snapshot as the one-group schedule
+    say("pipeline groups", name, n_snap, groups)
+    c = Case(name, n_snap, seed=13)
+    out = []
+    for g in (1, groups):
+        m = c.ctx(pipeline_groups=g)
+        iters, conv = m.mase_solve(1e-8, 10)
+        out.append((m.mase_state(), iters, conv))
+        # a second solve from the converged state: every group stops at once
+        it2, conv2 = m.mase_solve(1e-8, 10)
+        assert conv2.all() and (it2 == iters).all()
+        m.close()
+    np.testing.assert_array_equal(out[1][0][0], out[0][0][0])
+    np.testing.assert_array_equal(out[1][0][1], out[0][0][1])
+    np.testing.assert_array_equal(out[1][1], out[0][1])
+    np.testing.assert_array_equal(out[1][2], out[0][2])
+    assert out[0][2].all()
+
+
+def test_autotune_choice_cached_and_results_match(tmp_path):
+    say("autotune")
+    c = Case("c1", 8, seed=14)
+    ref = c.ctx()
+    ref.mase_solve(1e-10, 12)
+    xr = ref.mase_state()
+    ref.close()
+    cache = tmp_path / "tune.txt"
+    m = c.ctx(autotune=True, tune_cache=str(cache))
+    iters, conv = m.mase_solve(1e-10, 12)
+    assert conv.all()
+    x = m.mase_state()
+    assert_state_close(x[0], x[1], xr[0], xr[1], 1e-10)
+    choice = (m.mase_info("pipeline_groups"), m.mase_info("gamma_supernodal"))
+    m.close()
+    lines = [ln.split() for ln in cache.read_text().splitlines() if ln.strip()]
+    assert len(lines) == 1 and len(lines[0]) == 3
+    assert (int(lines[0][1]), int(lines[0][2])) == choice
+    # a second context takes the cached choice without tuning again
+    m2 = c.ctx(autotune=True, tune_cache=str(cache))
+    m2.mase_solve(1e-10, 12)
+    assert (m2.mase_info("pipeline_groups"), m2.mase_info("gamma_supernodal")) == choice
+    x2 = m2.mase_state()
+    np.testing.assert_array_equal(x2[0], x[0])
+    np.testing.assert_array_equal(x2[1], x[1])
+    m2.close()
+    assert len([ln for ln in cache.read_text().splitlines() if ln.strip()]) == 1
+
+
 def test_repeat_runs_bitwise_identical():
     say("determinism")
     c = Case("c1", 2, seed=8)
