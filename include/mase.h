@@ -281,7 +281,10 @@ int mase_warm_start(mase_ctx* ctx, mase_mlp* mlp, int32_t* accepted);
  * J(pred) <= J(flat), also J(pred) <= j_cap.  Default +inf (the objective
  * comparison alone).  A caller calibrates it on held-out snapshots when
  * predictions that beat flat start on J still cost Gauss-Newton iterations.
- * j_cap must not be NaN (MASE_ERR_ARG). */
+ * Since J >= 0, a negative cap rejects every prediction, and mase_warm_start
+ * then sets flat start without evaluating the network or the objectives
+ * (mase_warm_start_objectives reports NaN).  j_cap must not be NaN
+ * (MASE_ERR_ARG). */
 int mase_mlp_set_accept_cap(mase_mlp* mlp, double j_cap);
 
 /* J(pred) and J(flat) of every snapshot [n_snap] (host) as evaluated by the

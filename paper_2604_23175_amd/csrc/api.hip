@@ -118,7 +118,7 @@ int upload_plan(mase_ctx* c) {
   std::vector<I4> rowrec;
   std::vector<double> br_g, br_bs, br_hb;
   std::vector<I4> slot;
-  std::vector<I2> rslot;
+  std::vector<I4> rslot;
   std::vector<I4> scon, rcon;  // contributions with their row record inline
   size_t lds = 0;
   for (int k = 0; k < K; ++k) {
@@ -142,14 +142,33 @@ int upload_plan(mase_ctx* c) {
     row_loc.insert(row_loc.end(), t.row_loc.begin(), t.row_loc.end());
     row_meas.insert(row_meas.end(), t.row_meas.begin(), t.row_meas.end());
     for (size_t r = 0; r < t.row_type.size(); ++r) rowrec.push_back({t.row_type[r], t.row_loc[r], t.row_meas[r], 0});
+    // slots in order of decreasing contribution count, so that the lanes of
+    // a wave carry similar loads (each slot writes its own storage)
     a.slot = (int32_t)slot.size();
-    for (const I4& s : t.slot)
-      slot.push_back({s.x, s.y, s.z + (int32_t)scon.size(), s.w + (int32_t)scon.size()});
+    {
+      std::vector<int> ord(t.slot.size());
+      for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
+      std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+        return t.slot[x].w - t.slot[x].z > t.slot[y].w - t.slot[y].z;
+      });
+      for (int i : ord) {
+        const I4& s = t.slot[i];
+        slot.push_back({s.x, s.y, s.z + (int32_t)scon.size(), s.w + (int32_t)scon.size()});
+      }
+    }
     for (const I2& cc : t.scon)
       scon.push_back({t.row_type[cc.x], t.row_loc[cc.x], t.row_meas[cc.x], cc.y});
+    // rhs items {cbeg, cend, bus}, by decreasing contribution count
     a.rslot = (int32_t)rslot.size();
-    for (const I2& s : t.rslot)
-      rslot.push_back({s.x + (int32_t)rcon.size(), s.y + (int32_t)rcon.size()});
+    {
+      std::vector<int> ord(t.rslot.size());
+      for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
+      std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+        return t.rslot[x].y - t.rslot[x].x > t.rslot[y].y - t.rslot[y].x;
+      });
+      for (int v : ord)
+        rslot.push_back({t.rslot[v].x + (int32_t)rcon.size(), t.rslot[v].y + (int32_t)rcon.size(), v, 0});
+    }
     for (const I2& cc : t.rcon)
       rcon.push_back({t.row_type[cc.x], t.row_loc[cc.x], t.row_meas[cc.x], cc.y});
     a.tail_src = p.tail_src_ptr[k];

@@ -389,12 +389,15 @@ __global__ void __launch_bounds__(ASM_NT) k_assemble(Dev d, int a0, int na, int 
     o[stride] = c01;
     o[stride + 1] = c11;
   }
-  // b^k = H^T W r
+  // b^k = H^T W r: L lanes per bus (fixed per area, so the sum order is
+  // fixed), buses in order of decreasing contribution count
   double* rhs = d.rhs + (int64_t)s * d.rstride + sm.rhs_off;
-  for (int v = tid; v < am.nn; v += nt) {
-    const int2 rs = d.rslot[am.rslot + v];
+  const int L = (4 * am.nn <= nt) ? 4 : (2 * am.nn <= nt) ? 2 : 1;
+  const int sub = tid % L;
+  for (int i0 = tid / L; i0 < am.nn; i0 += nt / L) {
+    const int4 rs = d.rslot[am.rslot + i0];
     double b0 = 0, b1 = 0;
-    for (int c = rs.x; c < rs.y; ++c) {
+    for (int c = rs.x + sub; c < rs.y; c += L) {
       const int4 cr = d.rcon[c];
       double h, pt, pv, qt, qv;
       X.eval2(cr, cr.w, cr.w, h, pt, pv, qt, qv);
@@ -402,8 +405,14 @@ __global__ void __launch_bounds__(ASM_NT) k_assemble(Dev d, int a0, int na, int 
       b0 += pt * wres;
       b1 += pv * wres;
     }
-    rhs[2 * v] = b0;
-    rhs[2 * v + 1] = b1;
+    for (int off = 1; off < L; off <<= 1) {
+      b0 += __shfl_xor(b0, off, 64);
+      b1 += __shfl_xor(b1, off, 64);
+    }
+    if (sub == 0) {
+      rhs[2 * rs.z] = b0;
+      rhs[2 * rs.z + 1] = b1;
+    }
   }
 }
 
@@ -791,17 +800,19 @@ constexpr int SN_NT = 512;
 // b of w, block kk of that column (0: the diagonal block, then the own buses
 // below it, then R), element e of the column-major 2x2 block.
 // Column b starts at f(b) = 4 b (w + r) - 2 b (b - 1) = b (B - 2 b) with
-// B = 4 (w + r) + 2; b is the largest root bound of f(b) <= i, refined by one
-// step each way after the floating-point estimate.
+// B = 4 (w + r) + 2, increasing in b; b is found by binary search (w <= 32).
 __device__ inline void sn_coords(int i, int w, int r, int Wp, int& rowv, int& colv, int& kk, int& e,
                                  int& bb) {
   const int B = 4 * (w + r) + 2;
-  const double disc = (double)B * B - 8.0 * i;
-  bb = (int)((B - sqrt(disc > 0.0 ? disc : 0.0)) * 0.25);
-  if (bb < 0) bb = 0;
-  if (bb > w - 1) bb = w - 1;
-  while (bb > 0 && bb * (B - 2 * bb) > i) --bb;
-  while (bb < w - 1 && (bb + 1) * (B - 2 * (bb + 1)) <= i) ++bb;
+  int lo = 0, hi = w - 1;  // largest b with f(b) <= i
+#pragma unroll
+  for (int it = 0; it < 5; ++it) {
+    const int mid = (lo + hi + 1) >> 1;
+    const bool le = mid * (B - 2 * mid) <= i;
+    lo = le ? mid : lo;
+    hi = le ? hi : mid - 1;
+  }
+  bb = lo;
   const int st = bb * (B - 2 * bb);
   kk = (i - st) >> 2;
   e = (i - st) & 3;
@@ -913,7 +924,24 @@ __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
       }
       __syncthreads();
     }
-    // (3) Schur update of the R x R blocks: tiles (I >= J) of the R rows.  A
+    // (3) factor and forward-solved rhs back to HBM (issued before the Schur
+    // update, so that the stores drain while it computes)
+    for (int i = tid; i < T; i += SN_NT) {
+      int rowv, colv, kk, e, bb;
+      sn_coords(i, w, r, Wp, rowv, colv, kk, e, bb);
+      double val;
+      if (kk == 0) {
+        const double l00 = P[(2 * bb) * M + 2 * bb], l10 = P[(2 * bb) * M + 2 * bb + 1];
+        const double l11 = P[(2 * bb + 1) * M + 2 * bb + 1];
+        val = (e == 0) ? l00 * l00 : (e == 3) ? l10 * l10 + l11 * l11 : l10 * l00;
+      } else {
+        val = P[colv * M + rowv];
+      }
+      vals[sn2.x + i] = val;
+    }
+    for (int i = tid; i < W; i += SN_NT) rhs[2 * c0 + i] = yv[i];
+    for (int i = tid; i < 2 * r; i += SN_NT) rhs[2 * d.sn_rows[rb + (i >> 1)] + (i & 1)] = yv[Wp + i];
+    // (4) Schur update of the R x R blocks: tiles (I >= J) of the R rows.  A
     // wave computes TB tiles, then loads all their targets, then stores, so
     // the read-modify-write round trips overlap.
     const int nr = (M - Wp) / 16, nt3 = nr * (nr + 1) / 2;
@@ -961,22 +989,6 @@ __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
         for (int e = 0; e < 4; ++e)
           if (idx[b][e] >= 0) vals[idx[b][e]] = old[b][e] - acc[b][e];
     }
-    // (4) factor and forward-solved rhs back to HBM
-    for (int i = tid; i < T; i += SN_NT) {
-      int rowv, colv, kk, e, bb;
-      sn_coords(i, w, r, Wp, rowv, colv, kk, e, bb);
-      double val;
-      if (kk == 0) {
-        const double l00 = P[(2 * bb) * M + 2 * bb], l10 = P[(2 * bb) * M + 2 * bb + 1];
-        const double l11 = P[(2 * bb + 1) * M + 2 * bb + 1];
-        val = (e == 0) ? l00 * l00 : (e == 3) ? l10 * l10 + l11 * l11 : l10 * l00;
-      } else {
-        val = P[colv * M + rowv];
-      }
-      vals[sn2.x + i] = val;
-    }
-    for (int i = tid; i < W; i += SN_NT) rhs[2 * c0 + i] = yv[i];
-    for (int i = tid; i < 2 * r; i += SN_NT) rhs[2 * d.sn_rows[rb + (i >> 1)] + (i & 1)] = yv[Wp + i];
     __syncthreads();
   }
   if (tid == 0 && bad) d.status[(int64_t)s * (d.n_area + 1) + d.n_area] = 1;

@@ -660,6 +660,16 @@ int mase_warm_start(mase_ctx* c, mase_mlp* m, int32_t* accepted) {
   if (rc) return rc;
   if (!c->have_z) return fail(MASE_ERR_STATE, "no measurements set");
   hipStream_t st = c->stream;
+  if (m->j_cap < 0.0) {
+    // J >= 0, so no prediction can pass a negative cap: flat start for every
+    // snapshot without evaluating the network or the objectives
+    HIPTRY(launch_pack_state(c->d, nullptr, nullptr, c->d.x, st));
+    HIPTRY(launch_reset_flags(c->d, st));
+    for (int s = 0; s < S; ++s) c->h_active[s] = 1;
+    m->last_ws = -S;
+    if (accepted) std::memset(accepted, 0, sizeof(int32_t) * S);
+    return 0;
+  }
   if ((rc = forward(m, c->d.z, S))) return rc;
   const long long nout = (long long)S * m->n_out;
   hipLaunchKernelGGL(k_mlp_compose, dim3(nblk(nout)), dim3(256), 0, st, m->Y, S, m->n_out, m->n_bus,
@@ -692,6 +702,10 @@ int mase_mlp_set_accept_cap(mase_mlp* m, double j_cap) {
 int mase_warm_start_objectives(const mase_mlp* m, double* j_pred, double* j_flat) {
   if (!m || !j_pred || !j_flat) return fail(MASE_ERR_ARG, "null argument");
   if (m->last_ws == 0) return fail(MASE_ERR_STATE, "no warm start evaluated yet");
+  if (m->last_ws < 0) {  // short-circuited by a negative cap: nothing evaluated
+    for (int s = 0; s < -m->last_ws; ++s) j_pred[s] = j_flat[s] = std::nan("");
+    return 0;
+  }
   const int S = m->last_ws, K = m->ctx->plan.n_area;
   std::vector<double> jp((size_t)S * K), jf((size_t)S * K);
   HIPTRY(hipStreamSynchronize(m->ctx->stream));

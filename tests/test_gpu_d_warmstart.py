@@ -145,6 +145,10 @@ def test_warm_start_acceptance_rule_and_fallback():
     np.testing.assert_array_equal(mase.mase_warm_start(ctx, M), (jp <= jf) & (jp <= cap))
     M.mase_mlp_set_accept_cap(float("-inf"))
     assert not mase.mase_warm_start(ctx, M).any()
+    # a negative cap short-circuits: flat start, nothing evaluated
+    assert np.isnan(M.mase_warm_start_objectives()[0]).all()
+    it_neg, _ = ctx.mase_solve(1e-6, 10)
+    np.testing.assert_array_equal(it_neg, it_flat)
     with pytest.raises(mase.MaseError):
         M.mase_mlp_set_accept_cap(float("nan"))
     M.mase_mlp_set_accept_cap(float("inf"))
