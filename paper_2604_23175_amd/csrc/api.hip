@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "dev.hpp"
@@ -120,6 +121,7 @@ int upload_plan(mase_ctx* c) {
   std::vector<I4> slot;
   std::vector<I4> rslot;
   std::vector<I4> scon, rcon;  // contributions with their row record inline
+  std::vector<int32_t> slot_rhs;  // per slot: 2 v for the diagonal slot of bus v, else -1
   size_t lds = 0;
   for (int k = 0; k < K; ++k) {
     const AreaTemplates& t = p.tpl[k];
@@ -151,9 +153,14 @@ int upload_plan(mase_ctx* c) {
       std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
         return t.slot[x].w - t.slot[x].z > t.slot[y].w - t.slot[y].z;
       });
+      // a diagonal slot (v, v) also yields b_v: its contributions with equal
+      // roles are exactly bus v's rhs contributions, in the same order
+      std::unordered_map<int32_t, int32_t> diag_bus;
+      for (int v = 0; v < p.sys[k].nn; ++v) diag_bus[p.sys[k].blk_off(v, v)] = v;
       for (int i : ord) {
         const I4& s = t.slot[i];
         slot.push_back({s.x, s.y, s.z + (int32_t)scon.size(), s.w + (int32_t)scon.size()});
+        slot_rhs.push_back(s.y < 0 ? 2 * diag_bus.at(s.x) : -1);
       }
     }
     for (const I2& cc : t.scon)
@@ -220,7 +227,7 @@ int upload_plan(mase_ctx* c) {
   UP(br_lf, br_lf); UP(br_lt, br_lt); UP(br_g, br_g); UP(br_bs, br_bs); UP(br_hb, br_hb);
   UP(inc_ptr, inc_ptr); UP(inc_end, inc_end);
   UP(row_type, row_type); UP(row_loc, row_loc); UP(row_meas, row_meas); UP(rowrec, rowrec);
-  UP(slot, slot); UP(scon, scon); UP(rslot, rslot); UP(rcon, rcon);
+  UP(slot, slot); UP(scon, scon); UP(rslot, rslot); UP(rcon, rcon); UP(slot_rhs, slot_rhs);
   UP(cd_ptr, cd_ptr); UP(up_ptr, up_ptr); UP(rb_ptr, rb_ptr); UP(bs_ptr, bs_ptr);
   UP(cd_items, cd_items); UP(up_tgt, up_tgt); UP(up_con, up_con);
   UP(rb_tgt, rb_tgt); UP(rb_con, rb_con); UP(bs_items, bs_items); UP(bs_con, bs_con);

@@ -45,6 +45,7 @@ struct Dev {
   const int4* slot;
   const int4* scon;   // per G-slot contribution: {type, loc, meas, role_p | role_q << 16}
   const int4* rslot;  // per area rhs item: {cbeg, cend, local bus, 0}
+  const int32_t* slot_rhs;  // per slot: rhs offset 2 v of a diagonal slot (v, v), else -1
   const int4* rcon;   // per rhs contribution: {type, loc, meas, role}
   const int32_t *cd_ptr, *up_ptr, *rb_ptr, *bs_ptr;
   const int4* cd_items;

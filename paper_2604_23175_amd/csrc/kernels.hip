@@ -350,28 +350,42 @@ __global__ void __launch_bounds__(ASM_NT) k_assemble(Dev d, int a0, int na, int 
   if (tid == 0) d.jpart[(int64_t)s * d.n_area + k] = jt;
   if (mode == MODE_OBJECTIVE) return;
 
-  // G^k slots: slot += w * h_p h_q^T over the slot's contributions
+  // G^k slots: slot += w * h_p h_q^T over the slot's contributions.  The
+  // diagonal slot (v, v) also sums b_v = sum w r h_v (Eq. 7) over its
+  // contributions with equal roles, which are exactly bus v's rows.
   double* vals = d.vals + (int64_t)s * d.vstride + sm.val_off;
+  double* rhs = d.rhs + (int64_t)s * d.rstride + sm.rhs_off;
   for (int i = tid; i < am.nslot; i += nt) {
     const int4 sl = d.slot[am.slot + i];
-    double c00 = 0, c10 = 0, c01 = 0, c11 = 0;
-    // two-stage prefetch: the record of contribution c+2 and the weight of
-    // c+1 are in flight while c is evaluated
+    const int rb2 = d.slot_rhs[am.slot + i];
+    double c00 = 0, c10 = 0, c01 = 0, c11 = 0, b0 = 0, b1 = 0;
+    // two-stage prefetch: the record of contribution c+2 and the weight (and
+    // measurement) of c+1 are in flight while c is evaluated
     int4 r0 = make_int4(0, 0, 0, 0), r1 = r0;
-    double w0 = 0.0;
+    double w0 = 0.0, z0 = 0.0;
     if (sl.z < sl.w) {
       r0 = d.scon[sl.z];
       w0 = d.w[r0.z];
+      if (rb2 >= 0) z0 = zs[r0.z];
     }
     if (sl.z + 1 < sl.w) r1 = d.scon[sl.z + 1];
     for (int c = sl.z; c < sl.w; ++c) {
       const int4 cr = r0;
-      const double wr = w0;
+      const double wr = w0, zr = z0;
       r0 = r1;
-      if (c + 1 < sl.w) w0 = d.w[r1.z];
+      if (c + 1 < sl.w) {
+        w0 = d.w[r1.z];
+        if (rb2 >= 0) z0 = zs[r1.z];
+      }
       if (c + 2 < sl.w) r1 = d.scon[c + 2];
+      const int rp = cr.w & 0xFFFF, rq = (cr.w >> 16) & 0xFFFF;
       double h, pt, pv, qt, qv;
-      X.eval2(cr, cr.w & 0xFFFF, (cr.w >> 16) & 0xFFFF, h, pt, pv, qt, qv);
+      X.eval2(cr, rp, rq, h, pt, pv, qt, qv);
+      if (rb2 >= 0 && rp == rq) {
+        const double wres = wr * (zr - h);
+        b0 += pt * wres;
+        b1 += pv * wres;
+      }
       pt *= wr;
       pv *= wr;
       c00 += pt * qt;
@@ -388,30 +402,9 @@ __global__ void __launch_bounds__(ASM_NT) k_assemble(Dev d, int a0, int na, int 
     o[1] = c10;
     o[stride] = c01;
     o[stride + 1] = c11;
-  }
-  // b^k = H^T W r: L lanes per bus (fixed per area, so the sum order is
-  // fixed), buses in order of decreasing contribution count
-  double* rhs = d.rhs + (int64_t)s * d.rstride + sm.rhs_off;
-  const int L = (4 * am.nn <= nt) ? 4 : (2 * am.nn <= nt) ? 2 : 1;
-  const int sub = tid % L;
-  for (int i0 = tid / L; i0 < am.nn; i0 += nt / L) {
-    const int4 rs = d.rslot[am.rslot + i0];
-    double b0 = 0, b1 = 0;
-    for (int c = rs.x + sub; c < rs.y; c += L) {
-      const int4 cr = d.rcon[c];
-      double h, pt, pv, qt, qv;
-      X.eval2(cr, cr.w, cr.w, h, pt, pv, qt, qv);
-      const double wres = d.w[cr.z] * (zs[cr.z] - h);
-      b0 += pt * wres;
-      b1 += pv * wres;
-    }
-    for (int off = 1; off < L; off <<= 1) {
-      b0 += __shfl_xor(b0, off, 64);
-      b1 += __shfl_xor(b1, off, 64);
-    }
-    if (sub == 0) {
-      rhs[2 * rs.z] = b0;
-      rhs[2 * rs.z + 1] = b1;
+    if (rb2 >= 0) {
+      rhs[rb2] = b0;
+      rhs[rb2 + 1] = b1;
     }
   }
 }
