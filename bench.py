@@ -87,6 +87,118 @@ def traffic_for(kernel):
     return ent.get("bytes_per_launch")
 
 
+def k_sweep(ks, steps, warmup):
+    """Partition-count sweep on the benchmark grid (same buses, branches, states and
+    noise; only the partition changes): boundary size, snapshots/s and the share of
+    the boundary stages in the per-stage event timings."""
+    import dataclasses
+    import numpy as np
+    import torch
+    from gridgen import synth
+    from paper_2604_23175_amd import mase
+    dev = torch.device("cuda:0")
+    g0, t, a, s, vm_true, va_true, eps = make_inputs(N_SNAP)
+    gamma_stages = ("gamma_gather", "gamma_sparse", "gamma_dense", "gamma_back")
+    for k in ks:
+        g = dataclasses.replace(g0, n_area=k, bus_area=synth.partition(g0.pos, g0.br_from, g0.br_to, k, "plain"))
+        sizes = np.bincount(g.bus_area, minlength=k)
+        rec = {"n_area": k, "area_buses_min": int(sizes.min()), "area_buses_max": int(sizes.max())}
+        try:
+            ctx = mase.Mase.from_grid(g, t, a, s, N_SNAP)
+        except mase.MaseError as e:
+            rec["error"] = str(e)
+            print(json.dumps(rec), flush=True)
+            continue
+        vmt = torch.tensor(vm_true, device=dev)
+        vat = torch.tensor(va_true, device=dev)
+        h = torch.empty((N_SNAP, t.size), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        ctx.mase_eval_h_dev(vmt, vat, h)
+        torch.cuda.synchronize()
+        z = h + torch.tensor(s, device=dev) * torch.tensor(eps, device=dev)
+        torch.cuda.synchronize()
+        ctx.mase_set_measurements_dev(z)
+        for _ in range(warmup):
+            ctx.mase_set_state_dev(None, None)
+            ctx.mase_solve(TOL, MAX_ITER)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = 0
+        for _ in range(steps):
+            ctx.mase_set_state_dev(None, None)
+            it, conv = ctx.mase_solve(TOL, MAX_ITER)
+            its += int(it.sum())
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ctx.mase_profile(True)
+        for _ in range(steps):
+            ctx.mase_set_state_dev(None, None)
+            ctx.mase_solve(TOL, MAX_ITER)
+        prof = ctx.mase_profile_read()
+        ctx.mase_profile(False)
+        total = sum(v["ms"] for v in prof.values())
+        gam = sum(prof[k2]["ms"] for k2 in gamma_stages if k2 in prof)
+        rec.update({"n_gamma": ctx.mase_info("n_gamma"), "boundary_buses": ctx.mase_info("n_boundary_bus"),
+                    "snapshots_per_s": N_SNAP * steps / dt, "mean_iters": its / (N_SNAP * steps),
+                    "all_converged": bool(conv.all()),
+                    "boundary_share": gam / total if total > 0 else None,
+                    "stages_ms_per_step": {k2: v["ms"] / steps for k2, v in prof.items() if v["launches"]}})
+        print(json.dumps(rec), flush=True)
+        ctx.close()
+
+
+def masking(steps, warmup):
+    """One flow family at a time gets weight 0 (the rows stay in the templates);
+    reports removed rows, convergence, iterations and time per 64-snapshot batch."""
+    import dataclasses
+    import numpy as np
+    import torch
+    from gridgen import synth
+    from paper_2604_23175_amd import mase
+    dev = torch.device("cuda:0")
+    g = synth.make_config("c1")
+    g = dataclasses.replace(g, n_area=6, bus_area=synth.partition(g.pos, g.br_from, g.br_to, 6, "balanced"))
+    t, a, s = synth.measurement_set(g.n_bus, g.n_branch)
+    b = synth.make_batch(g, N_SNAP, 0)
+    va = b.va_true - b.va_true[:, [g.slack]]
+    ctx = mase.Mase.from_grid(g, t, a, s, N_SNAP)
+    h = torch.empty((N_SNAP, t.size), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    ctx.mase_eval_h_dev(torch.tensor(b.vm_true, device=dev), torch.tensor(va, device=dev), h)
+    torch.cuda.synchronize()
+    z = h + torch.tensor(s, device=dev) * torch.tensor(b.eps, device=dev)
+    torch.cuda.synchronize()
+    w0 = 1.0 / np.asarray(s) ** 2
+    for name, ty in (("none", None), ("Pf", mase.MASE_PF), ("Pt", mase.MASE_PT), ("Qf", mase.MASE_QF),
+                     ("Qt", mase.MASE_QT)):
+        w = w0.copy()
+        if ty is not None:
+            w[t == ty] = 0.0
+        wd = torch.tensor(w, device=dev)
+        torch.cuda.synchronize()
+        ctx.mase_set_measurements_dev(z, wd)
+        for _ in range(warmup):
+            ctx.mase_set_state_dev(None, None)
+            ctx.mase_solve(TOL, MAX_ITER)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its, conv_all, max_it = 0, True, 0
+        for _ in range(steps):
+            ctx.mase_set_state_dev(None, None)
+            it, conv = ctx.mase_solve(TOL, MAX_ITER)
+            its += int(it.sum())
+            conv_all &= bool(conv.all())
+            max_it = max(max_it, int(it.max()))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        print(json.dumps({"masked_family": name, "removed_rows": int((w == 0).sum()),
+                          "removed_fraction": float((w == 0).mean()), "all_converged": conv_all,
+                          "mean_iters": its / (N_SNAP * steps), "max_iters": max_it,
+                          "ms_per_batch": 1e3 * dt / steps, "snapshots_per_s": N_SNAP * steps / dt,
+                          "grid": "2869-bus/4582-branch synthetic, 6 areas", "snapshots": N_SNAP}), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,10 +213,22 @@ def main():
     ap.add_argument("--warm-epochs", type=int, default=20)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB 3 times (scale reference for HBM counters)")
+    ap.add_argument("--k-sweep", default=None,
+                    help="comma-separated area counts: re-partition the same grid and report, per count, "
+                         "the boundary size, throughput and the boundary-solve share (one JSON line each)")
+    ap.add_argument("--masking", action="store_true",
+                    help="structured masking experiment on the 2869-bus grid in 6 areas: each flow family "
+                         "(Pf, Pt, Qf, Qt) masked by zero weights in turn (one JSON line each)")
     ap.add_argument("--cpu-leg", type=float, default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_leg is not None:
         cpu_leg(args.cpu_leg)
+        return
+    if args.masking:
+        masking(args.steps, args.warmup)
+        return
+    if args.k_sweep:
+        k_sweep([int(k) for k in args.k_sweep.split(",")], args.steps, args.warmup)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "

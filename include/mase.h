@@ -168,7 +168,9 @@ const char* mase_strerror(int code);
  */
 int mase_set_measurements(mase_ctx* ctx, const double* z, const double* w);
 
-/* Same with device pointers; z_dev is copied on the context's stream. */
+/* Same with device pointers (w_dev NULL: 1/sigma^2); both are copied on the
+ * context's stream, so the caller's buffers must stay valid until that
+ * stream reaches the copy. */
 int mase_set_measurements_dev(mase_ctx* ctx, const double* z_dev, const double* w_dev);
 
 /*

@@ -193,6 +193,13 @@ int upload_plan(mase_ctx* c) {
   }
   c->br_lds = lds_br <= (size_t)maxlds;
   lds = c->br_lds ? lds_br : lds_nobr;
+  if (lds > (size_t)maxlds) {
+    int big = 0;
+    for (int k = 0; k < K; ++k) big = std::max(big, am[k].nn);
+    return fail(MASE_ERR_ARG, "an area of " + std::to_string(big) +
+                                  " buses exceeds the LDS the assembly kernel stages it in (" +
+                                  std::to_string(lds) + " > " + std::to_string(maxlds) + " bytes)");
+  }
   c->lds_asm = lds;
   c->lds_el_area = 0;
   for (int k = 0; k < K; ++k) c->lds_el_area = std::max(c->lds_el_area, 8 * (size_t)p.sys[k].lds_doubles);
@@ -249,6 +256,8 @@ int upload_plan(mase_ctx* c) {
   std::vector<double> w0(p.n_meas);
   for (int i = 0; i < p.n_meas; ++i) w0[i] = 1.0 / (p.sigma[i] * p.sigma[i]);
   HIPTRY(hipMemcpy(w, w0.data(), sizeof(double) * p.n_meas, hipMemcpyHostToDevice));
+  if ((rc = dalloc(c, p.n_meas, &c->w_default))) return rc;
+  HIPTRY(hipMemcpy(c->w_default, w0.data(), sizeof(double) * p.n_meas, hipMemcpyHostToDevice));
   if ((rc = dalloc(c, S * p.n_bus, &d.x))) return rc;
   if ((rc = dalloc(c, S * p.n_bus, &c->xscratch))) return rc;
   if ((rc = dalloc(c, S * p.n_bus, &c->stage_vm))) return rc;
@@ -757,8 +766,9 @@ int mase_set_measurements_dev(mase_ctx* c, const double* z_dev, const double* w_
   const Plan& p = c->plan;
   HIPTRY(hipMemcpyAsync((void*)c->d.z, z_dev, sizeof(double) * (size_t)p.n_snap * p.n_meas,
                         hipMemcpyDeviceToDevice, c->stream));
-  if (w_dev)
-    HIPTRY(hipMemcpyAsync((void*)c->d.w, w_dev, sizeof(double) * p.n_meas, hipMemcpyDeviceToDevice, c->stream));
+  // NULL weights mean 1/sigma^2, as in mase_set_measurements
+  HIPTRY(hipMemcpyAsync((void*)c->d.w, w_dev ? w_dev : c->w_default, sizeof(double) * p.n_meas,
+                        hipMemcpyDeviceToDevice, c->stream));
   c->have_z = true;
   return 0;
 }

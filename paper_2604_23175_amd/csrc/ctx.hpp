@@ -25,6 +25,7 @@ struct mase_ctx {
   double* stage_vm = nullptr;
   double* stage_va = nullptr;
   double* dtol = nullptr;
+  double* w_default = nullptr;  // 1/sigma^2 per measurement (device)
   size_t lds_asm = 0;
   bool br_lds = false;
   size_t lds_el_area = 0, lds_el_gamma = 0;  // elimination staging LDS bytes

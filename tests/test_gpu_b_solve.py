@@ -13,11 +13,14 @@
 """
 import numpy as np
 import pytest
+import torch
 
 from gpu_common import Case, assert_state_close, say
 from gridgen import synth
 from oracle import network as nw
 from paper_2604_23175_amd import mase
+
+DEV = torch.device("cuda:0") if torch.cuda.is_available() else None
 
 pytestmark = pytest.mark.gpu
 
@@ -212,6 +215,38 @@ def test_zero_weight_equals_deleted_row():
     ref = c.oracle_solve(0)
     assert_state_close(vm[0], va[0], ref["vm"], ref["va"], 1e-8)
     m.close()
+
+
+def test_device_weights_and_default_reset():
+    # weights given on the device mask rows like host weights; omitting them
+    # restores 1/sigma^2 (no stale mask)
+    say("device weights")
+    c = Case("k5", 2, seed=7)
+    w = 1.0 / c.s ** 2
+    w[c.t == synth.PT] = 0.0
+    zd = torch.tensor(c.z, device=DEV)
+    m = c.ctx()
+    m.mase_set_measurements_dev(zd, torch.tensor(w, device=DEV))
+    torch.cuda.synchronize()
+    m.mase_set_state()
+    m.mase_solve(1e-10, 12)
+    masked = m.mase_state()
+    m.mase_set_measurements_dev(zd)
+    torch.cuda.synchronize()
+    m.mase_set_state()
+    m.mase_solve(1e-10, 12)
+    plain = m.mase_state()
+    m.close()
+    ref = c.ctx()
+    ref.mase_solve(1e-10, 12)
+    x = ref.mase_state()
+    ref.close()
+    np.testing.assert_array_equal(plain[0], x[0])
+    np.testing.assert_array_equal(plain[1], x[1])
+    c.w = w
+    for i in range(2):
+        o = c.oracle_solve(i, tol=1e-10, max_iter=12)
+        assert_state_close(masked[0][i], masked[1][i], o["vm"], o["va"], 1e-8)
 
 
 def test_unobservable_area_reports_not_posdef():
