@@ -193,12 +193,16 @@ int upload_plan(mase_ctx* c) {
   }
   c->br_lds = lds_br <= (size_t)maxlds;
   lds = c->br_lds ? lds_br : lds_nobr;
+  // an area too large to stage in LDS: every area stages in its own region
+  // of HBM instead (same arithmetic)
+  int64_t asm_stride = 0;
   if (lds > (size_t)maxlds) {
-    int big = 0;
-    for (int k = 0; k < K; ++k) big = std::max(big, am[k].nn);
-    return fail(MASE_ERR_ARG, "an area of " + std::to_string(big) +
-                                  " buses exceeds the LDS the assembly kernel stages it in (" +
-                                  std::to_string(lds) + " > " + std::to_string(maxlds) + " bytes)");
+    for (int k = 0; k < K; ++k) {
+      am[k].stage_off = (int32_t)asm_stride;
+      asm_stride += ((8 * (int64_t)am[k].nn + 2 * (int64_t)am[k].nbr) + 31) / 32 * 32;
+    }
+    c->br_lds = false;
+    lds = 0;
   }
   c->lds_asm = lds;
   c->lds_el_area = 0;
@@ -257,6 +261,9 @@ int upload_plan(mase_ctx* c) {
   for (int i = 0; i < p.n_meas; ++i) w0[i] = 1.0 / (p.sigma[i] * p.sigma[i]);
   HIPTRY(hipMemcpy(w, w0.data(), sizeof(double) * p.n_meas, hipMemcpyHostToDevice));
   if ((rc = dalloc(c, p.n_meas, &c->w_default))) return rc;
+  d.asm_stage = nullptr;
+  d.asm_stride = asm_stride;
+  if (asm_stride > 0 && (rc = dalloc(c, (size_t)(asm_stride * S), &d.asm_stage))) return rc;
   HIPTRY(hipMemcpy(c->w_default, w0.data(), sizeof(double) * p.n_meas, hipMemcpyHostToDevice));
   if ((rc = dalloc(c, S * p.n_bus, &d.x))) return rc;
   if ((rc = dalloc(c, S * p.n_bus, &c->xscratch))) return rc;

@@ -23,7 +23,8 @@ struct SysMeta {
 struct AreaMeta {
   int32_t nn, nbr, nrow, nslot;
   int32_t br, inc_ptr, row, slot;  // first entries in the flattened arrays
-  int32_t rslot, tail_src, slack_local, pad;
+  int32_t rslot, tail_src, slack_local;
+  int32_t stage_off;  // doubles: this area's region in a snapshot's assembly staging (global mode)
 };
 
 enum { MODE_ASSEMBLE = 0, MODE_OBJECTIVE = 1, MODE_EVAL_H = 2 };
@@ -81,6 +82,11 @@ struct Dev {
   int32_t* status;  // [n_snap][n_area + 1]: 1 = non-positive pivot
   double* maxdx;    // [n_snap]
   const double* tol;  // [1]
+  // assembly staging in HBM for areas too large for LDS: per snapshot
+  // asm_stride doubles, area k's states, cos/sin and injection data at
+  // AreaMeta::stage_off (nullptr: staging in LDS)
+  double* asm_stage;
+  int64_t asm_stride;
 };
 
 }  // namespace mase

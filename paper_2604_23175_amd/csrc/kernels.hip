@@ -273,7 +273,7 @@ __device__ inline bool chol2(double a00, double a10, double a11, double& l00, do
 // workgroups, and the gathers are latency-bound, so waves are what hide it.
 constexpr int ASM_NT = 1024;
 
-template <bool BR_LDS>
+template <bool BR_LDS, bool STAGE_HBM>
 __global__ void __launch_bounds__(ASM_NT) k_assemble(Dev d, int a0, int na, int s0, int ns, int mode) {
   int ai, s;
   area_snap_of_block(blockIdx.x, na, ns, ai, s);
@@ -284,7 +284,9 @@ __global__ void __launch_bounds__(ASM_NT) k_assemble(Dev d, int a0, int na, int 
   const SysMeta sm = d.sys[k];
   extern __shared__ double2 lds2[];
   __shared__ double red[16];
-  double2* xs = lds2;
+  // staging: LDS, or (areas too large for it) this block's region of HBM
+  double2* xs = STAGE_HBM ? reinterpret_cast<double2*>(d.asm_stage + (int64_t)s * d.asm_stride + am.stage_off)
+                          : lds2;
   double2* cs = xs + am.nn;
   double* agg = reinterpret_cast<double*>(cs + am.nbr);
   BrL* brl = reinterpret_cast<BrL*>(agg + 6 * am.nn);
@@ -1140,10 +1142,12 @@ size_t assemble_lds_bytes(int nn, int nbr, bool br_lds) {
 hipError_t launch_assemble(const Dev& d, int a0, int na, int s0, int ns, int mode, size_t lds,
                            bool br_lds, hipStream_t st) {
   if (na <= 0 || ns <= 0) return hipSuccess;
-  if (br_lds)
-    hipLaunchKernelGGL(k_assemble<true>, dim3(na * ns), dim3(ASM_NT), lds, st, d, a0, na, s0, ns, mode);
+  if (d.asm_stage)
+    hipLaunchKernelGGL((k_assemble<false, true>), dim3(na * ns), dim3(ASM_NT), 0, st, d, a0, na, s0, ns, mode);
+  else if (br_lds)
+    hipLaunchKernelGGL((k_assemble<true, false>), dim3(na * ns), dim3(ASM_NT), lds, st, d, a0, na, s0, ns, mode);
   else
-    hipLaunchKernelGGL(k_assemble<false>, dim3(na * ns), dim3(ASM_NT), lds, st, d, a0, na, s0, ns, mode);
+    hipLaunchKernelGGL((k_assemble<false, false>), dim3(na * ns), dim3(ASM_NT), lds, st, d, a0, na, s0, ns, mode);
   return hipGetLastError();
 }
 
@@ -1236,9 +1240,9 @@ hipError_t launch_reset_flags(const Dev& d, hipStream_t st) {
 
 hipError_t allow_assemble_lds(size_t bytes, bool br_lds) {
   if (br_lds)
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_assemble<true>),
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_assemble<true, false>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_assemble<false>),
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_assemble<false, false>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 

@@ -249,6 +249,35 @@ def test_device_weights_and_default_reset():
         assert_state_close(masked[0][i], masked[1][i], o["vm"], o["va"], 1e-8)
 
 
+@pytest.mark.parametrize("n_area", [1, 2])
+def test_large_areas_stage_in_hbm(n_area):
+    # areas of ~1400-2900 buses exceed what the assembly kernel can stage in
+    # LDS, so every area stages in HBM; one area means no boundary at all
+    say("large areas", n_area)
+    import dataclasses
+    g = synth.make_config("c1")
+    g = dataclasses.replace(g, n_area=n_area,
+                            bus_area=synth.partition(g.pos, g.br_from, g.br_to, n_area, "balanced"))
+    t, a, s = synth.measurement_set(g.n_bus, g.n_branch)
+    b = synth.make_batch(g, 2, 21)
+    vt = b.va_true - b.va_true[:, [g.slack]]
+    net = nw.from_grid(g, t, a, s)
+    z = np.stack([nw.measurements(net, b.vm_true[i], vt[i], b.eps[i]) for i in range(2)])
+    m = mase.Mase.from_grid(g, t, a, s, 2)
+    m.mase_set_measurements(z)
+    m.mase_set_state()
+    iters, conv = m.mase_solve(1e-10, 12)
+    assert conv.all()
+    vm, va = m.mase_state()
+    if n_area == 1:
+        assert m.mase_info("n_gamma") == 0
+    m.close()
+    from oracle import wls
+    for i in range(2):
+        o = wls.gauss_newton(net, z[i], tol=1e-10, max_iter=12)
+        assert_state_close(vm[i], va[i], o["vm"], o["va"], 1e-8)
+
+
 def test_unobservable_area_reports_not_posdef():
     say("not posdef")
     c = Case("k5", 2, seed=1)
