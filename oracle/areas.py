@@ -165,6 +165,21 @@ class Areas:
         return dx
 
     # ---- symbolic structure --------------------------------------------------
+    def local_step(self, z, vm, va, w=None):
+        """One Gauss-Newton step of every area's local WLS problem with its
+        boundary variables held as parameters (Eq. 6): in the block normal
+        equations (Eq. 7) with dx_b = 0 the first block row gives
+        G_ii^k dx_i^k = b_i^k.  Each internal variable belongs to one area, so
+        the per-area steps combine into one vector; boundary entries stay 0.
+        Oracle column order."""
+        dx = np.zeros(self.net.n)
+        for k in range(self.K):
+            G, b = self.local_system(k, z, vm, va, w)
+            ni = self.n_internal_vars[k]
+            if ni:
+                dx[self.columns(self.local_vars[k][:ni])] = np.linalg.solve(G[:ni, :ni], b[:ni])
+        return dx
+
     def pattern(self, k):
         """Scalar symbolic pattern of G^k as CSR (rowptr, colidx), canonical order.
 

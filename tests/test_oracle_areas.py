@@ -144,3 +144,52 @@ def test_pattern_brute_force(K):
         z = nw.measurements(net, g.vm, g.va, rng.standard_normal(net.m))
         G, _ = A.local_system(k, z, g.vm * 1.01, g.va + 0.01)
         assert not np.any((G != 0) & ~P)
+
+
+# ---- local steps with the boundary fixed (Eq. 6) ------------------------------
+
+def _internal_columns(A):
+    return np.concatenate([A.columns(A.local_vars[k][:A.n_internal_vars[k]]) for k in range(A.K)])
+
+
+@pytest.mark.parametrize("K", [2, 3])
+def test_local_step_is_gn_in_internal_variables(K):
+    # every row that touches an internal variable of area k is owned by area k,
+    # so the per-area steps are the GN step of the centralized problem in the
+    # internal variables with all boundary variables held: checked against the
+    # centralized Jacobian restricted to the internal columns
+    g, net, A, z, vm, va = _case(K, 1)
+    dx = A.local_step(z, vm, va)
+    H = net.jacobian(vm, va)
+    H = H.toarray() if hasattr(H, "toarray") else np.asarray(H)
+    w = 1.0 / net.sigma ** 2
+    r = z - net.h(vm, va)
+    cols = _internal_columns(A)
+    HI = H[:, cols]
+    ref = np.zeros(net.n)
+    ref[cols] = np.linalg.solve(HI.T @ (w[:, None] * HI), HI.T @ (w * r))
+    np.testing.assert_allclose(dx, ref, rtol=1e-9, atol=1e-12)
+    assert (dx[A.columns(A.gamma_vars)] == 0.0).all()
+
+
+def test_local_step_single_area_is_full_gn_step():
+    g, net, A, z, vm, va = _case(1, 0)
+    np.testing.assert_allclose(A.local_step(z, vm, va), wls.gn_step(net, z, vm, va), rtol=1e-9, atol=1e-12)
+
+
+def test_local_steps_reach_local_stationarity():
+    # repeated local steps solve each area's local WLS problem: its gradient in
+    # the internal variables, b_i^k = H_i^T W r, vanishes
+    g, net, A, z, vm, va = _case(3, 2)
+    b0 = [A.local_system(k, z, vm, va)[1][:A.n_internal_vars[k]] for k in range(A.K)]
+    x = net.pack(vm, va)
+    for _ in range(8):
+        x = x + A.local_step(z, *net.unpack(x))
+    vm2, va2 = net.unpack(x)
+    for k in range(A.K):
+        ni = A.n_internal_vars[k]
+        b = A.local_system(k, z, vm2, va2)[1][:ni]
+        assert np.linalg.norm(b) < 1e-8 * np.linalg.norm(b0[k])
+    # the boundary variables never moved
+    cg = A.columns(A.gamma_vars)
+    np.testing.assert_array_equal(x[cg], net.pack(vm, va)[cg])
