@@ -199,6 +199,57 @@ def masking(steps, warmup):
     ctx.close()
 
 
+def local_sweep(ls, steps, warmup):
+    """Local steps with the boundary held (Eq. 6) before each condensed step:
+    per count, outer iterations, time per 64-snapshot batch and the largest
+    deviation of the converged states from those of the plain method (0 local
+    steps), on the 2869-bus grid (6 areas) and on the benchmark grid (32 areas)."""
+    import numpy as np
+    import torch
+    from gridgen import synth
+    from paper_2604_23175_amd import mase
+    dev = torch.device("cuda:0")
+    for gname in ("c1", WORKLOAD):
+        g = synth.make_config(gname)
+        t, a, s = synth.measurement_set(g.n_bus, g.n_branch)
+        b = synth.make_batch(g, N_SNAP, 0)
+        va_t = b.va_true - b.va_true[:, [g.slack]]
+        ref = None
+        for nl in ls:
+            ctx = mase.Mase.from_grid(g, t, a, s, N_SNAP, local_steps=nl)
+            h = torch.empty((N_SNAP, t.size), dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            ctx.mase_eval_h_dev(torch.tensor(b.vm_true, device=dev), torch.tensor(va_t, device=dev), h)
+            torch.cuda.synchronize()
+            z = h + torch.tensor(s, device=dev) * torch.tensor(b.eps, device=dev)
+            torch.cuda.synchronize()
+            ctx.mase_set_measurements_dev(z)
+            for _ in range(warmup):
+                ctx.mase_set_state_dev(None, None)
+                ctx.mase_solve(TOL, MAX_ITER)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            its, max_it, conv_all = 0, 0, True
+            for _ in range(steps):
+                ctx.mase_set_state_dev(None, None)
+                it, conv = ctx.mase_solve(TOL, MAX_ITER)
+                its += int(it.sum())
+                max_it = max(max_it, int(it.max()))
+                conv_all &= bool(conv.all())
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            vm, va = ctx.mase_state()
+            rec = {"grid": f"{g.n_bus}-bus, {g.n_area} areas", "local_steps": nl, "all_converged": conv_all,
+                   "mean_iters": its / (N_SNAP * steps), "max_iters": max_it,
+                   "ms_per_batch": 1e3 * dt / steps, "snapshots_per_s": N_SNAP * steps / dt}
+            if ref is None:
+                ref = (vm, va)
+            else:
+                rec["max_state_dev_vs_plain"] = float(max(np.abs(vm - ref[0]).max(), np.abs(va - ref[1]).max()))
+            print(json.dumps(rec), flush=True)
+            ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -219,6 +270,9 @@ def main():
     ap.add_argument("--masking", action="store_true",
                     help="structured masking experiment on the 2869-bus grid in 6 areas: each flow family "
                          "(Pf, Pt, Qf, Qt) masked by zero weights in turn (one JSON line each)")
+    ap.add_argument("--local-sweep", default=None,
+                    help="comma-separated local-step counts (boundary held, Eq. 6) before each condensed "
+                         "step; the first should be 0 (one JSON line each)")
     ap.add_argument("--cpu-leg", type=float, default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_leg is not None:
@@ -226,6 +280,9 @@ def main():
         return
     if args.masking:
         masking(args.steps, args.warmup)
+        return
+    if args.local_sweep:
+        local_sweep([int(k) for k in args.local_sweep.split(",")], args.steps, args.warmup)
         return
     if args.k_sweep:
         k_sweep([int(k) for k in args.k_sweep.split(",")], args.steps, args.warmup)

@@ -115,6 +115,12 @@ typedef struct {
   const char* tune_cache;/* path of a text file caching that choice per grid
                             structure, batch size and device (read before
                             tuning, appended after), or NULL */
+  int32_t local_steps;    /* Gauss-Newton steps of every area's local problem
+                            with its boundary held (Eq. 6) before each
+                            condensed step: re-assembly, elimination and
+                            back substitution with dx_b = 0, internal
+                            variables only.  Default 0 (every iteration is
+                            one exact GN step); batched mode only */
   int32_t pipeline_groups;/* mase_solve in the batched graph mode: split the
                             snapshots into this many groups that iterate on
                             their own streams, so that one group's boundary
@@ -305,6 +311,7 @@ enum {
   MASE_STAGE_GAMMA_BACK,     /* back substitution inside the boundary system */
   MASE_STAGE_BACKSOLVE,      /* scatter-back + interior recovery (Eq. 8) */
   MASE_STAGE_UPDATE,         /* x += dx, convergence */
+  MASE_STAGE_LOCAL,          /* all kernels of the local steps (mase_options.local_steps) */
   MASE_N_STAGE
 };
 

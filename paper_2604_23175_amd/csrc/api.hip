@@ -316,10 +316,21 @@ struct StageMark {
 
 bool snapshot_bad(const mase_ctx* c, int s);
 
-// Stages 1-2 (assembly, condensation) for snapshots [s0, s0 + ns).
+// Stages 1-2 (assembly, condensation) for snapshots [s0, s0 + ns), after
+// the iteration's local steps (Eq. 6: each area's internal variables take
+// GN steps with its boundary held; same kernels, dx_b = 0).
 int launch_area_part(mase_ctx* c, hipStream_t st, int s0, int ns) {
   const int K = c->plan.n_area;
   const Dev& d = c->d;
+  if (c->opt.local_steps > 0) {
+    StageMark m(c, st, MASE_STAGE_LOCAL);
+    for (int l = 0; l < c->opt.local_steps; ++l) {
+      HIPTRY(launch_assemble(d, 0, K, s0, ns, MODE_ASSEMBLE, c->lds_asm, c->br_lds, st));
+      HIPTRY(launch_eliminate(d, 0, K, s0, ns, c->lds_el_area, st));
+      HIPTRY(launch_backsolve(d, 0, K, s0, ns, st, true));
+      HIPTRY(launch_update(d, s0, ns, st, true));
+    }
+  }
   {
     StageMark m(c, st, MASE_STAGE_ASSEMBLE);
     HIPTRY(launch_assemble(d, 0, K, s0, ns, MODE_ASSEMBLE, c->lds_asm, c->br_lds, st));
@@ -661,6 +672,8 @@ int mase_create(int32_t n_bus, int32_t n_branch, const int32_t* br_from, const i
   Input in{n_bus, n_branch, br_from, br_to, br_r, br_x, br_b, slack_bus, n_area, bus_area,
            n_meas, meas_type, meas_at, meas_sigma, n_snap, o.gamma_mode};
   if (o.pipeline_groups < 0) return fail(MASE_ERR_ARG, "pipeline_groups must be >= 0");
+  if (o.local_steps < 0) return fail(MASE_ERR_ARG, "local_steps must be >= 0");
+  if (o.local_steps > 0 && !o.batched) return fail(MASE_ERR_ARG, "local_steps needs the batched schedule");
   mase_ctx* c = new (std::nothrow) mase_ctx();
   if (!c) return fail(MASE_ERR_OOM, "host allocation failed");
   c->opt = o;
@@ -874,7 +887,8 @@ uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
 std::string make_tune_key(const mase_ctx* c) {
   const Plan& p = c->plan;
   uint64_t h = 1469598103934665603ull;
-  const int32_t dims[6] = {p.n_bus, p.n_branch, p.n_area, p.n_meas, p.n_snap, c->opt.gamma_mode};
+  const int32_t dims[7] = {p.n_bus, p.n_branch, p.n_area, p.n_meas, p.n_snap, c->opt.gamma_mode,
+                           c->opt.local_steps};
   h = fnv1a(h, dims, sizeof(dims));
   h = fnv1a(h, p.br_from.data(), p.br_from.size() * sizeof(int32_t));
   h = fnv1a(h, p.br_to.data(), p.br_to.size() * sizeof(int32_t));

@@ -997,7 +997,7 @@ __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
 // a group of 8 lanes and combined by a fixed shuffle tree.
 // ---------------------------------------------------------------------------
 template <int NT>
-__global__ void __launch_bounds__(NT) k_backsolve(Dev d, int sys0, int nsys, int s0, int ns) {
+__global__ void __launch_bounds__(NT) k_backsolve(Dev d, int sys0, int nsys, int s0, int ns, int fixed_bnd) {
   // lanes per column: the boundary system's levels hold a few wide columns,
   // an area's levels many narrow ones
   constexpr int G = (NT >= 1024) ? 64 : 8;
@@ -1015,9 +1015,10 @@ __global__ void __launch_bounds__(NT) k_backsolve(Dev d, int sys0, int nsys, int
   if (is_area) {
     const AreaMeta am = d.area[k];
     for (int t = tid; t < sm.nt; t += NT) {
+      // dx_b = E_k dx_Gamma, or 0 for a local step with the boundary fixed
       const int src = d.tail_src[am.tail_src + t];
-      rhs[2 * (sm.ne + t)] = rb[src];
-      rhs[2 * (sm.ne + t) + 1] = rb[src + 1];
+      rhs[2 * (sm.ne + t)] = fixed_bnd ? 0.0 : rb[src];
+      rhs[2 * (sm.ne + t) + 1] = fixed_bnd ? 0.0 : rb[src + 1];
     }
   }
   __syncthreads();
@@ -1059,15 +1060,18 @@ __global__ void __launch_bounds__(NT) k_backsolve(Dev d, int sys0, int nsys, int
 // One workgroup per snapshot.  A snapshot whose factorisation hit a
 // non-positive pivot is frozen without an update.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(512) k_update(Dev d, int s0) {
+// local != 0: a local step (boundary fixed): boundary buses, whose dx lives in
+// the boundary system, do not move, and the convergence state is left alone.
+__global__ void __launch_bounds__(512) k_update(Dev d, int s0, int local) {
   const int s = s0 + blockIdx.x;
   __shared__ double red[16];
   __shared__ int bad;
   const int tid = threadIdx.x, nt = blockDim.x;
   if (!d.active[s]) {
-    if (tid == 0) d.maxdx[s] = 0.0;
+    if (tid == 0 && !local) d.maxdx[s] = 0.0;
     return;
   }
+  const int gamma_rhs = d.sys[d.n_area].rhs_off;
   if (tid == 0) {
     int b = 0;
     for (int k = 0; k <= d.n_area; ++k) b |= d.status[(int64_t)s * (d.n_area + 1) + k];
@@ -1080,8 +1084,9 @@ __global__ void __launch_bounds__(512) k_update(Dev d, int s0) {
     double2* xs = d.x + (int64_t)s * d.n_bus;
     for (int bus = tid; bus < d.n_bus; bus += nt) {
       const int src = d.bus_dx_src[bus];
-      const double dt = (bus == d.slack) ? 0.0 : rb[src];
-      const double dv = rb[src + 1];
+      const bool hold = local && src >= gamma_rhs;
+      const double dt = (bus == d.slack || hold) ? 0.0 : rb[src];
+      const double dv = hold ? 0.0 : rb[src + 1];
       double2 v = xs[bus];
       v.x += dt;
       v.y += dv;
@@ -1091,7 +1096,7 @@ __global__ void __launch_bounds__(512) k_update(Dev d, int s0) {
     }
   }
   const double mx = block_max(m, red);
-  if (tid == 0) {
+  if (tid == 0 && !local) {
     d.maxdx[s] = mx;
     d.iters[s] += 1;
     if (bad || mx < d.tol[0]) d.active[s] = 0;
@@ -1204,18 +1209,19 @@ hipError_t allow_dense_lds(size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-hipError_t launch_backsolve(const Dev& d, int sys0, int nsys, int s0, int ns, hipStream_t st) {
+hipError_t launch_backsolve(const Dev& d, int sys0, int nsys, int s0, int ns, hipStream_t st, bool fixed_bnd) {
   if (nsys <= 0 || ns <= 0) return hipSuccess;
   if (sys0 >= d.n_area)
-    hipLaunchKernelGGL(k_backsolve<GAMMA_NT>, dim3(nsys * ns), dim3(GAMMA_NT), 0, st, d, sys0, nsys, s0, ns);
+    hipLaunchKernelGGL(k_backsolve<GAMMA_NT>, dim3(nsys * ns), dim3(GAMMA_NT), 0, st, d, sys0, nsys, s0, ns, 0);
   else
-    hipLaunchKernelGGL(k_backsolve<AREA_NT>, dim3(nsys * ns), dim3(AREA_NT), 0, st, d, sys0, nsys, s0, ns);
+    hipLaunchKernelGGL(k_backsolve<AREA_NT>, dim3(nsys * ns), dim3(AREA_NT), 0, st, d, sys0, nsys, s0, ns,
+                       fixed_bnd ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_update(const Dev& d, int s0, int ns, hipStream_t st) {
+hipError_t launch_update(const Dev& d, int s0, int ns, hipStream_t st, bool local) {
   if (ns <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_update, dim3(ns), dim3(512), 0, st, d, s0);
+  hipLaunchKernelGGL(k_update, dim3(ns), dim3(512), 0, st, d, s0, local ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -24,8 +24,11 @@ hipError_t launch_gamma_gather(const Dev& d, int s0, int ns, int nslot, int nn, 
 size_t dense_lds_bytes(int ld, bool panel);
 hipError_t launch_dense_chol(const Dev& d, int s0, int ns, int ld, bool panel, hipStream_t st);
 hipError_t allow_dense_lds(size_t bytes);
-hipError_t launch_backsolve(const Dev& d, int sys0, int nsys, int s0, int ns, hipStream_t st);
-hipError_t launch_update(const Dev& d, int s0, int ns, hipStream_t st);
+// fixed_bnd (areas): dx_b = 0 instead of E_k dx_Gamma (a local step, Eq. 6)
+hipError_t launch_backsolve(const Dev& d, int sys0, int nsys, int s0, int ns, hipStream_t st,
+                            bool fixed_bnd = false);
+// local: boundary buses hold, convergence state untouched (a local step)
+hipError_t launch_update(const Dev& d, int s0, int ns, hipStream_t st, bool local = false);
 hipError_t launch_pack_state(const Dev& d, const double* vm, const double* va, double2* xout,
                              hipStream_t st);
 hipError_t launch_unpack_state(const Dev& d, double* vm, double* va, hipStream_t st);

@@ -26,7 +26,7 @@ INFO = {"n_gamma": 0, "n_boundary_bus": 1, "gamma_tail": 2, "nnz_factor": 3, "ma
         "bytes_condense": 10, "flops_dense": 11, "bytes_backsolve": 12, "flops_gamma_sparse": 13,
         "gamma_levels": 14, "gamma_supernodes": 15, "gamma_supernodal": 16, "pipeline_groups": 17}
 STAGES = ("assemble", "condense", "gamma_gather", "gamma_sparse", "gamma_dense", "gamma_back",
-          "backsolve", "update")
+          "backsolve", "update", "local")
 MAPS = {"boundary_flag": 0, "meas_area": 1, "gamma_vars": 2, "local_vars": 3,
         "n_internal": 4, "E": 5}
 
@@ -55,7 +55,8 @@ class Options(ctypes.Structure):
     _fields_ = [("stream", ctypes.c_void_p), ("batched", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("gamma_mode", ctypes.c_int32),
                 ("host_only", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("tune_cache", ctypes.c_char_p), ("pipeline_groups", ctypes.c_int32)]
+                ("tune_cache", ctypes.c_char_p), ("local_steps", ctypes.c_int32),
+                ("pipeline_groups", ctypes.c_int32)]
 
 
 _lib = None
@@ -186,7 +187,7 @@ class Mase:
     def __init__(self, n_bus, br_from, br_to, br_r, br_x, br_b, slack_bus, n_area, bus_area,
                  meas_type, meas_at, meas_sigma, n_snap, batched=True, use_graph=True,
                  gamma_mode=MASE_GAMMA_SPARSE, host_only=False, stream=None, pipeline_groups=0,
-                 autotune=False, tune_cache=None):
+                 autotune=False, tune_cache=None, local_steps=0):
         self.lib = load()
         o = mase_default_options()
         o.batched = int(bool(batched))
@@ -194,6 +195,7 @@ class Mase:
         o.gamma_mode = int(gamma_mode)
         o.host_only = int(bool(host_only))
         o.pipeline_groups = int(pipeline_groups)
+        o.local_steps = int(local_steps)
         o.autotune = int(bool(autotune))
         self._tune_cache = None if tune_cache is None else str(tune_cache).encode()
         o.tune_cache = self._tune_cache

@@ -313,3 +313,49 @@ def test_slack_on_boundary_solve():
         ref = c.oracle_solve(i)
         assert_state_close(vm[i], va[i], ref["vm"], ref["va"], 1e-8)
     m.close()
+
+
+@pytest.mark.parametrize("name,steps", [("k5", 1), ("c1", 2)])
+def test_local_steps_iterate_matches_oracle(name, steps):
+    """One iteration = `steps` local steps with the boundary held (Eq. 6),
+    then the condensed step (Eq. 8-11), each taken by the oracle in turn."""
+    say("local-steps iterate", name, steps)
+    c = Case(name, 3, seed=13)
+    m = c.ctx(local_steps=steps)
+    m.mase_gn_iter()
+    vm, va = m.mase_state()
+    for i in range(3):
+        x = c.net.pack(np.ones(c.g.n_bus), np.zeros(c.g.n_bus))
+        for _ in range(steps):
+            rvm, rva = c.net.unpack(x)
+            x = x + c.A.local_step(c.z[i], rvm, rva)
+        rvm, rva = c.net.unpack(x)
+        x = x + c.A.condensed_step(c.z[i], rvm, rva)
+        rvm, rva = c.net.unpack(x)
+        assert_state_close(vm[i], va[i], rvm, rva, 1e-8)
+    m.close()
+
+
+@pytest.mark.parametrize("steps", [1, 3])
+def test_local_steps_solve_reaches_oracle_minimizer(steps):
+    say("local-steps solve", steps)
+    c = Case("c1", 3, seed=17)
+    m = c.ctx(local_steps=steps)
+    iters, conv = m.mase_solve(1e-8, 12)
+    assert conv.all()
+    vm, va = m.mase_state()
+    for i in range(3):
+        ref = c.oracle_solve(i, tol=1e-10, max_iter=15)
+        assert ref["converged"]
+        assert_state_close(vm[i], va[i], ref["vm"], ref["va"], 1e-8)
+        say("  snapshot", i, "iterations", int(iters[i]), "centralized", ref["iters"])
+    m.close()
+
+
+def test_local_steps_need_batched_schedule():
+    say("local-steps plain schedule rejected")
+    c = Case("k5", 1, seed=1)
+    with pytest.raises(mase.MaseError):
+        c.ctx(local_steps=1, batched=False)
+    with pytest.raises(mase.MaseError):
+        c.ctx(local_steps=-1)
