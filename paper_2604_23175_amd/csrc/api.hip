@@ -68,7 +68,7 @@ int upload(mase_ctx* c, const std::vector<H>& v, const D** out) {
 // Sparse part of the boundary system: supernodal when its panels fit in LDS,
 // else the level-scheduled engine.
 hipError_t launch_gamma_sparse(const mase_ctx* c, int s0, int ns, hipStream_t st) {
-  if (c->gamma_snode) return launch_gamma_snode(c->d, s0, ns, c->lds_sn, st);
+  if (c->gamma_snode) return launch_gamma_snode(c->d, s0, ns, c->lds_sn, c->plan.sys[c->plan.n_area].ld, st);
   return launch_eliminate(c->d, c->plan.n_area, 1, s0, ns, c->lds_el_gamma, st);
 }
 
@@ -182,9 +182,10 @@ int upload_plan(mase_ctx* c) {
     a.slack_local = p.local_of_bus[k][p.slack];
     am[k] = a;
   }
-  int dev = 0, maxlds = 0;
+  int dev = 0, maxlds = 0, n_cu = 0;
   HIPTRY(hipGetDevice(&dev));
   HIPTRY(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  HIPTRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
   // stage branch records in LDS when every area fits
   size_t lds_br = 0, lds_nobr = 0;
   for (int k = 0; k < K; ++k) {
@@ -222,9 +223,19 @@ int upload_plan(mase_ctx* c) {
   {
     const char* env = getenv("MASE_GAMMA_SNODE");
     c->lds_sn = (size_t)p.sys[K].sn_lds_bytes;
-    c->snode_possible = !p.sys[K].sn.empty() && c->lds_sn + 4096 <= (size_t)maxlds;
+    const size_t tail_lds = gamma_tail_lds_bytes((int)p.sys[K].sn.size(), p.sys[K].ld);
+    c->snode_possible = !p.sys[K].sn.empty() && c->lds_sn + 4096 <= (size_t)maxlds &&
+                        tail_lds + 1024 <= (size_t)maxlds;
+    if (c->snode_possible && tail_lds > 65536) HIPTRY(allow_gamma_tail_lds(tail_lds));
     c->gamma_snode = c->snode_possible && !(env && env[0] == '0');
     if (c->gamma_snode && c->lds_sn > 65536) HIPTRY(allow_gamma_snode_lds(c->lds_sn));
+    // subtree groups: as many workgroups per snapshot as fit the device at
+    // once for the whole batch (MASE_SNODE_GROUPS overrides the limit)
+    const int per_cu = std::max(1, (int)(160 * 1024 / std::max<size_t>(c->lds_sn, 1)));
+    int gmax = std::max(1, n_cu * per_cu / std::max(1, p.n_snap));
+    const char* genv = getenv("MASE_SNODE_GROUPS");
+    if (genv && atoi(genv) > 0) gmax = atoi(genv);
+    c->plan.sys[K].group_supernodes(gmax);
   }
   c->hsys = sm;
   c->nslot_g = (int)p.g_slot.size();
@@ -246,6 +257,12 @@ int upload_plan(mase_ctx* c) {
     const SysPlan& gs = p.sys[K];
     d.n_sn = (int32_t)gs.sn.size();
     UP(sn, gs.sn); UP(sn2, gs.sn2); UP(sn_rows, gs.sn_rows); UP(sn_tgt, gs.sn_tgt);
+    d.n_sn_grp = (int32_t)gs.sn_grp_ptr.size() - 1;
+    UP(sn_grp_ptr, gs.sn_grp_ptr); UP(sn_grp, gs.sn_grp);
+    UP(sn3, gs.sn3); UP(sn_tpos, gs.sn_tpos); UP(sn_tvar, gs.sn_tvar);
+    d.tl_stride = gs.tl_doubles;
+    d.sn_tl = nullptr;
+    if (gs.tl_doubles > 0 && (rc = dalloc(c, (size_t)gs.tl_doubles * p.n_snap, &d.sn_tl))) return rc;
   }
   UP(g_slot, p.g_slot); UP(g_con, p.g_con); UP(g_rslot, p.g_rslot); UP(g_rcon, p.g_rcon);
   UP(tail_src, p.tail_src); UP(bus_dx_src, p.bus_dx_src);

@@ -62,6 +62,15 @@ struct Dev {
   const int4* sn2;
   const int32_t* sn_rows;
   const int32_t* sn_tgt;
+  // elimination subtree groups (one workgroup each) and tail rows of the panels
+  int32_t n_sn_grp;
+  const int32_t* sn_grp_ptr;
+  const int32_t* sn_grp;
+  const int4* sn3;
+  const int32_t* sn_tpos;
+  const int32_t* sn_tvar;
+  double* sn_tl;       // [n_snap][tl_stride]: compact tail rows of every panel
+  int32_t tl_stride;
   const int4* g_slot;
   const int4* g_con;
   const int2* g_rslot;

@@ -280,14 +280,78 @@ void SysPlan::build_supernodes() {
     }
     const auto& R = strct[j + w - 1];
     const int r = (int)R.size();
+    const int ntail = (int)(R.end() - std::lower_bound(R.begin(), R.end(), ne));
     sn.push_back({j, w, r, (int32_t)sn_rows.size()});
-    sn2.push_back({col_off[j], col_off[j + w - 1] + 4 * (1 + r) - col_off[j], (int32_t)sn_tgt.size(), 0});
+    sn2.push_back({col_off[j], col_off[j + w - 1] + 4 * (1 + r) - col_off[j], (int32_t)sn_tgt.size(), ntail});
     sn_rows.insert(sn_rows.end(), R.begin(), R.end());
     for (int a = 0; a < r; ++a)
       for (int c = 0; c <= a; ++c) sn_tgt.push_back(blk_off(R[a], R[c]));
     sn_tbase.push_back((int32_t)sn_tgt.size());
     sn_lds_bytes = std::max(sn_lds_bytes, sn_lds_bytes_of(w, r));
     j += w;
+  }
+  // subtree roots, in supernode order (children before parents)
+  const int nsn = (int)sn.size();
+  std::vector<int> sn_of(ne, -1);
+  for (int q = 0; q < nsn; ++q)
+    for (int b = 0; b < sn[q].y; ++b) sn_of[sn[q].x + b] = q;
+  sn_root.assign(nsn, -1);
+  sn_cost.assign(nsn, 0.0);
+  for (int q = nsn - 1; q >= 0; --q) {
+    const int r = sn[q].z;
+    const int first = r ? sn_rows[sn[q].w] : -1;
+    sn_root[q] = (first < 0 || first >= ne) ? q : sn_root[sn_of[first]];
+    // per 16-column step: one wave-level 16x16 Cholesky plus row-tile work,
+    // then staging, Schur update and write-back in proportion to the rows
+    const int Wp = sn_cols_padded(sn[q].y), M = sn_rows_padded(sn[q].y, r);
+    sn_cost[q] = (Wp / 16) * (7.0 + 0.6 * M / 16) + 1.5 * M / 16;
+  }
+  // compact tail rows
+  sn3.clear();
+  sn_tpos.clear();
+  sn_tvar.clear();
+  tl_doubles = 0;
+  const int nbt = ld / 16;
+  for (int q = 0; q < nsn; ++q) {
+    const int r = sn[q].z, ntail = sn2[q].w;
+    const int32_t* R = sn_rows.data() + sn[q].w;
+    sn3.push_back({tl_doubles, (int32_t)sn_tpos.size(), (int32_t)sn_tvar.size(), 0});
+    for (int a = r - ntail; a < r; ++a) {
+      sn_tvar.push_back(2 * (R[a] - ne));
+      sn_tvar.push_back(2 * (R[a] - ne) + 1);
+    }
+    const int32_t* tv = sn_tvar.data() + sn3.back().z;
+    for (int t = 0; t <= nbt; ++t)
+      sn_tpos.push_back((int32_t)(std::lower_bound(tv, tv + 2 * ntail, 16 * t) - tv));
+    tl_doubles += ntail ? (sn_cols_padded(sn[q].y) * 2 * ntail + 31) / 32 * 32 : 0;
+  }
+  group_supernodes(1);
+}
+
+void SysPlan::group_supernodes(int max_groups) {
+  const int nsn = (int)sn.size();
+  std::vector<int> roots;
+  std::vector<double> tree(nsn, 0.0);
+  for (int q = 0; q < nsn; ++q) {
+    tree[sn_root[q]] += sn_cost[q];
+    if (sn_root[q] == q) roots.push_back(q);
+  }
+  const int G = std::max(1, std::min(max_groups, (int)roots.size()));
+  // longest subtree first, each to the group with the least work so far
+  std::stable_sort(roots.begin(), roots.end(), [&](int a, int b) { return tree[a] > tree[b]; });
+  std::vector<double> load(G, 0.0);
+  std::vector<int> grp_of(nsn, 0);
+  for (int rt : roots) {
+    const int gi = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[gi] += tree[rt];
+    grp_of[rt] = gi;
+  }
+  sn_grp_ptr.assign(G + 1, 0);
+  sn_grp.clear();
+  for (int gi = 0; gi < G; ++gi) {
+    for (int q = 0; q < nsn; ++q)
+      if (grp_of[sn_root[q]] == gi) sn_grp.push_back(q);
+    sn_grp_ptr[gi + 1] = (int32_t)sn_grp.size();
   }
 }
 

@@ -80,17 +80,35 @@ struct SysPlan {
   // diagonal block are the same bus list R for every column.
   std::vector<I4> sn;             // {first bus c0, width w, |R| = r, base of R in sn_rows}
   std::vector<I4> sn2;            // {offset of column c0's diagonal block, doubles of the
-                                  // panel's columns (contiguous), base in sn_tgt, 0}
+                                  // panel's columns (contiguous), base in sn_tgt,
+                                  // number of R buses in the tail}
   std::vector<int32_t> sn_tbase;  // [nsn+1] -> sn_tgt
   std::vector<int32_t> sn_rows;   // R of each supernode, ascending local bus ids
   std::vector<int32_t> sn_tgt;    // per supernode, for a >= c in R: offset of block (R[a], R[c])
                                   // at a(a+1)/2 + c (in the dense tail when >= tail_off)
   int32_t sn_lds_bytes = 0;       // LDS of the largest panel (values, rhs, target offsets)
+  // Elimination subtrees: a supernode's parent is the supernode holding R[0];
+  // one whose R is empty or starts in the tail is a root.  Subtrees of
+  // different roots share no factor entries outside the tail block and the
+  // tail rhs, so they are eliminated in parallel (one workgroup per group of
+  // roots) and their updates of the tail are applied afterwards, per target
+  // in supernode order.
+  std::vector<int32_t> sn_root;   // supernode -> root of its subtree
+  std::vector<double> sn_cost;    // estimated elimination time of the supernode (arbitrary unit)
+  std::vector<int32_t> sn_grp_ptr;  // [ngrp+1] -> sn_grp
+  std::vector<int32_t> sn_grp;      // supernodes of each group, ascending
+  // Tail rows of each supernode's panel (R rows in the tail, 2 ntail of them)
+  // are copied to a compact per-snapshot buffer, column-major [Wp][2 ntail].
+  std::vector<I4> sn3;            // {offset in the compact buffer, base in sn_tpos, base in sn_tvar, 0}
+  std::vector<int32_t> sn_tpos;   // [nsn][ld/16 + 1]: first compact row of supernode q in tail tile t
+  std::vector<int32_t> sn_tvar;   // per supernode [2 ntail]: tail variable of each compact row
+  int32_t tl_doubles = 0;         // doubles of the compact buffer per snapshot
   std::vector<int32_t> bs_ptr;  // [nlev+1] -> bs_items (same levels, run top-down)
   std::vector<I4> bs_items;     // {diag_off, rhs_j, cbeg, cend}
   std::vector<I2> bs_con;       // {off L_ij, rhs_i}: t -= L_ij^T * x_i
 
   void build_supernodes();               // fills sn*, after the schedule
+  void group_supernodes(int max_groups); // sn_grp*: roots packed into at most max_groups groups
   int32_t blk_off(int i, int j) const;   // block (i, j), i >= j
   int32_t blk_stride(int i, int j) const;
   double elim_flops() const;             // flops of eliminating [0, ne) with rhs
