@@ -68,7 +68,7 @@ int upload(mase_ctx* c, const std::vector<H>& v, const D** out) {
 // Sparse part of the boundary system: supernodal when its panels fit in LDS,
 // else the level-scheduled engine.
 hipError_t launch_gamma_sparse(const mase_ctx* c, int s0, int ns, hipStream_t st) {
-  if (c->gamma_snode) return launch_gamma_snode(c->d, s0, ns, c->lds_sn, c->plan.sys[c->plan.n_area].ld, st);
+  if (c->gamma_snode) return launch_gamma_snode(c->d, s0, ns, c->lds_sn, st);
   return launch_eliminate(c->d, c->plan.n_area, 1, s0, ns, c->lds_el_gamma, st);
 }
 
@@ -223,10 +223,7 @@ int upload_plan(mase_ctx* c) {
   {
     const char* env = getenv("MASE_GAMMA_SNODE");
     c->lds_sn = (size_t)p.sys[K].sn_lds_bytes;
-    const size_t tail_lds = gamma_tail_lds_bytes((int)p.sys[K].sn.size(), p.sys[K].ld);
-    c->snode_possible = !p.sys[K].sn.empty() && c->lds_sn + 4096 <= (size_t)maxlds &&
-                        tail_lds + 1024 <= (size_t)maxlds;
-    if (c->snode_possible && tail_lds > 65536) HIPTRY(allow_gamma_tail_lds(tail_lds));
+    c->snode_possible = !p.sys[K].sn.empty() && c->lds_sn + 4096 <= (size_t)maxlds;
     c->gamma_snode = c->snode_possible && !(env && env[0] == '0');
     if (c->gamma_snode && c->lds_sn > 65536) HIPTRY(allow_gamma_snode_lds(c->lds_sn));
     // subtree groups: as many workgroups per snapshot as fit the device at
@@ -259,7 +256,8 @@ int upload_plan(mase_ctx* c) {
     UP(sn, gs.sn); UP(sn2, gs.sn2); UP(sn_rows, gs.sn_rows); UP(sn_tgt, gs.sn_tgt);
     d.n_sn_grp = (int32_t)gs.sn_grp_ptr.size() - 1;
     UP(sn_grp_ptr, gs.sn_grp_ptr); UP(sn_grp, gs.sn_grp);
-    UP(sn3, gs.sn3); UP(sn_tpos, gs.sn_tpos); UP(sn_tvar, gs.sn_tvar);
+    UP(sn3, gs.sn3); UP(tail_ent, gs.tail_ent); UP(tail_con, gs.tail_con);
+    d.n_tail_ent = (int32_t)gs.tail_ent.size();
     d.tl_stride = gs.tl_doubles;
     d.sn_tl = nullptr;
     if (gs.tl_doubles > 0 && (rc = dalloc(c, (size_t)gs.tl_doubles * p.n_snap, &d.sn_tl))) return rc;

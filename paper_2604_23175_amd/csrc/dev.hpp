@@ -67,9 +67,10 @@ struct Dev {
   const int32_t* sn_grp_ptr;
   const int32_t* sn_grp;
   const int4* sn3;
-  const int32_t* sn_tpos;
-  const int32_t* sn_tvar;
-  double* sn_tl;       // [n_snap][tl_stride]: compact tail rows of every panel
+  int32_t n_tail_ent;
+  const int4* tail_ent;
+  const int32_t* tail_con;
+  double* sn_tl;       // [n_snap][tl_stride]: every supernode's U_q and c_q
   int32_t tl_stride;
   const int4* g_slot;
   const int4* g_con;

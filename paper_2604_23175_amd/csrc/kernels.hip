@@ -819,8 +819,9 @@ __device__ inline void sn_coords(int i, int w, int r, int Wp, int& rowv, int& co
 // One workgroup per (snapshot, group of elimination subtrees): subtrees that
 // hang off different points of the tail share no factor entries below it, so
 // their groups run side by side.  What they do share, the tail block and the
-// tail rhs, is left alone here: each panel's tail rows go to a compact buffer
-// and k_gamma_tail applies their updates afterwards.
+// tail rhs, is left alone here: each supernode stores its update of them,
+// U_q = L_T L_T^T over its tail rows T and c_q = -L_T y_q, and k_gamma_tail
+// applies them afterwards.
 __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
   const int gi = blockIdx.x % d.n_sn_grp;
   const int s = s0 + blockIdx.x / d.n_sn_grp;
@@ -946,21 +947,14 @@ __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
     }
     for (int i = tid; i < W; i += SN_NT) rhs[2 * c0 + i] = yv[i];
     for (int i = tid; i < 2 * nrs; i += SN_NT) rhs[2 * d.sn_rows[rb + (i >> 1)] + (i & 1)] = yv[Wp + i];
-    if (sn2.w > 0) {
-      // tail rows of the factor, column-major [Wp][2 ntail]
-      const int mt = 2 * sn2.w;
-      double* tq = tl + d.sn3[q].x;
-      for (int i = tid; i < Wp * mt; i += SN_NT) {
-        const int col = i / mt, cr = i - col * mt;
-        tq[i] = P[col * M + Wp + 2 * nrs + cr];
-      }
-    }
-    // (4) Schur update of the R x R blocks outside the tail block: tiles
-    // (I >= J) of the R rows whose column tile J holds a non-tail bus.  A
+    const int mt = 2 * sn2.w;  // tail rows: their rhs started at 0, so they now hold c_q
+    const int4 s3 = d.sn3[q];
+    for (int i = tid; i < mt; i += SN_NT) tl[s3.y + i] = yv[Wp + 2 * nrs + i];
+    // (4) Schur update of the R x R blocks: tiles (I >= J) of the R rows.
+    // Targets outside the tail block are read, updated and written back (a
     // wave computes TB tiles, then loads all their targets, then stores, so
-    // the read-modify-write round trips overlap.
-    const int nr = (M - Wp) / 16, nrj = (2 * nrs + 15) / 16;
-    const int nt3 = nrj * nr - nrj * (nrj - 1) / 2;  // column J holds tiles I = J .. nr - 1
+    // the round trips overlap); the tail block's part is stored as U_q.
+    const int nr = (M - Wp) / 16, nt3 = nr * (nr + 1) / 2;
     for (int t0 = wv; t0 < nt3; t0 += NW * TB) {
       d4 acc[TB];
       int idx[TB][4];
@@ -970,12 +964,10 @@ __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) idx[b][e] = -1;
         if (t >= nt3) continue;
-        int J = 0, tt = t;
-        while (tt >= nr - J) {
-          tt -= nr - J;
-          ++J;
-        }
-        const int I = J + tt;
+        int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+        while (I * (I + 1) / 2 > t) --I;
+        while ((I + 1) * (I + 2) / 2 <= t) ++I;
+        const int J = t - I * (I + 1) / 2;
         // the tile is computed transposed (D = rows J x rows I): lane li then
         // holds row 16 I + li, so lanes run down a column of the target
         const int ri = Wp + 16 * I, rj = Wp + 16 * J;
@@ -989,7 +981,12 @@ __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
         for (int e = 0; e < 4; ++e) {
           const int xv = 16 * I + li, yc = 16 * J + 4 * e + lk;
           const int ab = xv >> 1, cb2 = yc >> 1;
-          if (xv < 2 * r && cb2 < nrs && ab >= cb2) idx[b][e] = tg[ab * (ab + 1) / 2 + cb2] + (xv & 1) + 2 * (yc & 1);
+          if (xv < 2 * r && yc < 2 * r && ab >= cb2) {
+            if (cb2 < nrs)
+              idx[b][e] = tg[ab * (ab + 1) / 2 + cb2] + (xv & 1) + 2 * (yc & 1);
+            else
+              tl[s3.x + (yc - 2 * nrs) * mt + (xv - 2 * nrs)] = acc[b][e];
+          }
         }
       }
       double old[TB][4];
@@ -1009,146 +1006,38 @@ __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
 }
 
 // ---------------------------------------------------------------------------
-// Stage 3b (sparse part, tail updates): every supernode's update of the tail
-// block, A_TT -= L_T L_T^T over its tail rows T, and of the tail rhs,
-// b_T -= L_T y, applied per target in supernode order (the order of the
-// one-workgroup elimination).  One workgroup per (snapshot, 16-column tile j
-// of the tail); wave v owns the 16x16 target tiles (i, j), i = j + v, j + v +
-// 4, ..., holds one in LDS at a time and runs the supernodes touching both
-// tile rows i and tile columns j through it (the product on FP64 MFMA).  Wave
-// 0 also owns the rhs entries of tile j.  Per supernode, sn_tpos gives the
-// compact rows of T that fall in each tile.
+// Stage 3b (sparse part, tail updates): every tail entry of the boundary
+// system takes the updates the supernodes left for it, A -= U_q and b += c_q,
+// in supernode order (the order of a one-workgroup elimination), from a
+// fixed contribution list.  One thread per entry.
 // ---------------------------------------------------------------------------
 constexpr int TAIL_NT = 256;
 
-__global__ void __launch_bounds__(TAIL_NT) k_gamma_tail(Dev d, int s0) {
+__global__ void __launch_bounds__(TAIL_NT) k_gamma_tail(Dev d, int s0, int nblk) {
+  const int e = (blockIdx.x % nblk) * TAIL_NT + threadIdx.x;
+  const int s = s0 + blockIdx.x / nblk;
+  if (e >= d.n_tail_ent || !d.active[s]) return;
   const SysMeta g = d.sys[d.n_area];
-  const int nbt = g.ld / 16, nq = d.n_sn;
-  const int j = blockIdx.x % nbt;
-  const int s = s0 + blockIdx.x / nbt;
-  if (!d.active[s]) return;
-  double* A = d.vals + (int64_t)s * d.vstride + g.val_off + g.tail_off;
-  double* bg = d.rhs + (int64_t)s * d.rstride + g.rhs_off;
+  const int4 te = d.tail_ent[e];
   const double* tl = d.sn_tl + (int64_t)s * d.tl_stride;
-  constexpr int NW = TAIL_NT / 64;
-  extern __shared__ double tsh[];
-  double* tile = tsh;                   // [NW][16 columns][16 rows]
-  double* bt = tsh + NW * 256;          // [16]
-  int4* qm = reinterpret_cast<int4*>(bt + 16);  // [nq] {compact offset, 2 ntail, Wp, sn_tvar base}
-  int* qy = reinterpret_cast<int*>(qm + nq);    // [nq] first own variable (2 c0), own width W
-  int* qw = qy + nq;
-  int* qpos = qw + nq;                  // [nq][nbt + 1]
-  int* qlist = qpos + nq * (nbt + 1);   // supernodes with tail rows in tile j, ascending
-  __shared__ int nlist;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  for (int q = tid; q < nq; q += TAIL_NT) {
-    const int4 sn = d.sn[q];
-    const int4 s2 = d.sn2[q];
-    const int4 s3 = d.sn3[q];
-    qm[q] = int4{s3.x, 2 * s2.w, (2 * sn.y + 15) & ~15, s3.z};
-    qy[q] = 2 * sn.x;
-    qw[q] = 2 * sn.y;
+  double* tgt = te.y ? d.rhs + (int64_t)s * d.rstride + g.rhs_off + 2 * g.ne + te.x
+                     : d.vals + (int64_t)s * d.vstride + g.val_off + g.tail_off + te.x;
+  double v = *tgt;
+  int c = te.z;
+  // four sources in flight at a time
+  for (; c + 4 <= te.w; c += 4) {
+    const int o0 = d.tail_con[c], o1 = d.tail_con[c + 1], o2 = d.tail_con[c + 2], o3 = d.tail_con[c + 3];
+    const double u0 = tl[o0], u1 = tl[o1], u2 = tl[o2], u3 = tl[o3];
+    v = te.y ? v + u0 : v - u0;
+    v = te.y ? v + u1 : v - u1;
+    v = te.y ? v + u2 : v - u2;
+    v = te.y ? v + u3 : v - u3;
   }
-  for (int t = tid; t < nq * (nbt + 1); t += TAIL_NT) qpos[t] = d.sn_tpos[t];  // [nq][nbt + 1] in order
-  __syncthreads();
-  if (wv == 0) {
-    int cnt = 0;
-    for (int q0 = 0; q0 < nq; q0 += 64) {
-      const int q = q0 + lane;
-      const bool f = q < nq && qm[q].y > 0 && qpos[q * (nbt + 1) + j + 1] > qpos[q * (nbt + 1) + j];
-      const unsigned long long m = __ballot(f);
-      if (f) qlist[cnt + __popcll(m & ((1ull << lane) - 1ull))] = q;
-      cnt += __popcll(m);
-    }
-    if (lane == 0) nlist = cnt;
+  for (; c < te.w; ++c) {
+    const double u = tl[d.tail_con[c]];
+    v = te.y ? v + u : v - u;
   }
-  __syncthreads();
-  const int nl = nlist;
-  // rhs entries of tile j (wave 0)
-  if (wv == 0) {
-    const int live = 2 * g.nt - 16 * j;
-    if (lane < 16 && lane < live) bt[lane] = bg[2 * g.ne + 16 * j + lane];
-    wave_lds_sync();
-    for (int u = 0; u < nl; ++u) {
-      const int q = qlist[u];
-      const int4 m = qm[q];
-      const int c_lo = qpos[q * (nbt + 1) + j], c_hi = qpos[q * (nbt + 1) + j + 1];
-      const int cr = c_lo + lane;
-      if (cr < c_hi) {
-        const double* L = tl + m.x;
-        const double* yq = bg + qy[q];
-        const int W = qw[q];
-        double v = bt[d.sn_tvar[m.w + cr] - 16 * j];
-        for (int cb = 0; cb < m.z; cb += 16) {
-          double acc = 0.0;
-#pragma unroll
-          for (int c = 0; c < 16; ++c) acc += L[(cb + c) * m.y + cr] * (cb + c < W ? yq[cb + c] : 0.0);
-          v -= acc;
-        }
-        bt[d.sn_tvar[m.w + cr] - 16 * j] = v;
-      }
-      wave_lds_sync();
-    }
-    if (lane < 16 && lane < live) bg[2 * g.ne + 16 * j + lane] = bt[lane];
-  }
-  // target tiles
-  double* T = tile + wv * 256;
-  for (int i = j + wv; i < nbt; i += NW) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int x = lane + 64 * e, c = x >> 4, r = x & 15;
-      T[x] = A[(int64_t)(16 * j + c) * g.ld + 16 * i + r];
-    }
-    wave_lds_sync();
-    for (int u = 0; u < nl; ++u) {
-      const int q = qlist[u];
-      const int r_lo = qpos[q * (nbt + 1) + i], r_hi = qpos[q * (nbt + 1) + i + 1];
-      if (r_lo == r_hi) continue;
-      const int4 m = qm[q];
-      const int c_lo = qpos[q * (nbt + 1) + j], c_hi = qpos[q * (nbt + 1) + j + 1];
-      const double* L = tl + m.x;
-      const bool ca = c_lo + li < c_hi, ra = r_lo + li < r_hi;
-      // computed transposed (D = columns x rows): lane li holds target row
-      // r_lo + li, element e target column c_lo + 4 e + lk
-      // all operands in flight at once (a panel is at most 64 columns)
-      double av[16], bv[16];
-#pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const bool live = 4 * k < m.z;
-        av[k] = (live && ca) ? L[(4 * k + lk) * m.y + c_lo + li] : 0.0;
-        bv[k] = (live && ra) ? L[(4 * k + lk) * m.y + r_lo + li] : 0.0;
-      }
-      d4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int k = 0; k < 16; ++k)
-        if (4 * k < m.z) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[k], bv[k], acc, 0, 0, 0);
-      if (ra) {
-        const int rv = d.sn_tvar[m.w + r_lo + li] - 16 * i;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int cc = c_lo + 4 * e + lk;
-          if (cc < c_hi) {
-            const int cv = d.sn_tvar[m.w + cc] - 16 * j;
-            if (16 * i + rv >= 16 * j + cv) T[cv * 16 + rv] -= acc[e];
-          }
-        }
-      }
-      wave_lds_sync();  // another lane may hold the same entry for the next supernode
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int x = lane + 64 * e, c = x >> 4, r = x & 15;
-      A[(int64_t)(16 * j + c) * g.ld + 16 * i + r] = T[x];
-    }
-    wave_lds_sync();
-  }
-}
-
-size_t gamma_tail_lds_bytes(int nq, int ld) {
-  const int nbt = ld / 16;
-  return sizeof(double) * ((TAIL_NT / 64) * 256 + 16) + sizeof(int) * (4 * (size_t)nq + 2 * (size_t)nq +
-                                                                        (size_t)nq * (nbt + 1) + nq);
+  *tgt = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -1342,18 +1231,14 @@ hipError_t launch_gamma_gather(const Dev& d, int s0, int ns, int nslot, int nn, 
   return hipGetLastError();
 }
 
-hipError_t launch_gamma_snode(const Dev& d, int s0, int ns, size_t lds, int ld, hipStream_t st) {
+hipError_t launch_gamma_snode(const Dev& d, int s0, int ns, size_t lds, hipStream_t st) {
   if (ns <= 0 || d.n_sn <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_gamma_snode, dim3(ns * d.n_sn_grp), dim3(SN_NT), lds, st, d, s0);
-  if (ld > 0)
-    hipLaunchKernelGGL(k_gamma_tail, dim3(ns * (ld / 16)), dim3(TAIL_NT), gamma_tail_lds_bytes(d.n_sn, ld), st,
-                       d, s0);
+  if (d.n_tail_ent > 0) {
+    const int nblk = (d.n_tail_ent + TAIL_NT - 1) / TAIL_NT;
+    hipLaunchKernelGGL(k_gamma_tail, dim3(ns * nblk), dim3(TAIL_NT), 0, st, d, s0, nblk);
+  }
   return hipGetLastError();
-}
-
-hipError_t allow_gamma_tail_lds(size_t bytes) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gamma_tail),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 hipError_t allow_gamma_snode_lds(size_t bytes) {

@@ -19,9 +19,7 @@ hipError_t allow_eliminate_lds(size_t bytes);
 // plan's sn_lds_bytes
 // supernodal elimination of the boundary system's leading buses (one
 // workgroup per snapshot and subtree group), then their tail updates
-hipError_t launch_gamma_snode(const Dev& d, int s0, int ns, size_t lds, int ld, hipStream_t st);
-hipError_t allow_gamma_tail_lds(size_t bytes);
-size_t gamma_tail_lds_bytes(int nq, int ld);
+hipError_t launch_gamma_snode(const Dev& d, int s0, int ns, size_t lds, hipStream_t st);
 hipError_t allow_gamma_snode_lds(size_t bytes);
 hipError_t launch_gamma_gather(const Dev& d, int s0, int ns, int nslot, int nn, hipStream_t st);
 // panel: stage each factor panel in LDS (needs dense_lds_bytes(ld, true))

@@ -306,24 +306,44 @@ void SysPlan::build_supernodes() {
     const int Wp = sn_cols_padded(sn[q].y), M = sn_rows_padded(sn[q].y, r);
     sn_cost[q] = (Wp / 16) * (7.0 + 0.6 * M / 16) + 1.5 * M / 16;
   }
-  // compact tail rows
+  // tail contributions: U_q and c_q offsets, and per tail entry the list of
+  // buffer offsets in supernode order
   sn3.clear();
-  sn_tpos.clear();
-  sn_tvar.clear();
+  tail_ent.clear();
+  tail_con.clear();
   tl_doubles = 0;
-  const int nbt = ld / 16;
+  const int nv = 2 * nt;
+  std::vector<std::vector<int32_t>> mat((size_t)nv * nv), rv(nv);
   for (int q = 0; q < nsn; ++q) {
-    const int r = sn[q].z, ntail = sn2[q].w;
+    const int r = sn[q].z, ntail = sn2[q].w, mt = 2 * ntail, nrs = r - ntail;
     const int32_t* R = sn_rows.data() + sn[q].w;
-    sn3.push_back({tl_doubles, (int32_t)sn_tpos.size(), (int32_t)sn_tvar.size(), 0});
-    for (int a = r - ntail; a < r; ++a) {
-      sn_tvar.push_back(2 * (R[a] - ne));
-      sn_tvar.push_back(2 * (R[a] - ne) + 1);
+    if (!ntail) {
+      sn3.push_back({0, 0, 0, 0});
+      continue;
     }
-    const int32_t* tv = sn_tvar.data() + sn3.back().z;
-    for (int t = 0; t <= nbt; ++t)
-      sn_tpos.push_back((int32_t)(std::lower_bound(tv, tv + 2 * ntail, 16 * t) - tv));
-    tl_doubles += ntail ? (sn_cols_padded(sn[q].y) * 2 * ntail + 31) / 32 * 32 : 0;
+    const int32_t uoff = tl_doubles;
+    tl_doubles += (mt * mt + 31) / 32 * 32;
+    const int32_t coff = tl_doubles;
+    tl_doubles += (mt + 31) / 32 * 32;
+    sn3.push_back({uoff, coff, 0, 0});
+    auto var = [&](int a) { return 2 * (R[nrs + a / 2] - ne) + (a & 1); };
+    for (int a = 0; a < mt; ++a) {
+      rv[var(a)].push_back(coff + a);
+      for (int c = 0; c < mt; ++c)
+        if (var(a) >= var(c)) mat[(size_t)var(c) * nv + var(a)].push_back(uoff + c * mt + a);
+    }
+  }
+  for (int c = 0; c < nv; ++c)
+    for (int a = c; a < nv; ++a) {
+      const auto& l = mat[(size_t)c * nv + a];
+      if (l.empty()) continue;
+      tail_ent.push_back({c * ld + a, 0, (int32_t)tail_con.size(), (int32_t)(tail_con.size() + l.size())});
+      tail_con.insert(tail_con.end(), l.begin(), l.end());
+    }
+  for (int a = 0; a < nv; ++a) {
+    if (rv[a].empty()) continue;
+    tail_ent.push_back({a, 1, (int32_t)tail_con.size(), (int32_t)(tail_con.size() + rv[a].size())});
+    tail_con.insert(tail_con.end(), rv[a].begin(), rv[a].end());
   }
   group_supernodes(1);
 }

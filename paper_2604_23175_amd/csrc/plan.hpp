@@ -97,11 +97,13 @@ struct SysPlan {
   std::vector<double> sn_cost;    // estimated elimination time of the supernode (arbitrary unit)
   std::vector<int32_t> sn_grp_ptr;  // [ngrp+1] -> sn_grp
   std::vector<int32_t> sn_grp;      // supernodes of each group, ascending
-  // Tail rows of each supernode's panel (R rows in the tail, 2 ntail of them)
-  // are copied to a compact per-snapshot buffer, column-major [Wp][2 ntail].
-  std::vector<I4> sn3;            // {offset in the compact buffer, base in sn_tpos, base in sn_tvar, 0}
-  std::vector<int32_t> sn_tpos;   // [nsn][ld/16 + 1]: first compact row of supernode q in tail tile t
-  std::vector<int32_t> sn_tvar;   // per supernode [2 ntail]: tail variable of each compact row
+  // The tail updates of each supernode, U_q = L_T L_T^T over its tail rows T
+  // (2 ntail of them, column-major 2 ntail x 2 ntail) and c_q = -L_T y_q, go to
+  // a per-snapshot buffer; each tail entry then gathers its contributions in
+  // supernode order.
+  std::vector<I4> sn3;            // {offset of U_q, offset of c_q, 0, 0} in that buffer
+  std::vector<I4> tail_ent;       // {target, 0 matrix (col * ld + row) / 1 rhs (variable), cbeg, cend}
+  std::vector<int32_t> tail_con;  // buffer offsets, per target in supernode order
   int32_t tl_doubles = 0;         // doubles of the compact buffer per snapshot
   std::vector<int32_t> bs_ptr;  // [nlev+1] -> bs_items (same levels, run top-down)
   std::vector<I4> bs_items;     // {diag_off, rhs_j, cbeg, cend}
