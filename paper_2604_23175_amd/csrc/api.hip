@@ -72,6 +72,13 @@ hipError_t launch_gamma_sparse(const mase_ctx* c, int s0, int ns, hipStream_t st
   return launch_eliminate(c->d, c->plan.n_area, 1, s0, ns, c->lds_el_gamma, st);
 }
 
+// Back substitution of the same part: supernodal after the supernodal
+// elimination, else level by level.
+hipError_t launch_gamma_back(const mase_ctx* c, int s0, int ns, hipStream_t st) {
+  if (c->gamma_snode) return launch_gamma_snode_back(c->d, s0, ns, c->lds_sn, st);
+  return launch_backsolve(c->d, c->plan.n_area, 1, s0, ns, st);
+}
+
 void append_rebased(std::vector<int32_t>& dst, const std::vector<int32_t>& src, int32_t base) {
   for (int32_t v : src) dst.push_back(v + base);
 }
@@ -211,21 +218,33 @@ int upload_plan(mase_ctx* c) {
   c->lds_el_gamma = 8 * (size_t)p.sys[K].lds_doubles;
   if (std::max(c->lds_el_area, c->lds_el_gamma) > 65536)
     HIPTRY(allow_eliminate_lds(std::max(c->lds_el_area, c->lds_el_gamma)));
-  // boundary dense block: stage each panel in LDS when it fits beside the
-  // kernel's static arrays (MASE_DENSE_PANEL=0 forces the global-memory variant)
+  // boundary dense block: the widest panel (up to 64 columns) that fits in
+  // LDS, else 16-column panels in LDS, else the matrix in HBM only
+  // (MASE_DENSE_PANEL=0/1/2 forces one of these)
   {
-    const size_t pan = dense_lds_bytes(p.sys[K].ld, true);
+    const int ld = p.sys[K].ld;
     const char* env = getenv("MASE_DENSE_PANEL");
-    c->dense_panel = pan + 8192 <= (size_t)maxlds && !(env && env[0] == '0');
-    if (c->dense_panel && pan > 65536) HIPTRY(allow_dense_lds(pan));
+    int nb = 64;
+    while (nb >= 16 && dense_lds_bytes(ld, DENSE_WIDE, nb) + 8192 > (size_t)maxlds) nb -= 16;
+    c->dense_nb = nb;
+    if (nb >= 16) c->dense_mode = DENSE_WIDE;
+    else if (dense_lds_bytes(ld, DENSE_PANEL16, 16) + 8192 <= (size_t)maxlds) c->dense_mode = DENSE_PANEL16;
+    else c->dense_mode = DENSE_GLOBAL;
+    if (env && env[0] >= '0' && env[0] <= '2' && env[0] - '0' <= c->dense_mode) c->dense_mode = env[0] - '0';
+    if (c->dense_mode == DENSE_WIDE) c->dense_nb = std::max(16, c->dense_nb);
+    const size_t bytes = dense_lds_bytes(ld, c->dense_mode, c->dense_nb);
+    if (c->dense_mode != DENSE_GLOBAL && bytes > 65536) HIPTRY(allow_dense_lds(c->dense_mode, bytes));
   }
   // supernodal boundary elimination (MASE_GAMMA_SNODE=0 selects the level engine)
   {
     const char* env = getenv("MASE_GAMMA_SNODE");
     c->lds_sn = (size_t)p.sys[K].sn_lds_bytes;
-    c->snode_possible = !p.sys[K].sn.empty() && c->lds_sn + 4096 <= (size_t)maxlds;
+    c->snode_possible = !p.sys[K].sn.empty() && c->lds_sn + 8192 <= (size_t)maxlds;
     c->gamma_snode = c->snode_possible && !(env && env[0] == '0');
-    if (c->gamma_snode && c->lds_sn > 65536) HIPTRY(allow_gamma_snode_lds(c->lds_sn));
+    if (c->snode_possible && c->lds_sn > 65536) {
+      HIPTRY(allow_gamma_snode_lds(c->lds_sn));
+      HIPTRY(allow_gamma_snode_back_lds(c->lds_sn));
+    }
     // subtree groups: as many workgroups per snapshot as fit the device at
     // once for the whole batch (MASE_SNODE_GROUPS overrides the limit)
     const int per_cu = std::max(1, (int)(160 * 1024 / std::max<size_t>(c->lds_sn, 1)));
@@ -374,11 +393,11 @@ int launch_gamma_part(mase_ctx* c, hipStream_t st, int s0, int ns) {
     }
     {
       StageMark m(c, st, MASE_STAGE_GAMMA_DENSE);
-      HIPTRY(launch_dense_chol(d, s0, ns, g.ld, c->dense_panel, st));
+      HIPTRY(launch_dense_chol(d, s0, ns, g.ld, c->dense_mode, c->dense_nb, st));
     }
     if (g.ne > 0) {
       StageMark m(c, st, MASE_STAGE_GAMMA_BACK);
-      HIPTRY(launch_backsolve(d, K, 1, s0, ns, st));
+      HIPTRY(launch_gamma_back(c, s0, ns, st));
     }
   }
   {
@@ -546,8 +565,8 @@ int launch_plain_iteration(mase_ctx* c, int s) {
   if (g.nn > 0) {
     HIPTRY(launch_gamma_gather(d, s, 1, c->nslot_g, g.nn, st));
     if (g.ne > 0) HIPTRY(launch_gamma_sparse(c, s, 1, st));
-    HIPTRY(launch_dense_chol(d, s, 1, g.ld, c->dense_panel, st));
-    if (g.ne > 0) HIPTRY(launch_backsolve(d, K, 1, s, 1, st));
+    HIPTRY(launch_dense_chol(d, s, 1, g.ld, c->dense_mode, c->dense_nb, st));
+    if (g.ne > 0) HIPTRY(launch_gamma_back(c, s, 1, st));
   }
   HIPTRY(hipEventRecord(c->ev_main, st));
   for (int i = 0; i < ns; ++i) HIPTRY(hipStreamWaitEvent(c->astreams[i], c->ev_main, 0));
@@ -1285,8 +1304,8 @@ int mase_stage_gamma_solve(mase_ctx* c) {
   const int K = c->plan.n_area, S = c->plan.n_snap;
   if (g.nn > 0) {
     if (g.ne > 0) HIPTRY(launch_gamma_sparse(c, 0, S, c->stream));
-    HIPTRY(launch_dense_chol(c->d, 0, S, g.ld, c->dense_panel, c->stream));
-    if (g.ne > 0) HIPTRY(launch_backsolve(c->d, K, 1, 0, S, c->stream));
+    HIPTRY(launch_dense_chol(c->d, 0, S, g.ld, c->dense_mode, c->dense_nb, c->stream));
+    if (g.ne > 0) HIPTRY(launch_gamma_back(c, 0, S, c->stream));
   }
   HIPTRY(hipStreamSynchronize(c->stream));
   return 0;

@@ -29,7 +29,8 @@ struct mase_ctx {
   size_t lds_asm = 0;
   bool br_lds = false;
   size_t lds_el_area = 0, lds_el_gamma = 0;  // elimination staging LDS bytes
-  bool dense_panel = false;                   // dense block panels staged in LDS
+  int dense_mode = 0;                         // DENSE_GLOBAL / DENSE_PANEL16 / DENSE_WIDE
+  int dense_nb = 16;                          // panel width of DENSE_WIDE
   bool gamma_snode = false;                   // supernodal boundary elimination
   size_t lds_sn = 0;                          // its LDS bytes
   int nslot_g = 0;

@@ -167,17 +167,18 @@ __device__ inline double bcast_lane(double v, int src) {
 // Cholesky of the 16x16 diagonal block at (cb, cb) of the column-major LDS
 // matrix P (pitch ldp) by one wave, with the forward solve of y[cb .. cb+15]
 // and the inverse X = L^-1 built alongside: lane r (mod 16) holds row r of L
-// and row r of X.  At step c, column c of L and row c of X are final; both are
-// shared through LDS (xbuf: 16 + 16 doubles) and every lower row subtracts its
-// multiple of them.  The step is branch-free: entries above the diagonal of a
-// lane's row of L pick up values that are never read or stored, and a
-// row's factor is zero where it must not change.  1/sqrt of the pivot comes
-// from the hardware estimate refined by two Newton steps.  L goes back to P;
-// Linv (row-major, pitch 17, zero above the diagonal) receives X, which turns
-// the solves against L below the block into products on MFMA.  A non-positive
+// and row r of X.  At step c, column c of L and row c of X are final; every
+// lower row subtracts its multiple of them, reading the other lanes' values
+// through the scalar unit (v_readlane), so the step needs no LDS round trip
+// and no barrier.  The step is branch-free: entries above the diagonal of a
+// lane's row of L pick up values that are never read or stored, and a row's
+// factor is zero where it must not change.  1/sqrt of the pivot comes from the
+// hardware estimate refined by two Newton steps.  L goes back to P; Linv
+// (row-major, pitch 17, zero above the diagonal) receives X, which turns the
+// solves against L below the block into products on MFMA.  A non-positive
 // pivot is replaced by 1 and reported by returning false.
 __device__ __attribute__((always_inline)) inline bool wave_chol16_inv(double* P, int ldp, int cb, double* y,
-                                                                      double* xbuf, double* Linv) {
+                                                                      double* Linv) {
   const int lane = threadIdx.x & 63;
   int rr = lane & 15;
   asm volatile("" : "+v"(rr));  // per-lane predicates stay here, not hoisted into the caller
@@ -208,18 +209,11 @@ __device__ __attribute__((always_inline)) inline bool wave_chol16_inv(double* P,
     const double yc = bcast_lane(yr, c);
     const double f = below ? a[c] : 0.0;  // L[r][c] for the rows that update
     yr -= f * yc;
-    // column c of L (entries below c) and row c of X
-    wave_lds_sync();  // the previous step's reads are done
-    if (lane < 16) xbuf[rr] = a[c];
-    if (lane == c) {
+    // A[r][m] -= L[r][c] L[m][c] (L[m][c] is lane m's a[c]); X[r][m] -= L[r][c] X[c][m]
 #pragma unroll
-      for (int m = 0; m <= c; ++m) xbuf[16 + m] = x[m];
-    }
-    wave_lds_sync();
+    for (int m = c + 1; m < 16; ++m) a[m] -= a[c] * bcast_lane(a[c], m);
 #pragma unroll
-    for (int m = c + 1; m < 16; ++m) a[m] -= a[c] * xbuf[m];
-#pragma unroll
-    for (int m = 0; m <= c; ++m) x[m] -= f * xbuf[16 + m];
+    for (int m = 0; m <= c; ++m) x[m] -= f * bcast_lane(x[m], c);
   }
   if (lane < 16) {
 #pragma unroll
@@ -636,7 +630,6 @@ __global__ void __launch_bounds__(DENSE_NT) k_dense_chol(Dev d, int s0) {
   double* Lp = bl + n;            // [n - 16][PANEL_PITCH]: rows below the diagonal block
   __shared__ double Dk[16 * 17];    // diagonal block, column-major, pitch 17
   __shared__ double Linv[16 * 17];  // its inverse factor, row-major
-  __shared__ double xbuf[32];
   __shared__ double part[16 * 16];
   __shared__ int bad;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -658,7 +651,7 @@ __global__ void __launch_bounds__(DENSE_NT) k_dense_chol(Dev d, int s0) {
     }
     __syncthreads();
     if (wv == 0) {
-      const bool ok = wave_chol16_inv(Dk, 17, 0, bl + c0, xbuf, Linv);
+      const bool ok = wave_chol16_inv(Dk, 17, 0, bl + c0, Linv);
       if (!ok && lane == 0) bad = 1;
     }
     __syncthreads();
@@ -773,6 +766,188 @@ __global__ void __launch_bounds__(DENSE_NT) k_dense_chol(Dev d, int s0) {
 }
 
 // ---------------------------------------------------------------------------
+// Stage 3b, wide panels: the same factorisation and solve with nb-column
+// panels (nb a multiple of 16, up to 64) staged whole in LDS.  A panel is
+// factored there in 16-column steps (wave-level 16x16 Cholesky with its
+// inverse, rows below on MFMA, the panel's later columns updated on MFMA),
+// written back, and the trailing matrix then takes one rank-nb update on
+// MFMA: nb/16 times fewer read-modify-write rounds over the trailing matrix
+// in HBM than 16-column steps need.  The rhs stays in LDS throughout.
+// ---------------------------------------------------------------------------
+constexpr int DW_NT = 512;
+
+__global__ void __launch_bounds__(DW_NT) k_dense_wide(Dev d, int s0, int nb) {
+  const int s = s0 + blockIdx.x;
+  if (!d.active[s]) return;
+  const SysMeta g = d.sys[d.n_area];
+  const int n = g.ld;
+  if (n == 0) return;
+  const int nlive = 2 * g.nt;
+  double* A = d.vals + (int64_t)s * d.vstride + g.val_off + g.tail_off;
+  double* b = d.rhs + (int64_t)s * d.rstride + g.rhs_off + 2 * g.ne;
+  extern __shared__ double dw[];
+  double* yv = dw;      // [n] rhs, then the solution
+  double* P = dw + n;   // [nb columns][M rows] of the current panel, M = n - c0, pitch M + 1
+  __shared__ double Linv[16 * 17];
+  __shared__ double part[16 * 16];
+  __shared__ int bad;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr int NW = DW_NT / 64, TB = 4, UL = 8;
+  const int li = lane & 15, lk = lane >> 4;
+  if (tid == 0) bad = 0;
+  for (int i = tid; i < n; i += DW_NT) yv[i] = (i < nlive) ? b[i] : 0.0;
+  // identity padding (lower triangle of the padded rows / columns)
+  for (int c = tid; c < n; c += DW_NT)
+    for (int r = (c > nlive ? c : nlive); r < n; ++r) A[(int64_t)c * n + r] = (r == c) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int c0 = 0; c0 < n; c0 += nb) {
+    const int w = min(nb, n - c0), M = n - c0, ldp = M + 1;  // odd pitch: columns in distinct banks
+    const double invM = 1.0 / M;
+    // (1) stage the panel's lower part, UL loads in flight per thread
+    for (int i0 = tid; i0 < w * M; i0 += UL * DW_NT) {
+      double v[UL];
+#pragma unroll
+      for (int u = 0; u < UL; ++u) {
+        const int i = i0 + u * DW_NT;
+        const int col = (int)((i + 0.5) * invM), row = i - col * M;
+        v[u] = (i < w * M && row >= col) ? A[(int64_t)(c0 + col) * n + c0 + row] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < UL; ++u) {
+        const int i = i0 + u * DW_NT;
+        const int col = (int)((i + 0.5) * invM), row = i - col * M;
+        if (i < w * M) P[col * ldp + row] = v[u];
+      }
+    }
+    __syncthreads();
+    // (2) factor the panel in 16-column steps
+    for (int cb = 0; cb < w; cb += 16) {
+      if (wv == 0) {
+        const bool ok = wave_chol16_inv(P, ldp, cb, yv + c0, Linv);
+        if (!ok && lane == 0) bad = 1;
+      }
+      __syncthreads();
+      // rows below the block: X = A L^-T, one 16-row tile per wave, on MFMA
+      const int rt0 = cb / 16 + 1, nrt = M / 16 - rt0;
+      for (int t = wv; t < nrt; t += NW) {
+        const int ri = 16 * (rt0 + t);
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const double a = P[(cb + 4 * e + lk) * ldp + ri + li];
+          const double bb = Linv[li * 17 + 4 * e + lk];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) P[(cb + li) * ldp + ri + 4 * e + lk] = acc[e];
+      }
+      __syncthreads();
+      // rhs of the rows below, and the panel's remaining columns
+      for (int row = cb + 16 + tid; row < M; row += DW_NT) {
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) acc += P[(cb + c) * ldp + row] * yv[c0 + cb + c];
+        yv[c0 + row] -= acc;
+      }
+      const int jt0 = cb / 16 + 1, njt = w / 16 - jt0, nrt2 = M / 16;
+      int ntile = 0;
+      for (int j = 0; j < njt; ++j) ntile += nrt2 - (jt0 + j);
+      for (int t = wv; t < ntile; t += NW) {
+        int j = 0, tt = t;
+        while (tt >= nrt2 - (jt0 + j)) {
+          tt -= nrt2 - (jt0 + j);
+          ++j;
+        }
+        const int rj = 16 * (jt0 + j), ri = rj + 16 * tt;
+        d4 acc;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] = P[(rj + li) * ldp + ri + 4 * e + lk];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const double a = -P[(cb + 4 * e + lk) * ldp + ri + li];
+          const double bb = P[(cb + 4 * e + lk) * ldp + rj + li];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) P[(rj + li) * ldp + ri + 4 * e + lk] = acc[e];
+      }
+      __syncthreads();
+    }
+    // (3) the factor back to HBM (lower part)
+    for (int i = tid; i < w * M; i += DW_NT) {
+      const int col = (int)((i + 0.5) * invM), row = i - col * M;
+      if (row >= col) A[(int64_t)(c0 + col) * n + c0 + row] = P[col * ldp + row];
+    }
+    // (4) trailing update A_IJ -= L_I L_J^T over the rows below the panel:
+    // tiles (I >= J); a wave loads TB tiles, updates them, stores them
+    const int mt = (M - w) / 16, ntile = mt * (mt + 1) / 2;
+    for (int t0 = wv; t0 < ntile; t0 += NW * TB) {
+      int ri[TB], rj[TB];
+      d4 acc[TB];
+#pragma unroll
+      for (int bq = 0; bq < TB; ++bq) {
+        const int t = t0 + bq * NW;
+        ri[bq] = -1;
+        if (t < ntile) {
+          int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+          while (I * (I + 1) / 2 > t) --I;
+          while ((I + 1) * (I + 2) / 2 <= t) ++I;
+          const int J = t - I * (I + 1) / 2;
+          ri[bq] = w + 16 * I;
+          rj[bq] = w + 16 * J;
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            acc[bq][q] = A[(int64_t)(c0 + rj[bq] + 4 * q + lk) * n + c0 + ri[bq] + li];
+        }
+      }
+#pragma unroll
+      for (int bq = 0; bq < TB; ++bq) {
+        if (ri[bq] < 0) continue;
+        // computed transposed (rows J x rows I): lane li holds row ri + li,
+        // so the accumulator's global accesses run down a column
+        for (int k4 = 0; k4 < w; k4 += 4) {
+          const double a = -P[(k4 + lk) * ldp + rj[bq] + li];
+          const double bb = P[(k4 + lk) * ldp + ri[bq] + li];
+          acc[bq] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc[bq], 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) A[(int64_t)(c0 + rj[bq] + 4 * q + lk) * n + c0 + ri[bq] + li] = acc[bq][q];
+      }
+    }
+    __syncthreads();
+  }
+  // back substitution L^T x = y, 16-column blocks from the bottom
+  for (int k = n / 16 - 1; k >= 0; --k) {
+    const int c0 = 16 * k;
+    if (tid < 256) {
+      const int c = tid >> 4, pp = tid & 15;  // 16 lanes read 16 consecutive rows of column c
+      double acc = 0.0;
+      for (int r = c0 + 16 + pp; r < n; r += 16) acc += A[(int64_t)(c0 + c) * n + r] * yv[r];
+      part[pp * 16 + c] = acc;
+    }
+    __syncthreads();
+    if (wv == 0) {
+      const int r = lane & 15;
+      double col[16];
+#pragma unroll
+      for (int mm = 0; mm < 16; ++mm) col[mm] = (mm >= r) ? A[(int64_t)(c0 + r) * n + c0 + mm] : 0.0;
+      double t = yv[c0 + r];
+      for (int pp = 0; pp < 16; ++pp) t -= part[pp * 16 + r];
+#pragma unroll
+      for (int c = 15; c >= 0; --c) {
+        if (r == c) t /= col[c];
+        const double xc = bcast_lane(t, c);
+        if (r < c) t -= col[c] * xc;
+      }
+      if (lane < 16) yv[c0 + r] = t;
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < nlive; i += DW_NT) b[i] = yv[i];
+  if (tid == 0 && bad) d.status[(int64_t)s * (d.n_area + 1) + d.n_area] = 1;
+}
+
+// ---------------------------------------------------------------------------
 // Stage 3b (sparse part, supernodal): elimination of the boundary system's
 // leading buses one supernode at a time (one workgroup per snapshot).  A
 // supernode is a run of buses whose factor columns share the row list R below
@@ -832,7 +1007,6 @@ __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
   double* tl = d.sn_tl + (int64_t)s * d.tl_stride;
   extern __shared__ double sl[];
   __shared__ double Linv[16 * 17];
-  __shared__ double xbuf[32];
   __shared__ int bad;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   constexpr int NW = SN_NT / 64, UL = 8, TB = 4;
@@ -846,15 +1020,16 @@ __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
     const int c0 = sn.x, w = sn.y, r = sn.z, rb = sn.w;
     const int nrs = r - sn2.w;  // R buses outside the tail
     const int W = 2 * w, Wp = (W + 15) & ~15, M = Wp + ((2 * r + 15) & ~15);
+    const int ldp = M + 1;  // odd pitch: the panel's columns start in distinct LDS banks
     const int T = sn2.y, ntg = r * (r + 1) / 2;
-    double* P = sl;            // [Wp columns][M rows]
-    double* yv = sl + M * Wp;  // [M]
+    double* P = sl;              // [Wp columns][M rows], pitch ldp
+    double* yv = sl + ldp * Wp;  // [M]
     int* tg = reinterpret_cast<int*>(yv + M);
-    for (int i = tid; i < M * Wp; i += SN_NT) P[i] = 0.0;
+    for (int i = tid; i < ldp * Wp; i += SN_NT) P[i] = 0.0;
     for (int i = tid; i < M; i += SN_NT) yv[i] = 0.0;
     __syncthreads();
     // (1) staging: UL loads in flight per thread; identity on the padding
-    if (tid < Wp - W) P[(W + tid) * M + W + tid] = 1.0;
+    if (tid < Wp - W) P[(W + tid) * ldp + W + tid] = 1.0;
     for (int i0 = tid; i0 < T; i0 += UL * SN_NT) {
       double v[UL];
 #pragma unroll
@@ -869,7 +1044,7 @@ __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
         int rowv, colv, kk, e, bb;
         sn_coords(i, w, r, Wp, rowv, colv, kk, e, bb);
         if (kk == 0 && e == 2) continue;  // upper entry of the diagonal block
-        P[colv * M + rowv] = v[u];
+        P[colv * ldp + rowv] = v[u];
       }
     }
     for (int i = tid; i < W; i += SN_NT) yv[i] = rhs[2 * c0 + i];
@@ -879,7 +1054,7 @@ __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
     // (2) blocked Cholesky of the panel and forward solve
     for (int cb = 0; cb < Wp; cb += 16) {
       if (wv == 0) {
-        const bool ok = wave_chol16_inv(P, M, cb, yv, xbuf, Linv);
+        const bool ok = wave_chol16_inv(P, ldp, cb, yv, Linv);
         if (!ok && lane == 0) bad = 1;
       }
       __syncthreads();
@@ -890,12 +1065,12 @@ __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
         d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const double a = P[(cb + 4 * e + lk) * M + ri + li];
+          const double a = P[(cb + 4 * e + lk) * ldp + ri + li];
           const double bb = Linv[li * 17 + 4 * e + lk];
           acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
         }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) P[(cb + li) * M + ri + 4 * e + lk] = acc[e];
+        for (int e = 0; e < 4; ++e) P[(cb + li) * ldp + ri + 4 * e + lk] = acc[e];
       }
       __syncthreads();
       // rhs of the rows below, and the remaining panel columns: tiles
@@ -903,7 +1078,7 @@ __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
       for (int row = cb + 16 + tid; row < M; row += SN_NT) {
         double acc = 0.0;
 #pragma unroll
-        for (int c = 0; c < 16; ++c) acc += P[(cb + c) * M + row] * yv[cb + c];
+        for (int c = 0; c < 16; ++c) acc += P[(cb + c) * ldp + row] * yv[cb + c];
         yv[row] -= acc;
       }
       const int jt0 = cb / 16 + 1, njt = Wp / 16 - jt0, nrt2 = M / 16;
@@ -918,15 +1093,15 @@ __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
         const int rj = 16 * (jt0 + j), ri = rj + 16 * tt;
         d4 acc;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc[e] = P[(rj + li) * M + ri + 4 * e + lk];
+        for (int e = 0; e < 4; ++e) acc[e] = P[(rj + li) * ldp + ri + 4 * e + lk];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const double a = -P[(cb + 4 * e + lk) * M + ri + li];
-          const double bb = P[(cb + 4 * e + lk) * M + rj + li];
+          const double a = -P[(cb + 4 * e + lk) * ldp + ri + li];
+          const double bb = P[(cb + 4 * e + lk) * ldp + rj + li];
           acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
         }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) P[(rj + li) * M + ri + 4 * e + lk] = acc[e];
+        for (int e = 0; e < 4; ++e) P[(rj + li) * ldp + ri + 4 * e + lk] = acc[e];
       }
       __syncthreads();
     }
@@ -937,11 +1112,11 @@ __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
       sn_coords(i, w, r, Wp, rowv, colv, kk, e, bb);
       double val;
       if (kk == 0) {
-        const double l00 = P[(2 * bb) * M + 2 * bb], l10 = P[(2 * bb) * M + 2 * bb + 1];
-        const double l11 = P[(2 * bb + 1) * M + 2 * bb + 1];
+        const double l00 = P[(2 * bb) * ldp + 2 * bb], l10 = P[(2 * bb) * ldp + 2 * bb + 1];
+        const double l11 = P[(2 * bb + 1) * ldp + 2 * bb + 1];
         val = (e == 0) ? l00 * l00 : (e == 3) ? l10 * l10 + l11 * l11 : l10 * l00;
       } else {
-        val = P[colv * M + rowv];
+        val = P[colv * ldp + rowv];
       }
       vals[sn2.x + i] = val;
     }
@@ -973,8 +1148,8 @@ __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
         const int ri = Wp + 16 * I, rj = Wp + 16 * J;
         acc[b] = d4{0.0, 0.0, 0.0, 0.0};
         for (int k4 = 0; k4 < Wp; k4 += 4) {
-          const double a = P[(k4 + lk) * M + rj + li];
-          const double bb = P[(k4 + lk) * M + ri + li];
+          const double a = P[(k4 + lk) * ldp + rj + li];
+          const double bb = P[(k4 + lk) * ldp + ri + li];
           acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc[b], 0, 0, 0);
         }
 #pragma unroll
@@ -1003,6 +1178,112 @@ __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
     __syncthreads();
   }
   if (tid == 0 && bad) d.status[(int64_t)s * (d.n_area + 1) + d.n_area] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// Stage 3c, supernodal back substitution of the boundary system's leading
+// buses (Eq. 8-11 through the cached factor), after the dense block has been
+// solved: one workgroup per (snapshot, subtree group), the group's supernodes
+// from the top down.  Per supernode the panel is staged in LDS (diagonal 2x2
+// blocks, stored as L_jj L_jj^T, are factored again), then
+// t = y_own - L_R^T x_R with x_R the solution of its row buses (tail or
+// ancestors in the same subtree, both final), and L_own^T x_own = t is solved
+// by one wave, one variable per lane.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(SN_NT) k_gamma_snode_back(Dev d, int s0) {
+  const int gi = blockIdx.x % d.n_sn_grp;
+  const int s = s0 + blockIdx.x / d.n_sn_grp;
+  if (!d.active[s]) return;
+  const SysMeta g = d.sys[d.n_area];
+  const double* vals = d.vals + (int64_t)s * d.vstride + g.val_off;
+  double* rhs = d.rhs + (int64_t)s * d.rstride + g.rhs_off;
+  extern __shared__ double sl[];
+  __shared__ double part[8 * 64];
+  __shared__ double tv[64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr int UL = 8;
+  const int qb = d.sn_grp_ptr[gi];
+  for (int qi = d.sn_grp_ptr[gi + 1] - 1; qi >= qb; --qi) {
+    const int q = d.sn_grp[qi];
+    const int4 sn = d.sn[q];
+    const int4 sn2 = d.sn2[q];
+    const int c0 = sn.x, w = sn.y, r = sn.z, rb = sn.w;
+    const int W = 2 * w, Wp = (W + 15) & ~15, M = Wp + ((2 * r + 15) & ~15);
+    const int ldp = M + 1;
+    const int T = sn2.y;
+    double* P = sl;              // [Wp columns][M rows], pitch ldp
+    double* xr = sl + ldp * Wp;  // [2 r] solution of the row buses
+    // (1) staging of the panel's stored factor
+    for (int i0 = tid; i0 < T; i0 += UL * SN_NT) {
+      double v[UL];
+#pragma unroll
+      for (int u = 0; u < UL; ++u) {
+        const int i = i0 + u * SN_NT;
+        v[u] = (i < T) ? vals[sn2.x + i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < UL; ++u) {
+        const int i = i0 + u * SN_NT;
+        if (i >= T) break;
+        int rowv, colv, kk, e, bb;
+        sn_coords(i, w, r, Wp, rowv, colv, kk, e, bb);
+        if (kk == 0 && e == 2) continue;  // upper entry of the diagonal block
+        P[colv * ldp + rowv] = v[u];
+      }
+    }
+    for (int i = tid; i < 2 * r; i += SN_NT) xr[i] = rhs[2 * d.sn_rows[rb + (i >> 1)] + (i & 1)];
+    if (tid < W) tv[tid] = rhs[2 * c0 + tid];
+    __syncthreads();
+    // diagonal blocks back from L_jj L_jj^T to L_jj
+    if (tid < w) {
+      const int j = 2 * tid;
+      double l00, l10, l11;
+      if (!chol2(P[j * ldp + j], P[j * ldp + j + 1], P[(j + 1) * ldp + j + 1], l00, l10, l11)) {
+        l00 = l11 = 1.0;
+        l10 = 0.0;
+      }
+      P[j * ldp + j] = l00;
+      P[j * ldp + j + 1] = l10;
+      P[(j + 1) * ldp + j + 1] = l11;
+    }
+    // (2) t = y_own - L_R^T x_R: column c by 8 threads, fixed-order sum
+    {
+      const int c = tid & 63, pp = tid >> 6;
+      double acc = 0.0;
+      if (c < W)
+        for (int j = pp; j < 2 * r; j += 8) acc += P[c * ldp + Wp + j] * xr[j];
+      part[pp * 64 + c] = acc;
+    }
+    __syncthreads();
+    // (3) L_own^T x = t by wave 0, lane c holding variable c (c < W), from
+    // the last variable up
+    if (wv == 0) {
+      double t = 0.0, rinv = 1.0;
+      if (lane < W) {
+        t = tv[lane];
+        for (int pp = 0; pp < 8; ++pp) t -= part[pp * 64 + lane];
+        rinv = 1.0 / P[lane * ldp + lane];
+      }
+      for (int c = W - 1; c >= 0; --c) {
+        if (lane == c) t *= rinv;
+        const double xc = bcast_lane(t, c);
+        if (lane < c) t -= P[lane * ldp + c] * xc;
+      }
+      if (lane < W) rhs[2 * c0 + lane] = t;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_gamma_snode_back(const Dev& d, int s0, int ns, size_t lds, hipStream_t st) {
+  if (ns <= 0 || d.n_sn <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gamma_snode_back, dim3(ns * d.n_sn_grp), dim3(SN_NT), lds, st, d, s0);
+  return hipGetLastError();
+}
+
+hipError_t allow_gamma_snode_back_lds(size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gamma_snode_back),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 // ---------------------------------------------------------------------------
@@ -1246,22 +1527,27 @@ hipError_t allow_gamma_snode_lds(size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-size_t dense_lds_bytes(int ld, bool panel) {
-  return sizeof(double) * ((size_t)ld + (panel ? (size_t)ld * PANEL_PITCH : 0));
+size_t dense_lds_bytes(int ld, int mode, int nb) {
+  if (mode == DENSE_WIDE) return sizeof(double) * ((size_t)ld + (size_t)nb * (ld + 1));
+  return sizeof(double) * ((size_t)ld + (mode == DENSE_PANEL16 ? (size_t)ld * PANEL_PITCH : 0));
 }
 
-hipError_t launch_dense_chol(const Dev& d, int s0, int ns, int ld, bool panel, hipStream_t st) {
+hipError_t launch_dense_chol(const Dev& d, int s0, int ns, int ld, int mode, int nb, hipStream_t st) {
   if (ld <= 0 || ns <= 0) return hipSuccess;
-  if (panel)
-    hipLaunchKernelGGL(k_dense_chol<true>, dim3(ns), dim3(DENSE_NT), dense_lds_bytes(ld, true), st, d, s0);
+  const size_t lds = dense_lds_bytes(ld, mode, nb);
+  if (mode == DENSE_WIDE)
+    hipLaunchKernelGGL(k_dense_wide, dim3(ns), dim3(DW_NT), lds, st, d, s0, nb);
+  else if (mode == DENSE_PANEL16)
+    hipLaunchKernelGGL(k_dense_chol<true>, dim3(ns), dim3(DENSE_NT), lds, st, d, s0);
   else
-    hipLaunchKernelGGL(k_dense_chol<false>, dim3(ns), dim3(DENSE_NT), dense_lds_bytes(ld, false), st, d, s0);
+    hipLaunchKernelGGL(k_dense_chol<false>, dim3(ns), dim3(DENSE_NT), lds, st, d, s0);
   return hipGetLastError();
 }
 
-hipError_t allow_dense_lds(size_t bytes) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dense_chol<true>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+hipError_t allow_dense_lds(int mode, size_t bytes) {
+  const void* f = mode == DENSE_WIDE ? reinterpret_cast<const void*>(&k_dense_wide)
+                                     : reinterpret_cast<const void*>(&k_dense_chol<true>);
+  return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 hipError_t launch_backsolve(const Dev& d, int sys0, int nsys, int s0, int ns, hipStream_t st, bool fixed_bnd) {

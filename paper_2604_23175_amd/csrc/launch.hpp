@@ -20,12 +20,18 @@ hipError_t allow_eliminate_lds(size_t bytes);
 // supernodal elimination of the boundary system's leading buses (one
 // workgroup per snapshot and subtree group), then their tail updates
 hipError_t launch_gamma_snode(const Dev& d, int s0, int ns, size_t lds, hipStream_t st);
+// back substitution of the same buses, supernode by supernode (after the dense block)
+hipError_t launch_gamma_snode_back(const Dev& d, int s0, int ns, size_t lds, hipStream_t st);
+hipError_t allow_gamma_snode_back_lds(size_t bytes);
 hipError_t allow_gamma_snode_lds(size_t bytes);
 hipError_t launch_gamma_gather(const Dev& d, int s0, int ns, int nslot, int nn, hipStream_t st);
-// panel: stage each factor panel in LDS (needs dense_lds_bytes(ld, true))
-size_t dense_lds_bytes(int ld, bool panel);
-hipError_t launch_dense_chol(const Dev& d, int s0, int ns, int ld, bool panel, hipStream_t st);
-hipError_t allow_dense_lds(size_t bytes);
+// variants of the dense block's factorisation: 16-column steps on the matrix
+// in HBM, the same with each 16-column panel staged in LDS, or nb-column
+// panels staged whole in LDS (nb a multiple of 16, at most 64)
+enum { DENSE_GLOBAL = 0, DENSE_PANEL16 = 1, DENSE_WIDE = 2 };
+size_t dense_lds_bytes(int ld, int mode, int nb);
+hipError_t launch_dense_chol(const Dev& d, int s0, int ns, int ld, int mode, int nb, hipStream_t st);
+hipError_t allow_dense_lds(int mode, size_t bytes);
 // fixed_bnd (areas): dx_b = 0 instead of E_k dx_Gamma (a local step, Eq. 6)
 hipError_t launch_backsolve(const Dev& d, int sys0, int nsys, int s0, int ns, hipStream_t st,
                             bool fixed_bnd = false);

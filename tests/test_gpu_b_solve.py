@@ -149,23 +149,28 @@ def test_dense_and_sparse_gamma_agree():
 
 
 @pytest.mark.parametrize("gm", ["sparse", "dense"])
-def test_dense_block_panel_variants_bitwise_identical(gm, monkeypatch):
-    # The boundary block's Cholesky stages each panel in LDS when it fits;
-    # MASE_DENSE_PANEL=0 selects the variant that reads panels from HBM.
-    # Both do the same arithmetic in the same order.
+def test_dense_block_panel_variants(gm, monkeypatch):
+    # The boundary block's Cholesky uses the widest panels that fit in LDS
+    # (MASE_DENSE_PANEL=2); =1 stages 16-column panels in LDS and =0 reads them
+    # from HBM.  1 and 0 do the same arithmetic in the same order (bitwise
+    # equal); wide panels sum the trailing updates in another order.
     say("dense panel variants", gm)
     c = Case("c1", 2, seed=11)
     mode = mase.MASE_GAMMA_SPARSE if gm == "sparse" else mase.MASE_GAMMA_DENSE
     res = []
-    for flag in ("1", "0"):
+    for flag in ("2", "1", "0"):
         monkeypatch.setenv("MASE_DENSE_PANEL", flag)
         m = c.ctx(gamma_mode=mode)
         iters, conv = m.mase_solve(1e-8, 12)
+        assert conv.all()
         res.append((m.mase_state(), iters))
         m.close()
-    np.testing.assert_array_equal(res[0][0][0], res[1][0][0])
-    np.testing.assert_array_equal(res[0][0][1], res[1][0][1])
+    np.testing.assert_array_equal(res[1][0][0], res[2][0][0])
+    np.testing.assert_array_equal(res[1][0][1], res[2][0][1])
+    np.testing.assert_array_equal(res[1][1], res[2][1])
     np.testing.assert_array_equal(res[0][1], res[1][1])
+    for i in range(2):
+        assert_state_close(res[0][0][0][i], res[0][0][1][i], res[1][0][0][i], res[1][0][1][i], 1e-10)
 
 
 @pytest.mark.parametrize("name", ["c1", "k8"])
