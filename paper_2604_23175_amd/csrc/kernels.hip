@@ -240,16 +240,31 @@ __device__ inline double block_max(double v, double* red) {
   return t;
 }
 
-// 2x2 Cholesky of [[a00, .], [a10, a11]]; false on a non-positive pivot.
-__device__ inline bool chol2(double a00, double a10, double a11, double& l00, double& l10,
-                             double& l11) {
+// 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton steps.
+__device__ inline double rsq_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  r = r * (1.5 - 0.5 * x * r * r);
+  return r * (1.5 - 0.5 * x * r * r);
+}
+
+// 2x2 Cholesky of [[a00, .], [a10, a11]] with the reciprocals i00 = 1/l00,
+// i11 = 1/l11 (the solves multiply by them); false on a non-positive pivot.
+__device__ inline bool chol2(double a00, double a10, double a11, double& l00, double& l10, double& l11,
+                             double& i00, double& i11) {
   if (!(a00 > 0.0)) return false;
-  l00 = sqrt(a00);
-  l10 = a10 / l00;
+  i00 = rsq_nr(a00);
+  l00 = a00 * i00;
+  l10 = a10 * i00;
   const double p = a11 - l10 * l10;
   if (!(p > 0.0)) return false;
-  l11 = sqrt(p);
+  i11 = rsq_nr(p);
+  l11 = p * i11;
   return true;
+}
+
+__device__ inline bool chol2(double a00, double a10, double a11, double& l00, double& l10, double& l11) {
+  double i00, i11;
+  return chol2(a00, a10, a11, l00, l10, l11, i00, i11);
 }
 
 }  // namespace
@@ -460,11 +475,15 @@ __global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int
     for (int it = c0 + tid; it < c1; it += NT) {
       const int4 c = (it == c0 + tid) ? cpre : d.cd_items[it];
       const double* D = vals + c.x;
-      double l00, l10, l11;
-      if (!chol2(D[0], D[1], D[3], l00, l10, l11)) { bad = true; l00 = l11 = 1.0; l10 = 0.0; }
+      double l00, l10, l11, i00, i11;
+      if (!chol2(D[0], D[1], D[3], l00, l10, l11, i00, i11)) {
+        bad = true;
+        l00 = l11 = i00 = i11 = 1.0;
+        l10 = 0.0;
+      }
       if (c.y < 0) {
-        const double y0 = rhs[c.z] / l00;
-        const double y1 = (rhs[c.z + 1] - l10 * y0) / l11;
+        const double y0 = rhs[c.z] * i00;
+        const double y1 = (rhs[c.z + 1] - l10 * y0) * i11;
         rhs[c.z] = y0;
         rhs[c.z + 1] = y1;
         lst[c.w] = y0;
@@ -473,8 +492,8 @@ __global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int
         double* M = vals + c.y;  // X L^T = M
         const double2 m0 = *reinterpret_cast<const double2*>(M);
         const double2 m1 = *reinterpret_cast<const double2*>(M + 2);
-        const double x00 = m0.x / l00, x10 = m0.y / l00;
-        const double x01 = (m1.x - x00 * l10) / l11, x11 = (m1.y - x10 * l10) / l11;
+        const double x00 = m0.x * i00, x10 = m0.y * i00;
+        const double x01 = (m1.x - x00 * l10) * i11, x11 = (m1.y - x10 * l10) * i11;
         *reinterpret_cast<double2*>(M) = make_double2(x00, x10);
         *reinterpret_cast<double2*>(M + 2) = make_double2(x01, x11);
         *reinterpret_cast<double2*>(lst + c.w) = make_double2(x00, x10);
@@ -1376,11 +1395,14 @@ __global__ void __launch_bounds__(NT) k_backsolve(Dev d, int sys0, int nsys, int
         t0 = rhs[b.y] - t0;
         t1 = rhs[b.y + 1] - t1;
         const double* D = vals + b.x;
-        double l00, l10, l11;
-        if (!chol2(D[0], D[1], D[3], l00, l10, l11)) { l00 = l11 = 1.0; l10 = 0.0; }
-        const double x1 = t1 / l11;
+        double l00, l10, l11, i00, i11;
+        if (!chol2(D[0], D[1], D[3], l00, l10, l11, i00, i11)) {
+          l00 = l11 = i00 = i11 = 1.0;
+          l10 = 0.0;
+        }
+        const double x1 = t1 * i11;
         rhs[b.y + 1] = x1;
-        rhs[b.y] = (t0 - l10 * x1) / l00;
+        rhs[b.y] = (t0 - l10 * x1) * i00;
       }
     }
     __syncthreads();
