@@ -1230,6 +1230,7 @@ int mase_info(const mase_ctx* c, int32_t what, int64_t* value) {
     case MASE_INFO_GAMMA_SUPERNODES: v = (int64_t)p.sys[p.n_area].sn.size(); break;
     case MASE_INFO_GAMMA_SUPERNODAL: v = c->gamma_snode ? 1 : 0; break;
     case MASE_INFO_PIPELINE_GROUPS: v = c->npipe; break;
+    case MASE_INFO_GAMMA_SUBTREE_GROUPS: v = c->d.n_sn_grp; break;
     default: return fail(MASE_ERR_ARG, "unknown info key");
   }
   *value = v;

@@ -364,3 +364,29 @@ def test_local_steps_need_batched_schedule():
         c.ctx(local_steps=1, batched=False)
     with pytest.raises(mase.MaseError):
         c.ctx(local_steps=-1)
+
+
+@pytest.mark.parametrize("name", ["c1", "k8"])
+def test_subtree_groups_bitwise_identical(name, monkeypatch):
+    # The supernodal boundary elimination runs independent elimination
+    # subtrees in separate workgroups and applies every update of the dense
+    # block in supernode order afterwards, so the number of groups changes
+    # nothing in the arithmetic.
+    say("subtree groups", name)
+    c = Case(name, 3, seed=19)
+    res = []
+    for cap in ("1", "64"):
+        monkeypatch.setenv("MASE_SNODE_GROUPS", cap)
+        m = c.ctx()
+        if m.mase_info("gamma_supernodal") != 1:
+            pytest.skip("boundary system not supernodal on this grid")
+        groups = m.mase_info("gamma_subtree_groups")
+        iters, conv = m.mase_solve(1e-8, 12)
+        assert conv.all()
+        res.append((groups, m.mase_state(), iters))
+        m.close()
+    say("  groups", res[0][0], "->", res[1][0])
+    assert res[0][0] == 1 and res[1][0] >= 1
+    np.testing.assert_array_equal(res[0][1][0], res[1][1][0])
+    np.testing.assert_array_equal(res[0][1][1], res[1][1][1])
+    np.testing.assert_array_equal(res[0][2], res[1][2])
