@@ -348,18 +348,20 @@ __global__ void __launch_bounds__(ASM_NT) k_assemble(Dev d, int a0, int na, int 
     }
     return;
   }
-  // objective J = sum w r^2 over the area's rows (Eq. 2)
-  double jl = 0.0;
-  for (int r = tid; r < am.nrow; r += nt) {
-    const int4 rec = d.rowrec[am.row + r];
-    double h, a1, a2, a3, a4;
-    X.eval2(rec, ROLE_SELF, ROLE_SELF, h, a1, a2, a3, a4);
-    const double res = zs[rec.z] - h;
-    jl += d.w[rec.z] * res * res;
+  // objective J = sum w r^2 over the area's rows (Eq. 2), objective mode only
+  if (mode == MODE_OBJECTIVE) {
+    double jl = 0.0;
+    for (int r = tid; r < am.nrow; r += nt) {
+      const int4 rec = d.rowrec[am.row + r];
+      double h, a1, a2, a3, a4;
+      X.eval2(rec, ROLE_SELF, ROLE_SELF, h, a1, a2, a3, a4);
+      const double res = zs[rec.z] - h;
+      jl += d.w[rec.z] * res * res;
+    }
+    const double jt = block_sum(jl, red);
+    if (tid == 0) d.jpart[(int64_t)s * d.n_area + k] = jt;
+    return;
   }
-  const double jt = block_sum(jl, red);
-  if (tid == 0) d.jpart[(int64_t)s * d.n_area + k] = jt;
-  if (mode == MODE_OBJECTIVE) return;
 
   // G^k slots: slot += w * h_p h_q^T over the slot's contributions.  The
   // diagonal slot (v, v) also sums b_v = sum w r h_v (Eq. 7) over its
