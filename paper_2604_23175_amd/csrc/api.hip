@@ -258,6 +258,9 @@ int upload_plan(mase_ctx* c) {
 
   Dev& d = c->d;
   d.n_bus = p.n_bus; d.n_meas = p.n_meas; d.n_area = K; d.n_snap = p.n_snap; d.slack = p.slack;
+  d.bs_max_nn_area = 0;
+  for (int k = 0; k < K; ++k) d.bs_max_nn_area = std::max(d.bs_max_nn_area, (int32_t)p.sys[k].nn);
+  d.bs_max_nn_gamma = p.sys[K].nn;
   d.vstride = p.vstride; d.rstride = p.rstride;
   int rc = 0;
 #define UP(field, vec) if ((rc = upload(c, vec, &d.field))) return rc

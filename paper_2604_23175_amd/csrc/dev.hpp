@@ -32,6 +32,7 @@ enum { MODE_ASSEMBLE = 0, MODE_OBJECTIVE = 1, MODE_EVAL_H = 2 };
 struct Dev {
   // sizes
   int32_t n_bus, n_meas, n_area, n_snap, slack;
+  int32_t bs_max_nn_area, bs_max_nn_gamma;  // largest local bus counts (back substitution LDS)
   int64_t vstride, rstride;
   // plan
   const SysMeta* sys;

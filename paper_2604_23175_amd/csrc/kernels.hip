@@ -1349,7 +1349,7 @@ __global__ void __launch_bounds__(TAIL_NT) k_gamma_tail(Dev d, int s0, int nblk)
 // which is Eq. 8 through the cached factor.  Each column's sum is split over
 // a group of 8 lanes and combined by a fixed shuffle tree.
 // ---------------------------------------------------------------------------
-template <int NT>
+template <int NT, bool XL>
 __global__ void __launch_bounds__(NT) k_backsolve(Dev d, int sys0, int nsys, int s0, int ns, int fixed_bnd) {
   // lanes per column: the boundary system's levels hold a few wide columns,
   // an area's levels many narrow ones
@@ -1365,14 +1365,22 @@ __global__ void __launch_bounds__(NT) k_backsolve(Dev d, int sys0, int nsys, int
   double* rb = d.rhs + (int64_t)s * d.rstride;
   double* rhs = rb + sm.rhs_off;
   const int tid = threadIdx.x;
+  // the system's rhs lives in LDS for the whole substitution (y in, x out),
+  // or stays in HBM when the largest system's does not fit
+  extern __shared__ double xlds[];
+  double* xl = XL ? xlds : rhs;
+  if (XL)
+    for (int i = tid; i < 2 * sm.ne; i += NT) xl[i] = rhs[i];
   if (is_area) {
     const AreaMeta am = d.area[k];
     for (int t = tid; t < sm.nt; t += NT) {
       // dx_b = E_k dx_Gamma, or 0 for a local step with the boundary fixed
       const int src = d.tail_src[am.tail_src + t];
-      rhs[2 * (sm.ne + t)] = fixed_bnd ? 0.0 : rb[src];
-      rhs[2 * (sm.ne + t) + 1] = fixed_bnd ? 0.0 : rb[src + 1];
+      xl[2 * (sm.ne + t)] = fixed_bnd ? 0.0 : rb[src];
+      xl[2 * (sm.ne + t) + 1] = fixed_bnd ? 0.0 : rb[src + 1];
     }
+  } else if (XL) {
+    for (int i = 2 * sm.ne + tid; i < 2 * sm.nn; i += NT) xl[i] = rhs[i];
   }
   __syncthreads();
   const int grp = tid / G, gl = tid % G;
@@ -1384,7 +1392,7 @@ __global__ void __launch_bounds__(NT) k_backsolve(Dev d, int sys0, int nsys, int
       for (int c = b.z + gl; c < b.w; c += G) {
         const int2 u = d.bs_con[c];
         const double* L = vals + u.x;
-        const double x0 = rhs[u.y], x1 = rhs[u.y + 1];
+        const double x0 = xl[u.y], x1 = xl[u.y + 1];
         t0 += L[0] * x0 + L[1] * x1;
         t1 += L[2] * x0 + L[3] * x1;
       }
@@ -1394,8 +1402,8 @@ __global__ void __launch_bounds__(NT) k_backsolve(Dev d, int sys0, int nsys, int
         t1 += __shfl_xor(t1, off, G);
       }
       if (gl == 0) {
-        t0 = rhs[b.y] - t0;
-        t1 = rhs[b.y + 1] - t1;
+        t0 = xl[b.y] - t0;
+        t1 = xl[b.y + 1] - t1;
         const double* D = vals + b.x;
         double l00, l10, l11, i00, i11;
         if (!chol2(D[0], D[1], D[3], l00, l10, l11, i00, i11)) {
@@ -1403,12 +1411,14 @@ __global__ void __launch_bounds__(NT) k_backsolve(Dev d, int sys0, int nsys, int
           l10 = 0.0;
         }
         const double x1 = t1 * i11;
-        rhs[b.y + 1] = x1;
-        rhs[b.y] = (t0 - l10 * x1) * i00;
+        xl[b.y + 1] = x1;
+        xl[b.y] = (t0 - l10 * x1) * i00;
       }
     }
     __syncthreads();
   }
+  if (XL)
+    for (int i = tid; i < 2 * sm.nn; i += NT) rhs[i] = xl[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -1494,6 +1504,7 @@ __global__ void k_reset_flags(Dev d) {
 // Launch wrappers
 // ---------------------------------------------------------------------------
 constexpr int AREA_NT = 256;   // level kernels over areas: many workgroups
+constexpr size_t BACKSOLVE_LDS_MAX = 65536;  // rhs staged in LDS up to 4096 buses per system
 constexpr int GAMMA_NT = 1024; // level kernels over the one boundary system
 
 size_t assemble_lds_bytes(int nn, int nbr, bool br_lds) {
@@ -1576,11 +1587,24 @@ hipError_t allow_dense_lds(int mode, size_t bytes) {
 
 hipError_t launch_backsolve(const Dev& d, int sys0, int nsys, int s0, int ns, hipStream_t st, bool fixed_bnd) {
   if (nsys <= 0 || ns <= 0) return hipSuccess;
-  if (sys0 >= d.n_area)
-    hipLaunchKernelGGL(k_backsolve<GAMMA_NT>, dim3(nsys * ns), dim3(GAMMA_NT), 0, st, d, sys0, nsys, s0, ns, 0);
-  else
-    hipLaunchKernelGGL(k_backsolve<AREA_NT>, dim3(nsys * ns), dim3(AREA_NT), 0, st, d, sys0, nsys, s0, ns,
-                       fixed_bnd ? 1 : 0);
+  // LDS: the largest system's rhs (2 doubles per local bus), if it fits
+  if (sys0 >= d.n_area) {
+    const size_t lds = 16 * (size_t)d.bs_max_nn_gamma;
+    if (lds <= BACKSOLVE_LDS_MAX)
+      hipLaunchKernelGGL((k_backsolve<GAMMA_NT, true>), dim3(nsys * ns), dim3(GAMMA_NT), lds, st, d, sys0, nsys, s0,
+                         ns, 0);
+    else
+      hipLaunchKernelGGL((k_backsolve<GAMMA_NT, false>), dim3(nsys * ns), dim3(GAMMA_NT), 0, st, d, sys0, nsys, s0,
+                         ns, 0);
+  } else {
+    const size_t lds = 16 * (size_t)d.bs_max_nn_area;
+    if (lds <= BACKSOLVE_LDS_MAX)
+      hipLaunchKernelGGL((k_backsolve<AREA_NT, true>), dim3(nsys * ns), dim3(AREA_NT), lds, st, d, sys0, nsys, s0,
+                         ns, fixed_bnd ? 1 : 0);
+    else
+      hipLaunchKernelGGL((k_backsolve<AREA_NT, false>), dim3(nsys * ns), dim3(AREA_NT), 0, st, d, sys0, nsys, s0,
+                         ns, fixed_bnd ? 1 : 0);
+  }
   return hipGetLastError();
 }
 
