@@ -433,8 +433,8 @@ __global__ void __launch_bounds__(ASM_NT) k_assemble(Dev d, int a0, int na, int 
 // sum_j L_ij y_j.  After the last level the tail holds the Schur complement
 // S_b = G_bb - G_bi G_ii^-1 G_ib and the tail rhs holds bhat_b (Eq. 9-10).
 // ---------------------------------------------------------------------------
-template <int NT>
-__global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int s0, int ns) {
+template <int NT, bool RL>
+__global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int s0, int ns, int lstride) {
   int si, s;
   area_snap_of_block(blockIdx.x, nsys, ns, si, s);
   s += s0;
@@ -442,11 +442,18 @@ __global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int
   const int k = (sys0 < d.n_area) ? d.area_order[sys0 + si] : sys0 + si;
   const SysMeta sm = d.sys[k];
   double* vals = d.vals + (int64_t)s * d.vstride + sm.val_off;
-  double* rhs = d.rhs + (int64_t)s * d.rstride + sm.rhs_off;
-  // the level's new factor blocks (4 doubles each) and y_j (2 each)
+  double* rhs_g = d.rhs + (int64_t)s * d.rstride + sm.rhs_off;
+  // the level's new factor blocks (4 doubles each) and y_j (2 each); after
+  // them (lstride doubles in) the system's rhs, kept in LDS throughout when
+  // the largest system's fits (RL)
   extern __shared__ double2 lstage2[];
   double* lst = reinterpret_cast<double*>(lstage2);
+  double* rhs = RL ? lst + lstride : rhs_g;
   const int tid = threadIdx.x;
+  if (RL) {
+    for (int i = tid; i < 2 * sm.nn; i += NT) rhs[i] = rhs_g[i];
+    __syncthreads();
+  }
   bool bad = false;
   // UB targets per thread and pass: their records, then their current
   // values, are loaded together so the global round trips overlap.  The
@@ -570,6 +577,8 @@ __global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int
     }
     __syncthreads();
   }
+  if (RL)
+    for (int i = tid; i < 2 * sm.nn; i += NT) rhs_g[i] = rhs[i];
   if (bad) d.status[(int64_t)s * (d.n_area + 1) + k] = 1;
 }
 
@@ -1505,6 +1514,7 @@ __global__ void k_reset_flags(Dev d) {
 // ---------------------------------------------------------------------------
 constexpr int AREA_NT = 256;   // level kernels over areas: many workgroups
 constexpr size_t BACKSOLVE_LDS_MAX = 65536;  // rhs staged in LDS up to 4096 buses per system
+constexpr size_t ELIM_LDS_MAX = 65536;       // elimination staging + rhs in LDS up to this size
 constexpr int GAMMA_NT = 1024; // level kernels over the one boundary system
 
 size_t assemble_lds_bytes(int nn, int nbr, bool br_lds) {
@@ -1525,19 +1535,38 @@ hipError_t launch_assemble(const Dev& d, int a0, int na, int s0, int ns, int mod
 
 hipError_t launch_eliminate(const Dev& d, int sys0, int nsys, int s0, int ns, size_t lds, hipStream_t st) {
   if (nsys <= 0 || ns <= 0) return hipSuccess;
-  if (sys0 >= d.n_area)
-    hipLaunchKernelGGL(k_eliminate<GAMMA_NT>, dim3(nsys * ns), dim3(GAMMA_NT), lds, st, d, sys0, nsys, s0, ns);
-  else
-    hipLaunchKernelGGL(k_eliminate<AREA_NT>, dim3(nsys * ns), dim3(AREA_NT), lds, st, d, sys0, nsys, s0, ns);
+  // LDS: the staging area (lds bytes), then the largest system's rhs when
+  // the two fit in ELIM_LDS_MAX
+  const int lstride = (int)(lds / sizeof(double));
+  const bool gamma = sys0 >= d.n_area;
+  const size_t rl = 16 * (size_t)(gamma ? d.bs_max_nn_gamma : d.bs_max_nn_area);
+  const bool in_lds = lds + rl <= ELIM_LDS_MAX;
+  const size_t bytes = in_lds ? lds + rl : lds;
+  const dim3 grid(nsys * ns);
+  if (gamma) {
+    if (in_lds)
+      hipLaunchKernelGGL((k_eliminate<GAMMA_NT, true>), grid, dim3(GAMMA_NT), bytes, st, d, sys0, nsys, s0, ns, lstride);
+    else
+      hipLaunchKernelGGL((k_eliminate<GAMMA_NT, false>), grid, dim3(GAMMA_NT), bytes, st, d, sys0, nsys, s0, ns, lstride);
+  } else {
+    if (in_lds)
+      hipLaunchKernelGGL((k_eliminate<AREA_NT, true>), grid, dim3(AREA_NT), bytes, st, d, sys0, nsys, s0, ns, lstride);
+    else
+      hipLaunchKernelGGL((k_eliminate<AREA_NT, false>), grid, dim3(AREA_NT), bytes, st, d, sys0, nsys, s0, ns, lstride);
+  }
   return hipGetLastError();
 }
 
 hipError_t allow_eliminate_lds(size_t bytes) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eliminate<GAMMA_NT>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eliminate<AREA_NT>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  const void* f[4] = {reinterpret_cast<const void*>(&k_eliminate<GAMMA_NT, true>),
+                      reinterpret_cast<const void*>(&k_eliminate<GAMMA_NT, false>),
+                      reinterpret_cast<const void*>(&k_eliminate<AREA_NT, true>),
+                      reinterpret_cast<const void*>(&k_eliminate<AREA_NT, false>)};
+  for (const void* fn : f) {
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_gamma_gather(const Dev& d, int s0, int ns, int nslot, int nn, hipStream_t st) {
