@@ -74,17 +74,24 @@ def run_cpu_baseline(budget_s):
 
 
 def traffic_for(kernel):
-    """Counter-measured HBM bytes per launch, if taken on the current kernel source."""
+    """Counter-measured HBM bytes per launch and the kernel's full name, if taken on
+    the current kernel source.  `kernel` is a name prefix ("k_eliminate<256"
+    matches the template instance the counters saw, e.g. "k_eliminate<256, true>");
+    among several matches the one with the most dispatches wins."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
-        return None
+        return None, kernel
     src = open(os.path.join(ROOT, "paper_2604_23175_amd", "csrc", "kernels.hip"), "rb").read()
     digest = hashlib.sha256(src).hexdigest()[:16]
     d = json.load(open(path))
-    ent = d.get(kernel)
-    if not ent or ent.get("kernels_sha") != digest:
-        return None
-    return ent.get("bytes_per_launch")
+    hits = [(v.get("dispatches", 0), k) for k, v in d.items() if k.startswith(kernel) and isinstance(v, dict)]
+    if not hits:
+        return None, kernel
+    name = max(hits)[1]
+    ent = d[name]
+    if ent.get("kernels_sha") != digest:
+        return None, name
+    return ent.get("bytes_per_launch"), name
 
 
 def k_sweep(ks, steps, warmup):
@@ -433,9 +440,9 @@ def main():
                 "backsolve": ("hbm", info["bytes_backsolve"]), "gamma_dense": ("mfma", info["flops_dense"]),
                 "gamma_sparse": ("alu", info["flops_gamma_sparse"])}
     stages = {k: v for k, v in prof.items() if v["launches"]}
-    kernel_names = {"assemble": "k_assemble", "condense": "k_eliminate<256>", "backsolve": "k_backsolve<256>",
-                    "gamma_dense": "k_dense_chol",
-                    "gamma_sparse": "k_gamma_snode" if info["gamma_supernodal"] else "k_eliminate<1024>"}
+    kernel_names = {"assemble": "k_assemble", "condense": "k_eliminate<256", "backsolve": "k_backsolve<256",
+                    "gamma_dense": "k_dense",
+                    "gamma_sparse": "k_gamma_snode" if info["gamma_supernodal"] else "k_eliminate<1024"}
     dom = max((k for k in stages if k in per_unit), key=lambda k: stages[k]["ms"])
     bound, unit_work = per_unit[dom]
     st = stages[dom]
@@ -444,9 +451,10 @@ def main():
     achieved = unit_work * units_per_launch / (avg_ms * 1e-3)
     peak = HBM_PEAK if bound == "hbm" else FP64_PEAK
     scale = 1e9 if bound == "hbm" else 1e12
-    roofline = {"bound": bound, "kernel": kernel_names[dom], "achieved": achieved / scale,
+    traffic, kname = traffic_for(kernel_names[dom])
+    roofline = {"bound": bound, "kernel": kname, "achieved": achieved / scale,
                 "peak": peak / scale, "unit": "GB/s" if bound == "hbm" else "TFLOP/s", "frac": achieved / peak,
-                "traffic": traffic_for(kernel_names[dom]), "avg_launch_ms": avg_ms,
+                "traffic": traffic, "avg_launch_ms": avg_ms,
                 "per_snapshot_work": unit_work, "snapshots_per_launch": units_per_launch}
     others = {}
     for k, (b, w) in per_unit.items():
