@@ -164,65 +164,82 @@ __device__ inline double bcast_lane(double v, int src) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton steps.
+__device__ inline double rsq_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  r = r * (1.5 - 0.5 * x * r * r);
+  return r * (1.5 - 0.5 * x * r * r);
+}
+
 // Cholesky of the 16x16 diagonal block at (cb, cb) of the column-major LDS
 // matrix P (pitch ldp) by one wave, with the forward solve of y[cb .. cb+15]
-// and the inverse X = L^-1 built alongside: lane r (mod 16) holds row r of L
-// and row r of X.  At step c, column c of L and row c of X are final; every
-// lower row subtracts its multiple of them, reading the other lanes' values
-// through the scalar unit (v_readlane), so the step needs no LDS round trip
-// and no barrier.  The step is branch-free: entries above the diagonal of a
-// lane's row of L pick up values that are never read or stored, and a row's
-// factor is zero where it must not change.  1/sqrt of the pivot comes from the
-// hardware estimate refined by two Newton steps.  L goes back to P; Linv
-// (row-major, pitch 17, zero above the diagonal) receives X, which turns the
-// solves against L below the block into products on MFMA.  A non-positive
-// pivot is replaced by 1 and reported by returning false.
-__device__ __attribute__((always_inline)) inline bool wave_chol16_inv(double* P, int ldp, int cb, double* y,
-                                                                      double* Linv) {
+// and the inverse X = L^-1 built alongside.  Lane (r, g) = (lane & 15,
+// lane >> 4) holds row r of L and of X at the columns m = g, g + 4, g + 8,
+// g + 12.  At step c, column c of L and row c of X are final; they go through
+// LDS (cxb: two buffers of 16 + 16 doubles, alternating, so one wave barrier
+// per column suffices) and every lower row subtracts its multiple of them
+// from its four entries.  The pivot comes to all lanes through the scalar
+// unit; 1/sqrt of it is the hardware estimate refined by two Newton steps.
+// Entries above the diagonal of a lane's row of L pick up values that are
+// never read or stored.  L goes back to P; Linv (row-major, pitch 17, zero
+// above the diagonal) receives X, which turns the solves against L below the
+// block into products on MFMA.  A non-positive pivot is replaced by 1 and
+// reported by returning false.
+__device__ __attribute__((always_inline)) inline bool wave_chol16_inv4(double* P, int ldp, int cb, double* y,
+                                                                       double* Linv, double* cxb) {
   const int lane = threadIdx.x & 63;
   int rr = lane & 15;
   asm volatile("" : "+v"(rr));  // per-lane predicates stay here, not hoisted into the caller
-  double a[16], x[16];
+  const int g = lane >> 4;
+  double a[4], x[4];
 #pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    a[m] = (m <= rr) ? P[(cb + m) * ldp + cb + rr] : 0.0;
-    x[m] = (m == rr) ? 1.0 : 0.0;
+  for (int t = 0; t < 4; ++t) {
+    const int m = g + 4 * t;
+    a[t] = (m <= rr) ? P[(cb + m) * ldp + cb + rr] : 0.0;
+    x[t] = (m == rr) ? 1.0 : 0.0;
   }
   double yr = y[cb + rr];
   bool ok = true;
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
-    double piv = bcast_lane(a[c], c);
+    const int tc = c >> 2, gc = c & 3;  // column c sits in slot tc of lanes with g == gc
+    double piv = bcast_lane(a[tc], c + 16 * gc);
     if (!(piv > 0.0)) {
       ok = false;
       piv = 1.0;
     }
-    double inv = __builtin_amdgcn_rsq(piv);
-    inv = inv * (1.5 - 0.5 * piv * inv * inv);
-    inv = inv * (1.5 - 0.5 * piv * inv * inv);
+    const double inv = rsq_nr(piv);
     const bool own = (rr == c), below = (rr > c);
-    const double scale = own ? inv : 1.0;
-    a[c] = own ? piv * inv : (below ? a[c] * inv : a[c]);
-    yr *= scale;
+    if (g == gc) a[tc] = own ? piv * inv : (below ? a[tc] * inv : a[tc]);
+    if (own) {
+      yr *= inv;
 #pragma unroll
-    for (int m = 0; m <= c; ++m) x[m] *= scale;
-    const double yc = bcast_lane(yr, c);
-    const double f = below ? a[c] : 0.0;  // L[r][c] for the rows that update
-    yr -= f * yc;
-    // A[r][m] -= L[r][c] L[m][c] (L[m][c] is lane m's a[c]); X[r][m] -= L[r][c] X[c][m]
-#pragma unroll
-    for (int m = c + 1; m < 16; ++m) a[m] -= a[c] * bcast_lane(a[c], m);
-#pragma unroll
-    for (int m = 0; m <= c; ++m) x[m] -= f * bcast_lane(x[m], c);
-  }
-  if (lane < 16) {
-#pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      if (m <= rr) P[(cb + m) * ldp + cb + rr] = a[m];
-      Linv[rr * 17 + m] = x[m];
+      for (int t = 0; t < 4; ++t) x[t] *= inv;
     }
-    y[cb + rr] = yr;
+    const double yc = bcast_lane(yr, c);
+    double* cb_ = cxb + 32 * (c & 1);  // [0, 16): column c of L; [16, 32): row c of X
+    if (g == gc) cb_[rr] = a[tc];
+    if (own) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) cb_[16 + g + 4 * t] = x[t];
+    }
+    wave_lds_sync();
+    const double f = below ? cb_[rr] : 0.0;  // L[r][c] for the rows that update
+    yr -= f * yc;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int m = g + 4 * t;
+      if (m > c) a[t] -= f * cb_[m];
+      else x[t] -= f * cb_[16 + m];
+    }
   }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int m = g + 4 * t;
+    if (m <= rr) P[(cb + m) * ldp + cb + rr] = a[t];
+    Linv[rr * 17 + m] = x[t];
+  }
+  if (g == 0) y[cb + rr] = yr;
   return ok;
 }
 
@@ -238,13 +255,6 @@ __device__ inline double block_max(double v, double* red) {
   if (threadIdx.x == 0)
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t = nanmax(t, red[i]);
   return t;
-}
-
-// 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton steps.
-__device__ inline double rsq_nr(double x) {
-  double r = __builtin_amdgcn_rsq(x);
-  r = r * (1.5 - 0.5 * x * r * r);
-  return r * (1.5 - 0.5 * x * r * r);
 }
 
 // 2x2 Cholesky of [[a00, .], [a10, a11]] with the reciprocals i00 = 1/l00,
@@ -660,6 +670,7 @@ __global__ void __launch_bounds__(DENSE_NT) k_dense_chol(Dev d, int s0) {
   double* Lp = bl + n;            // [n - 16][PANEL_PITCH]: rows below the diagonal block
   __shared__ double Dk[16 * 17];    // diagonal block, column-major, pitch 17
   __shared__ double Linv[16 * 17];  // its inverse factor, row-major
+  __shared__ double cxb[64];
   __shared__ double part[16 * 16];
   __shared__ int bad;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -681,7 +692,7 @@ __global__ void __launch_bounds__(DENSE_NT) k_dense_chol(Dev d, int s0) {
     }
     __syncthreads();
     if (wv == 0) {
-      const bool ok = wave_chol16_inv(Dk, 17, 0, bl + c0, Linv);
+      const bool ok = wave_chol16_inv4(Dk, 17, 0, bl + c0, Linv, cxb);
       if (!ok && lane == 0) bad = 1;
     }
     __syncthreads();
@@ -819,6 +830,7 @@ __global__ void __launch_bounds__(DW_NT) k_dense_wide(Dev d, int s0, int nb) {
   double* yv = dw;      // [n] rhs, then the solution
   double* P = dw + n;   // [nb columns][M rows] of the current panel, M = n - c0, pitch M + 1
   __shared__ double Linv[16 * 17];
+  __shared__ double cxb[64];
   __shared__ double part[16 * 16];
   __shared__ int bad;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -853,7 +865,7 @@ __global__ void __launch_bounds__(DW_NT) k_dense_wide(Dev d, int s0, int nb) {
     // (2) factor the panel in 16-column steps
     for (int cb = 0; cb < w; cb += 16) {
       if (wv == 0) {
-        const bool ok = wave_chol16_inv(P, ldp, cb, yv + c0, Linv);
+        const bool ok = wave_chol16_inv4(P, ldp, cb, yv + c0, Linv, cxb);
         if (!ok && lane == 0) bad = 1;
       }
       __syncthreads();
@@ -1037,6 +1049,7 @@ __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
   double* tl = d.sn_tl + (int64_t)s * d.tl_stride;
   extern __shared__ double sl[];
   __shared__ double Linv[16 * 17];
+  __shared__ double cxb[64];
   __shared__ int bad;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   constexpr int NW = SN_NT / 64, UL = 8, TB = 4;
@@ -1084,7 +1097,7 @@ __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
     // (2) blocked Cholesky of the panel and forward solve
     for (int cb = 0; cb < Wp; cb += 16) {
       if (wv == 0) {
-        const bool ok = wave_chol16_inv(P, ldp, cb, yv, Linv);
+        const bool ok = wave_chol16_inv4(P, ldp, cb, yv, Linv, cxb);
         if (!ok && lane == 0) bad = 1;
       }
       __syncthreads();
