@@ -9,7 +9,13 @@
 //                  boundary solve
 //   k_gamma_gather boundary assembly S_Gamma = sum E_k^T S_b^k E_k (Eq. 11,
 //                  Section 4.4), as a gather (no atomics)
-//   k_dense_chol   Cholesky + solve of the boundary system's dense block;
+//   k_gamma_snode  supernodal elimination of the boundary system's leading
+//                  buses, independent elimination subtrees in parallel
+//                  workgroups (FP64 MFMA panels); k_gamma_tail applies their
+//                  updates of the dense block; k_gamma_snode_back is the
+//                  matching back substitution
+//   k_dense_wide   Cholesky + solve of the boundary system's dense block with
+//                  64-column LDS panels (k_dense_chol: 16-column panels);
 //                  trailing updates on FP64 MFMA
 //   k_backsolve    scatter-back dx_b^k = E_k dx_Gamma and interior recovery
 //                  dx_i^k = G_ii^-1 (b_i - G_ib dx_b) (Eq. 8)
@@ -643,9 +649,9 @@ __global__ void __launch_bounds__(256) k_gamma_gather(Dev d, int s0, int nslot) 
 // ---------------------------------------------------------------------------
 // Stage 3b: dense Cholesky and solve of the boundary system's trailing block
 // (the whole S_Gamma in dense mode).  One workgroup per snapshot, blocked
-// right-looking with 16-wide panels: the 16x16 diagonal block is factored in
-// registers by one wave (one row per lane, shuffles), the panel below by
-// row-parallel triangular solves, and the symmetric trailing update
+// right-looking with 16-wide panels: the 16x16 diagonal block is factored by
+// one wave (wave_chol16_inv4, which also forms its inverse), the panel below
+// is multiplied by that inverse on MFMA, and the symmetric trailing update
 // A_ij -= L_ik L_jk^T runs on v_mfma_f64_16x16x4f64, one 16x16 tile per wave.
 // The forward solve rides along; the back solve runs block by block from the
 // bottom.  The block is column-major with leading dimension n (a multiple of
