@@ -18,6 +18,12 @@ def say(*a):
 def grid(name):
     if name in synth.CONFIGS:
         return synth.make_config(name)
+    if name.startswith("c2k"):
+        # the 9241-bus grid re-partitioned into K areas (same buses and branches)
+        import dataclasses
+        k = int(name[3:])
+        g = synth.make_config("c2")
+        return dataclasses.replace(g, n_area=k, bus_area=synth.partition(g.pos, g.br_from, g.br_to, k, "plain"))
     if name == "k2":
         return synth.make_grid(30, 41, 2, seed=1)
     if name == "k5":

@@ -47,3 +47,22 @@ def test_plain_schedule_matches_batched_c2():
         m.close()
     np.testing.assert_array_equal(res[0][0], res[1][0])
     np.testing.assert_array_equal(res[0][1], res[1][1])
+
+
+@pytest.mark.parametrize("name", ["c2k2", "c2k64"])
+def test_partition_extremes_sampled_parity(name):
+    # K = 2: areas of up to 6,950 buses (assembly staged in HBM, right-hand
+    # sides of the level kernels in HBM); K = 64: a 1,476-variable boundary
+    # system with many independent elimination subtrees
+    say("partition extreme", name)
+    c = Case(name, 16, seed=4)
+    m = c.ctx()
+    iters, conv = m.mase_solve(1e-6, 10)
+    assert conv.all(), iters
+    vm, va = m.mase_state()
+    for i in (0, 15):
+        say("  oracle snapshot", i)
+        ref = c.oracle_solve(i)
+        assert ref["converged"] and iters[i] == ref["iters"]
+        assert_state_close(vm[i], va[i], ref["vm"], ref["va"], 1e-8)
+    m.close()
