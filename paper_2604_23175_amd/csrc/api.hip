@@ -309,19 +309,26 @@ int upload_plan(mase_ctx* c) {
   if ((rc = dalloc(c, S * p.vstride, &d.vals))) return rc;
   if ((rc = dalloc(c, S * p.rstride, &d.rhs))) return rc;
   if ((rc = dalloc(c, S * K, &d.jpart))) return rc;
-  if ((rc = dalloc(c, S, &d.active))) return rc;
-  if ((rc = dalloc(c, S, &d.iters))) return rc;
-  if ((rc = dalloc(c, S * (K + 1), &d.status))) return rc;
-  if ((rc = dalloc(c, S, &d.maxdx))) return rc;
+  // per-snapshot flags in one block, {maxdx [S] | active [S] | status [S][K+1] | iters [S]},
+  // so that one copy brings an iteration's outcome to the host
+  const size_t flag_bytes = sizeof(double) * S + sizeof(int32_t) * (S * (K + 2) + S);
+  {
+    double* blk = nullptr;
+    if ((rc = dalloc(c, (flag_bytes + 7) / 8, &blk))) return rc;
+    d.maxdx = blk;
+    d.active = reinterpret_cast<int32_t*>(blk + S);
+    d.status = d.active + S;
+    d.iters = d.status + S * (K + 1);
+  }
   if ((rc = dalloc(c, 1, &c->dtol))) return rc;
   d.tol = c->dtol;
   d.hout = nullptr;
   HIPTRY(hipMemset(d.vals, 0, sizeof(double) * S * p.vstride));
   HIPTRY(hipMemset(d.rhs, 0, sizeof(double) * S * p.rstride));
-  HIPTRY(hipHostMalloc((void**)&c->h_active, sizeof(int32_t) * S, hipHostMallocDefault));
-  HIPTRY(hipHostMalloc((void**)&c->h_iters, sizeof(int32_t) * S, hipHostMallocDefault));
-  HIPTRY(hipHostMalloc((void**)&c->h_status, sizeof(int32_t) * S * (K + 1), hipHostMallocDefault));
-  HIPTRY(hipHostMalloc((void**)&c->h_maxdx, sizeof(double) * S, hipHostMallocDefault));
+  HIPTRY(hipHostMalloc((void**)&c->h_maxdx, (flag_bytes + 7) / 8 * 8, hipHostMallocDefault));
+  c->h_active = reinterpret_cast<int32_t*>(c->h_maxdx + S);
+  c->h_status = c->h_active + S;
+  c->h_iters = c->h_status + S * (K + 1);
   HIPTRY(hipHostMalloc((void**)&c->h_tol, sizeof(double), hipHostMallocDefault));
   c->h_tol[0] = 1e-6;
   HIPTRY(hipMemcpy(c->dtol, c->h_tol, sizeof(double), hipMemcpyHostToDevice));
@@ -584,10 +591,9 @@ int launch_plain_iteration(mase_ctx* c, int s) {
 
 int read_flags(mase_ctx* c) {
   const int S = c->plan.n_snap, K = c->plan.n_area;
-  HIPTRY(hipMemcpyAsync(c->h_active, c->d.active, sizeof(int32_t) * S, hipMemcpyDeviceToHost, c->stream));
-  HIPTRY(hipMemcpyAsync(c->h_maxdx, c->d.maxdx, sizeof(double) * S, hipMemcpyDeviceToHost, c->stream));
-  HIPTRY(hipMemcpyAsync(c->h_status, c->d.status, sizeof(int32_t) * S * (K + 1), hipMemcpyDeviceToHost,
-                        c->stream));
+  // maxdx, active and status are contiguous on both sides
+  HIPTRY(hipMemcpyAsync(c->h_maxdx, c->d.maxdx, sizeof(double) * S + sizeof(int32_t) * S * (K + 2),
+                        hipMemcpyDeviceToHost, c->stream));
   HIPTRY(hipStreamSynchronize(c->stream));
   return 0;
 }
@@ -788,10 +794,7 @@ void mase_destroy(mase_ctx* c) {
     if (c->ev_main) (void)hipEventDestroy(c->ev_main);
     for (auto e : c->pev) if (e) (void)hipEventDestroy(e);
     for (void* p : c->dallocs) (void)hipFree(p);
-    if (c->h_active) (void)hipHostFree(c->h_active);
-    if (c->h_iters) (void)hipHostFree(c->h_iters);
-    if (c->h_status) (void)hipHostFree(c->h_status);
-    if (c->h_maxdx) (void)hipHostFree(c->h_maxdx);
+    if (c->h_maxdx) (void)hipHostFree(c->h_maxdx);  // also holds h_active, h_status, h_iters
     if (c->h_tol) (void)hipHostFree(c->h_tol);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   }
@@ -996,11 +999,8 @@ int reset_graphs(mase_ctx* c) {
 // The batched iteration loop of mase_solve (pipelined when npipe > 1).
 int solve_batched(mase_ctx* c, int max_iter) {
   const int S = c->plan.n_snap;
-  int rc = 0;
-  HIPTRY(hipMemcpyAsync(c->h_active, c->d.active, sizeof(int32_t) * S, hipMemcpyDeviceToHost, c->stream));
-  HIPTRY(hipMemcpyAsync(c->h_status, c->d.status, sizeof(int32_t) * S * (c->plan.n_area + 1),
-                        hipMemcpyDeviceToHost, c->stream));
-  HIPTRY(hipStreamSynchronize(c->stream));
+  int rc = read_flags(c);
+  if (rc) return rc;
   if (c->opt.use_graph && !c->prof && c->npipe > 1) return pipelined_solve(c, max_iter);
   int nact = 0;
   for (int s = 0; s < S; ++s) nact += c->h_active[s] != 0;
