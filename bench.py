@@ -479,6 +479,7 @@ def main():
                    "schedule": {"pipeline_groups": info["pipeline_groups"],
                                 "boundary_elimination": "supernodal" if info["gamma_supernodal"] else "levels",
                                 "boundary_subtree_groups": info["gamma_subtree_groups"],
+                                "boundary_dense_panel_columns": info["gamma_dense_panel"],
                                 "chosen_by": "autotuner"}},
         "gn_iters_per_s": tot_iters / dt, "all_converged": all_conv,
         "warm_start": None if not warm else {"accepted_fraction": acc_frac, "training": train_info},

@@ -354,9 +354,11 @@ enum {
   MASE_INFO_GAMMA_SUPERNODAL, /* 1 if the boundary elimination runs supernodal (else the
                                  level schedule) */
   MASE_INFO_PIPELINE_GROUPS,  /* snapshot groups of mase_solve's pipelined schedule */
-  MASE_INFO_GAMMA_SUBTREE_GROUPS /* workgroups per snapshot of the supernodal boundary
-                                    elimination: groups of independent elimination subtrees
-                                    (the environment variable MASE_SNODE_GROUPS caps it) */
+  MASE_INFO_GAMMA_SUBTREE_GROUPS, /* workgroups per snapshot of the supernodal boundary
+                                     elimination: groups of independent elimination subtrees
+                                     (the environment variable MASE_SNODE_GROUPS caps it) */
+  MASE_INFO_GAMMA_DENSE_PANEL     /* columns per LDS panel of the boundary system's dense block
+                                     (0: panels read from HBM); the autotuner may change it */
 };
 int mase_info(const mase_ctx* ctx, int32_t what, int64_t* value);
 

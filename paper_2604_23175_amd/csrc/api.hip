@@ -234,6 +234,9 @@ int upload_plan(mase_ctx* c) {
     if (c->dense_mode == DENSE_WIDE) c->dense_nb = std::max(16, c->dense_nb);
     const size_t bytes = dense_lds_bytes(ld, c->dense_mode, c->dense_nb);
     if (c->dense_mode != DENSE_GLOBAL && bytes > 65536) HIPTRY(allow_dense_lds(c->dense_mode, bytes));
+    // the autotuner may also pick 16-column panels in LDS
+    const size_t b16 = dense_lds_bytes(ld, DENSE_PANEL16, 16);
+    if (c->dense_mode == DENSE_WIDE && b16 > 65536) HIPTRY(allow_dense_lds(DENSE_PANEL16, b16));
   }
   // supernodal boundary elimination (MASE_GAMMA_SNODE=0 selects the level engine)
   {
@@ -945,28 +948,33 @@ std::string make_tune_key(const mase_ctx* c) {
   return std::string(buf) + "/" + (arch.empty() ? "unknown" : arch);
 }
 
-bool read_tune_cache(const mase_ctx* c, int& npipe, int& snode) {
+// One cache line per tuned configuration: "key npipe snode dense_mode dense_nb".
+bool read_tune_cache(const mase_ctx* c, int& npipe, int& snode, int& dmode, int& dnb) {
   if (c->tune_path.empty()) return false;
   FILE* f = std::fopen(c->tune_path.c_str(), "r");
   if (!f) return false;
-  char key[256];
-  int a = 0, b = 0;
+  char line[512], key[256];
   bool found = false;
-  while (std::fscanf(f, "%255s %d %d", key, &a, &b) == 3)
-    if (c->tune_key == key && a >= 1 && (b == 0 || b == 1)) {
+  while (std::fgets(line, sizeof(line), f)) {
+    int a = 0, b = 0, m = 0, w = 0;
+    if (std::sscanf(line, "%255s %d %d %d %d", key, &a, &b, &m, &w) != 5) continue;
+    if (c->tune_key == key && a >= 1 && (b == 0 || b == 1) && m >= DENSE_GLOBAL && m <= DENSE_WIDE && w >= 0) {
       npipe = a;
       snode = b;
+      dmode = m;
+      dnb = w;
       found = true;  // the last matching line wins
     }
+  }
   std::fclose(f);
   return found;
 }
 
-void write_tune_cache(const mase_ctx* c, int npipe, int snode) {
+void write_tune_cache(const mase_ctx* c, int npipe, int snode, int dmode, int dnb) {
   if (c->tune_path.empty()) return;
   FILE* f = std::fopen(c->tune_path.c_str(), "a");
   if (!f) return;
-  std::fprintf(f, "%s %d %d\n", c->tune_key.c_str(), npipe, snode);
+  std::fprintf(f, "%s %d %d %d %d\n", c->tune_key.c_str(), npipe, snode, dmode, dnb);
   std::fclose(f);
 }
 
@@ -1017,12 +1025,24 @@ int solve_batched(mase_ctx* c, int max_iter) {
 int autotune(mase_ctx* c) {
   c->tuned = true;
   if (c->tune_key.empty()) c->tune_key = make_tune_key(c);
-  int np = 0, sn = 0;
-  if (read_tune_cache(c, np, sn)) {
+  // dense-block variants: the widest LDS panel that fits, a 32-column one,
+  // and 16-column panels (each only where the create-time choice allows it)
+  std::vector<std::pair<int, int>> dense_cands{{c->dense_mode, c->dense_nb}};
+  if (c->dense_mode == DENSE_WIDE) {
+    if (c->dense_nb > 32) dense_cands.push_back({DENSE_WIDE, 32});
+    dense_cands.push_back({DENSE_PANEL16, 16});
+  }
+  int np = 0, sn = 0, dm = 0, dnb = 0;
+  if (read_tune_cache(c, np, sn, dm, dnb)) {
     int rc = reset_graphs(c);
     if (rc) return rc;
     c->npipe = std::max(1, std::min(np, c->plan.n_snap));
     c->gamma_snode = sn && c->snode_possible;
+    for (const auto& dc : dense_cands)
+      if (dc.first == dm && dc.second == dnb) {
+        c->dense_mode = dm;
+        c->dense_nb = dnb;
+      }
     return 0;
   }
   const int S = c->plan.n_snap, K = c->plan.n_area;
@@ -1057,33 +1077,41 @@ int autotune(mase_ctx* c) {
   const bool snode0 = c->gamma_snode;
   double best = 1e300;
   int best_np = c->npipe, best_sn = snode0 ? 1 : 0;
+  std::pair<int, int> best_dense = dense_cands[0];
   for (int snc = 1; snc >= 0; --snc) {
     if (snc == 1 && !c->snode_possible) continue;
     for (int npc : {1, 2, 4, 8}) {
       if (npc > S) continue;
-      if ((rc = reset_graphs(c))) return rc;
-      c->npipe = npc;
-      c->gamma_snode = snc == 1;
-      double t = 0.0;
-      for (int rep = 0; rep < 2; ++rep) {  // the first run captures the graphs
-        if ((rc = save_restore(false))) return rc;
-        const auto t0 = std::chrono::steady_clock::now();
-        if ((rc = solve_batched(c, 2))) return rc;
-        HIPTRY(hipStreamSynchronize(c->stream));
-        t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-      }
-      if (t < best) {
-        best = t;
-        best_np = npc;
-        best_sn = snc;
+      for (const auto& dc : dense_cands) {
+        if ((rc = reset_graphs(c))) return rc;
+        c->npipe = npc;
+        c->gamma_snode = snc == 1;
+        c->dense_mode = dc.first;
+        c->dense_nb = dc.second;
+        double t = 0.0;
+        for (int rep = 0; rep < 2; ++rep) {  // the first run captures the graphs
+          if ((rc = save_restore(false))) return rc;
+          const auto t0 = std::chrono::steady_clock::now();
+          if ((rc = solve_batched(c, 2))) return rc;
+          HIPTRY(hipStreamSynchronize(c->stream));
+          t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+        if (t < best) {
+          best = t;
+          best_np = npc;
+          best_sn = snc;
+          best_dense = dc;
+        }
       }
     }
   }
   if ((rc = reset_graphs(c))) return rc;
   c->npipe = best_np;
   c->gamma_snode = best_sn == 1;
+  c->dense_mode = best_dense.first;
+  c->dense_nb = best_dense.second;
   if ((rc = save_restore(false))) return rc;
-  write_tune_cache(c, best_np, best_sn);
+  write_tune_cache(c, best_np, best_sn, best_dense.first, best_dense.second);
   return 0;
 }
 
@@ -1234,6 +1262,8 @@ int mase_info(const mase_ctx* c, int32_t what, int64_t* value) {
     case MASE_INFO_GAMMA_SUPERNODAL: v = c->gamma_snode ? 1 : 0; break;
     case MASE_INFO_PIPELINE_GROUPS: v = c->npipe; break;
     case MASE_INFO_GAMMA_SUBTREE_GROUPS: v = c->d.n_sn_grp; break;
+    case MASE_INFO_GAMMA_DENSE_PANEL: v = c->dense_mode == DENSE_WIDE ? c->dense_nb
+                                        : c->dense_mode == DENSE_PANEL16 ? 16 : 0; break;
     default: return fail(MASE_ERR_ARG, "unknown info key");
   }
   *value = v;

@@ -106,15 +106,17 @@ def test_autotune_choice_cached_and_results_match(tmp_path):
     assert conv.all()
     x = m.mase_state()
     assert_state_close(x[0], x[1], xr[0], xr[1], 1e-10)
-    choice = (m.mase_info("pipeline_groups"), m.mase_info("gamma_supernodal"))
+    keys = ("pipeline_groups", "gamma_supernodal", "gamma_dense_panel")
+    choice = tuple(m.mase_info(k) for k in keys)
     m.close()
     lines = [ln.split() for ln in cache.read_text().splitlines() if ln.strip()]
-    assert len(lines) == 1 and len(lines[0]) == 3
-    assert (int(lines[0][1]), int(lines[0][2])) == choice
+    assert len(lines) == 1 and len(lines[0]) == 5
+    panel = {0: 0, 1: 16}.get(int(lines[0][3]), int(lines[0][4]))
+    assert (int(lines[0][1]), int(lines[0][2]), panel) == choice
     # a second context takes the cached choice without tuning again
     m2 = c.ctx(autotune=True, tune_cache=str(cache))
     m2.mase_solve(1e-10, 12)
-    assert (m2.mase_info("pipeline_groups"), m2.mase_info("gamma_supernodal")) == choice
+    assert tuple(m2.mase_info(k) for k in keys) == choice
     x2 = m2.mase_state()
     np.testing.assert_array_equal(x2[0], x[0])
     np.testing.assert_array_equal(x2[1], x[1])
