@@ -659,7 +659,7 @@ void unpack_blocks(const Plan& p, int k, const std::vector<double>& vals, const 
     for (int i : s.strct[j]) put(i, j, s.blk_off(i, j), 2);
   }
   for (int q = s.ne; q < s.nn; ++q)
-    for (int i = q; i < s.nn; ++i) put(i, q, s.blk_off(i, q), s.ld);
+    for (int i = q; i < s.nn; ++i) put(i, q, s.blk_off(i, q), s.blk_stride(i, q));
 }
 
 }  // namespace

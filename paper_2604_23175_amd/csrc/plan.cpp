@@ -87,7 +87,7 @@ void finish_system(SysPlan& s) {
   cur = round_up(cur, 16);
   s.tail_off = (int32_t)cur;
   s.ld = round_up(2 * (int64_t)s.nt, 16);
-  cur += (int64_t)s.ld * s.ld;
+  cur += s.packed_tail ? 2 * (int64_t)s.nt * (s.nt + 1) : (int64_t)s.ld * s.ld;
   if (cur > (int64_t)1 << 30) throw std::runtime_error("system too large for 32-bit offsets");
   s.nval = (int32_t)cur;
 
@@ -256,10 +256,12 @@ int32_t SysPlan::blk_off(int i, int j) const {
     if (it == s.end() || *it != i) throw std::logic_error("block not in pattern");
     return col_off[j] + 4 * (1 + (int32_t)(it - s.begin()));
   }
-  return tail_off + 2 * (j - ne) * ld + 2 * (i - ne);
+  const int a = i - ne, b = j - ne;
+  if (packed_tail) return tail_off + 4 * (b * nt - b * (b - 1) / 2 + (a - b));
+  return tail_off + 2 * b * ld + 2 * a;
 }
 
-int32_t SysPlan::blk_stride(int /*i*/, int j) const { return j < ne ? 2 : ld; }
+int32_t SysPlan::blk_stride(int /*i*/, int j) const { return (j < ne || packed_tail) ? 2 : ld; }
 
 void SysPlan::build_supernodes() {
   sn.clear();
@@ -574,6 +576,7 @@ std::string build_plan(const Input& in, Plan& p) {
     for (int v = 0; v < nn; ++v) lob[gold[v]] = newof[v];
     for (auto& sv : sup)
       for (auto& a : sv) a.bus = newof[a.bus];
+    s.packed_tail = true;
     try { finish_system(s); } catch (std::exception& ex) { return ex.what(); }
     if (p.slack >= 0 && area[p.slack] == k && !p.is_bnd[p.slack]) s.pin_off = s.col_off[lob[p.slack]];
 
@@ -726,8 +729,9 @@ std::string build_plan(const Input& in, Plan& p) {
         for (int b = s.ne; b <= a; ++b) {
           const int gb = gpos[s.gbus[b]];
           const int32_t src = p.val_off[k] + s.blk_off(a, b);
-          if (ga >= gb) by_blk[g.blk_off(ga, gb)].push_back({src, s.ld, 0, 0});
-          else by_blk[g.blk_off(gb, ga)].push_back({src, s.ld, 1, 0});
+          const int32_t sst = s.blk_stride(a, b);
+          if (ga >= gb) by_blk[g.blk_off(ga, gb)].push_back({src, sst, 0, 0});
+          else by_blk[g.blk_off(gb, ga)].push_back({src, sst, 1, 0});
         }
       }
     }

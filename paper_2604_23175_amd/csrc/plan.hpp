@@ -45,7 +45,8 @@ inline int sn_lds_bytes_of(int w, int r) {
 //   for each eliminated bus j: diagonal block (4 doubles, column-major 2x2)
 //   followed by one 2x2 block per row bus i in strct[j] (column-major);
 //   then the tail: a dense column-major matrix with leading dimension ld
-//   (ld = 2*nt rounded up to 16), of which the lower triangle is used.
+//   (ld = 2*nt rounded up to 16), of which the lower triangle is used, or
+//   with packed_tail its lower triangle of 2x2 blocks, each contiguous.
 // Right-hand side storage: 2 doubles per local bus.
 struct SysPlan {
   int nn = 0, ne = 0, nt = 0;
@@ -54,6 +55,10 @@ struct SysPlan {
   std::vector<int32_t> col_off;          // eliminated bus j -> offset of its diagonal block
   int32_t tail_off = 0;
   int32_t ld = 0;                        // tail leading dimension (multiple of 16)
+  // Packed tail (the areas' Schur blocks): the lower triangle of 2x2 blocks,
+  // each block contiguous (column-major 2x2), block columns one after another;
+  // else (the boundary system) the dense column-major ld x ld layout above.
+  bool packed_tail = false;
   int32_t nval = 0;                      // doubles of packed storage
   int32_t pin_off = -1;                  // entry forced to 1 (slack theta pivot), or -1
   std::vector<int> level;                // eliminated bus -> level (leaves 0)
