@@ -9,8 +9,12 @@ branch ends).  A step solves the whole batch from its starting point to
 max |dx| < 1e-6 (at most 10 Gauss-Newton iterations) and writes the states to
 device memory.  Measurements are resident in HBM before the timed region.
 
-Printed as one JSON line: the batched path (all areas x snapshots per launch,
-hipGraph-captured iteration) as `value`, the plain per-area / per-snapshot
+`value` is the continuous-batching path: the K steps' K x 64 snapshots pass
+through 64 slots (all areas x slots per launch, hipGraph-captured iteration),
+and a slot whose snapshot has converged takes the next one at once, so no
+iteration runs for a batch's last few snapshots alone.  The same steps as
+separate batches (`batched_warm`, `batched_flat`) are reported beside it.
+Printed as one JSON line: that path as `value`, the plain per-area / per-snapshot
 schedule on the same batch as `plain`, per-kernel times from HIP events
 recorded around each stage kernel inside the timed region, the roofline of the
 dominant kernel, and the CPU oracle timed on a bounded sample.
@@ -260,7 +264,7 @@ def local_sweep(ls, steps, warmup):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -378,17 +382,54 @@ def main():
         return time.perf_counter() - t0, n_it, ok
 
     warm = mlp is not None
+    # continuous batching: the K steps' batches as one stream of K x 64
+    # snapshots through the context's 64 slots; with the warm start, each
+    # batch's starting states come from the network (with rejection) first
+    n_stream = N_SNAP * args.steps
+    z_stream = z.repeat(args.steps, 1).contiguous()
+    vm_s = torch.empty((n_stream, g.n_bus), dtype=torch.float64, device=dev)
+    va_s = torch.empty_like(vm_s)
+    vm0_s = torch.empty_like(vm_s) if warm else None
+    va0_s = torch.empty_like(vm_s) if warm else None
+
+    def stream(c, warm):
+        if warm:
+            for k in range(args.steps):
+                acc = mase.mase_warm_start(c, mlp)
+                accepted_count[0] += int(acc.sum())
+                accepted_count[1] += acc.size
+                c.mase_state_dev(vm0_s[k * N_SNAP:(k + 1) * N_SNAP], va0_s[k * N_SNAP:(k + 1) * N_SNAP])
+            iters, conv = c.mase_solve_stream(z_stream, vm_s, va_s, vm0_s, va0_s, TOL, MAX_ITER)
+        else:
+            iters, conv = c.mase_solve_stream(z_stream, vm_s, va_s, None, None, TOL, MAX_ITER)
+        # the context's measurements are the batch again (for the batched legs)
+        c.mase_set_measurements_dev(z)
+        return iters, conv
+
+    def timed_stream(c, warm):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters, conv = stream(c, warm)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, int(iters.sum()), bool(conv.all())
+
     for _ in range(args.warmup):
         step(ctx, warm)
         step(ctx, False)
-    # headline: batched (+ warm start when trained), graph-replayed iterations
+    stream(ctx, warm)
+    # headline: continuous batching (+ warm start when trained), graph-replayed iterations
     accepted_count[:] = [0, 0]
-    dt, tot_iters, all_conv = timed(ctx, args.steps, warm)
-    value = N_SNAP * args.steps / dt
+    dt, tot_iters, all_conv = timed_stream(ctx, warm)
+    value = n_stream / dt
     acc_frac = accepted_count[0] / max(1, accepted_count[1])
-    # the batched flat-start path on the same batch
+    sdt, s_iters, s_conv = timed_stream(ctx, False)
+    vm_st, va_st = vm_s.cpu().numpy(), va_s.cpu().numpy()
+    # the same steps as separate batches (+ warm start), then flat start
+    bdt, b_iters, b_conv = timed(ctx, args.steps, warm)
     fdt, f_iters, f_conv = timed(ctx, args.steps, False)
     vm_b, va_b = vm_out.cpu().numpy(), va_out.cpu().numpy()
+    stream_same = bool(np.array_equal(vm_st, np.tile(vm_b, (args.steps, 1)))
+                       and np.array_equal(va_st, np.tile(va_b, (args.steps, 1))))
     # the same flat-start steps with host buffers at the boundary: measurements
     # uploaded and states downloaded through PCIe inside the timed region
     z_host = z.cpu().numpy()
@@ -404,10 +445,10 @@ def main():
     hdt = time.perf_counter() - t0
     ctx.mase_set_measurements_dev(z)
     torch.cuda.synchronize()
-    # the headline steps again with a HIP event pair around every stage kernel
+    # the headline stream again with a HIP event pair around every stage kernel
     # (direct launches: event pairs inside a graph cannot be timed)
     ctx.mase_profile(True)
-    pdt_prof, _, _ = timed(ctx, args.steps, warm)
+    pdt_prof, _, _ = timed_stream(ctx, warm)
     prof = ctx.mase_profile_read()
     ctx.mase_profile(False)
     info = {k: ctx.mase_info(k) for k in mase.INFO}
@@ -472,7 +513,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "9241-bus/16049-branch synthetic grid, 32 areas, 64 snapshots per batch, "
                                + ("learned warm start with rejection, " if warm else "flat start, ")
-                               + "batched + hipGraph, sparse boundary solve",
+                               + "continuous batching through 64 slots + hipGraph, sparse boundary solve",
                    "n_bus": g.n_bus, "n_branch": g.n_branch, "n_area": g.n_area, "snapshots": N_SNAP,
                    "n_meas": int(t.size), "n_gamma": info["n_gamma"], "tol": TOL, "max_iter": MAX_ITER,
                    "warm_start": warm,
@@ -483,6 +524,13 @@ def main():
                                 "chosen_by": "autotuner"}},
         "gn_iters_per_s": tot_iters / dt, "all_converged": all_conv,
         "warm_start": None if not warm else {"accepted_fraction": acc_frac, "training": train_info},
+        "stream_flat": {"value": n_stream / sdt, "unit": "snapshots/s", "ms_per_step": 1e3 * sdt / args.steps,
+                        "mean_iters": s_iters / n_stream, "all_converged": s_conv,
+                        "states_bitwise_equal_to_batched_flat": stream_same},
+        "batched_warm": None if not warm else {
+            "value": N_SNAP * args.steps / bdt, "unit": "snapshots/s", "ms_per_step": 1e3 * bdt / args.steps,
+            "mean_iters": b_iters / (N_SNAP * args.steps), "all_converged": b_conv,
+            "note": "each step a separate 64-snapshot batch: the batch iterates until its last snapshot converges"},
         "batched_flat": {"value": N_SNAP * args.steps / fdt, "unit": "snapshots/s",
                          "ms_per_step": 1e3 * fdt / args.steps, "mean_iters": f_iters / (N_SNAP * args.steps),
                          "gn_iters_per_s": f_iters / fdt, "all_converged": f_conv},

@@ -207,6 +207,41 @@ int mase_gn_iter(mase_ctx* ctx, double* max_abs_dx);
 int mase_solve(mase_ctx* ctx, double tol, int32_t max_iter, int32_t* iters,
                int32_t* converged);
 
+/*
+ * Continuous batching over a stream of n_total snapshots (each solved as in
+ * mase_solve: Gauss-Newton, Eq. 3 through Eq. 7-11, until a step has
+ * max |dx| < tol, at most max_iter steps).  The context's n_snap snapshots
+ * act as slots: after every batched iteration, a slot whose snapshot has
+ * converged, failed or used max_iter steps writes that snapshot's state to
+ * the outputs and takes the next snapshot of the stream, so no iteration is
+ * spent on a batch in which only a few snapshots are still running.  Each
+ * snapshot's arithmetic is that of mase_solve (results are bitwise equal to
+ * solving it in a batch from the same start).
+ *
+ *   z_dev        [n_total][n_meas] measurements (device); weights are those
+ *                of the last mase_set_measurements call, else 1/sigma^2
+ *   vm0_dev,
+ *   va0_dev      [n_total][n_bus] starting states (device), or both NULL for
+ *                flat start; the slack angle is forced to 0
+ *   vm_dev,
+ *   va_dev       [n_total][n_bus] solved states (device, written)
+ *   iters,
+ *   converged    [n_total] (host, may be NULL) per-snapshot step count and
+ *                flag
+ *
+ * The caller's buffers must stay valid until the call returns (it
+ * synchronises the context's stream).  Needs the batched schedule
+ * (MASE_ERR_ARG otherwise), 0 <= n_total <= 2^30.  Runs the autotuner first
+ * when the context asks for it and has not tuned yet.  Returns
+ * MASE_NOT_CONVERGED if any snapshot did not converge, MASE_ERR_NOT_POSDEF
+ * (outputs still written) if any hit a non-positive pivot.  Afterwards every
+ * slot is frozen; the slots' measurements and states are those of the last
+ * snapshots that passed through them.
+ */
+int mase_solve_stream(mase_ctx* ctx, const double* z_dev, const double* vm0_dev, const double* va0_dev,
+                      int64_t n_total, double tol, int32_t max_iter, double* vm_dev, double* va_dev,
+                      int32_t* iters, int32_t* converged);
+
 /* Current state vm, va [n_snap][n_bus] (host / device). */
 int mase_state(mase_ctx* ctx, double* vm, double* va);
 int mase_state_dev(mase_ctx* ctx, double* vm_dev, double* va_dev);

@@ -799,6 +799,7 @@ void mase_destroy(mase_ctx* c) {
     for (void* p : c->dallocs) (void)hipFree(p);
     if (c->h_maxdx) (void)hipHostFree(c->h_maxdx);  // also holds h_active, h_status, h_iters
     if (c->h_tol) (void)hipHostFree(c->h_tol);
+    if (c->st_out) (void)hipFree(c->st_out);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   }
   delete c;
@@ -1159,6 +1160,99 @@ int mase_solve(mase_ctx* c, double tol, int32_t max_iter, int32_t* iters, int32_
     if (converged) converged[s] = conv ? 1 : 0;
   }
   if (bad) return fail(MASE_ERR_NOT_POSDEF, "a snapshot hit a non-positive pivot");
+  return all ? MASE_OK : MASE_NOT_CONVERGED;
+}
+
+int mase_solve_stream(mase_ctx* c, const double* z_dev, const double* vm0_dev, const double* va0_dev,
+                      int64_t n_total, double tol, int32_t max_iter, double* vm_dev, double* va_dev,
+                      int32_t* iters, int32_t* converged) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  if (!c->opt.batched) return fail(MASE_ERR_ARG, "the stream solve needs the batched schedule");
+  if (!(tol > 0.0) || max_iter < 1) return fail(MASE_ERR_ARG, "need tol > 0 and max_iter >= 1");
+  if (n_total < 0 || n_total > (int64_t(1) << 30)) return fail(MASE_ERR_ARG, "n_total must be in [0, 2^30]");
+  if ((vm0_dev == nullptr) != (va0_dev == nullptr)) return fail(MASE_ERR_ARG, "give both vm0 and va0 or neither");
+  if (n_total == 0) return MASE_OK;
+  if (!z_dev || !vm_dev || !va_dev) return fail(MASE_ERR_ARG, "null z or output");
+  const int S = c->plan.n_snap;
+  if (!c->st_slots && (rc = dalloc(c, (size_t)3 * S + 1, &c->st_slots))) return rc;
+  if (c->st_out_cap < n_total) {
+    if (c->st_out) HIPTRY(hipFree(c->st_out));
+    c->st_out = nullptr;
+    c->st_out_cap = 0;
+    void* p = nullptr;
+    if (hipMalloc(&p, sizeof(int32_t) * 2 * (size_t)n_total) != hipSuccess)
+      return fail(MASE_ERR_OOM, "hipMalloc failed for the stream results");
+    c->st_out = static_cast<int32_t*>(p);
+    c->st_out_cap = n_total;
+  }
+  int32_t* slot_id = c->st_slots;
+  int32_t* retire = slot_id + S;
+  int32_t* refill = retire + S;
+  int32_t* next = refill + S;
+  int32_t* out_iters = c->st_out;
+  int32_t* out_flag = c->st_out + n_total;
+  const int32_t nt = (int32_t)n_total;
+  c->h_tol[0] = tol;
+  HIPTRY(hipMemcpyAsync(c->dtol, c->h_tol, sizeof(double), hipMemcpyHostToDevice, c->stream));
+  // every slot idle, then the first refill loads the first n_snap snapshots
+  HIPTRY(hipMemsetAsync(slot_id, 0xff, sizeof(int32_t) * S, c->stream));
+  HIPTRY(hipMemsetAsync(next, 0, sizeof(int32_t), c->stream));
+  // weights: those of the last mase_set_measurements call, else 1/sigma^2
+  if (!c->have_z)
+    HIPTRY(hipMemcpyAsync((void*)c->d.w, c->w_default, sizeof(double) * c->plan.n_meas, hipMemcpyDeviceToDevice,
+                          c->stream));
+  auto refill_slots = [&]() -> int {
+    HIPTRY(launch_stream_refill(c->d, slot_id, next, retire, refill, out_iters, out_flag, nt, max_iter,
+                                c->stream));
+    HIPTRY(launch_stream_copy(c->d, retire, refill, z_dev, vm0_dev, va0_dev, vm_dev, va_dev, c->stream));
+    return read_flags(c);
+  };
+  if ((rc = refill_slots())) return rc;
+  c->have_z = true;
+  if (c->opt.autotune && !c->tuned && c->opt.use_graph && !c->prof)
+    if ((rc = autotune(c)) || (rc = read_flags(c))) return rc;
+  // every busy slot advances one iteration per pass and leaves after at most
+  // max_iter, so the stream needs at most ceil(n_total / S) * max_iter passes
+  const int64_t limit = ((n_total + S - 1) / S) * (int64_t)max_iter + 1;
+  int64_t pass = 0;
+  for (;;) {
+    int nact = 0;
+    for (int s = 0; s < S; ++s) nact += c->h_active[s] != 0;
+    if (nact == 0) break;
+    if (++pass > limit) return fail(MASE_ERR_STATE, "stream solve did not drain");
+    if (c->opt.use_graph && !c->prof) {
+      if (!c->gexec) {
+        HIPTRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        rc = launch_batched_iteration(c, c->stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c->stream, &g);
+        if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+        if (e != hipSuccess) return fail(MASE_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+        c->graph = g;
+        HIPTRY(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+      }
+      HIPTRY(hipGraphLaunch(c->gexec, c->stream));
+    } else {
+      if ((rc = launch_batched_iteration(c, c->stream))) return rc;
+    }
+    if ((rc = refill_slots())) return rc;
+    if ((rc = accumulate_profile(c, nact))) return rc;
+  }
+  std::vector<int32_t> h((size_t)2 * n_total);
+  HIPTRY(hipMemcpyAsync(h.data(), out_iters, sizeof(int32_t) * n_total, hipMemcpyDeviceToHost, c->stream));
+  HIPTRY(hipMemcpyAsync(h.data() + n_total, out_flag, sizeof(int32_t) * n_total, hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPTRY(hipStreamSynchronize(c->stream));
+  bool all = true, bad = false;
+  for (int64_t i = 0; i < n_total; ++i) {
+    const int32_t f = h[(size_t)(n_total + i)];
+    bad |= f == 2;
+    all &= f == 1;
+    if (iters) iters[i] = h[(size_t)i];
+    if (converged) converged[i] = f == 1 ? 1 : 0;
+  }
+  if (bad) return fail(MASE_ERR_NOT_POSDEF, "a snapshot of the stream hit a non-positive pivot");
   return all ? MASE_OK : MASE_NOT_CONVERGED;
 }
 

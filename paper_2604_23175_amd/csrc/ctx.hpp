@@ -57,6 +57,12 @@ struct mase_ctx {
   double* h_maxdx = nullptr;
   double* h_tol = nullptr;
   std::vector<mase::SysMeta> hsys;
+  // continuous batching: per-slot snapshot ids, retire / refill tables and
+  // the stream position (3 n_snap + 1 ints); per-snapshot results of the
+  // stream (iterations, outcome), grown on demand
+  int32_t* st_slots = nullptr;
+  int32_t* st_out = nullptr;
+  int64_t st_out_cap = 0;
   // per-stage timing
   bool prof = false;
   hipEvent_t pev[2 * MASE_N_STAGE] = {};

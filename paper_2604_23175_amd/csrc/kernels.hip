@@ -20,6 +20,9 @@
 //   k_backsolve    scatter-back dx_b^k = E_k dx_Gamma and interior recovery
 //                  dx_i^k = G_ii^-1 (b_i - G_ib dx_b) (Eq. 8)
 //   k_update       x += dx, max |dx| per snapshot, convergence flags
+//   k_stream_refill, k_stream_copy
+//                  continuous batching: a slot whose snapshot has finished
+//                  hands its result over and takes the next snapshot
 //
 // Every reduction has a fixed order, so results are bitwise reproducible.
 // All arithmetic is FP64.
@@ -1529,6 +1532,104 @@ __global__ void k_reset_flags(Dev d) {
 }
 
 // ---------------------------------------------------------------------------
+// Continuous batching over a stream of snapshots
+// ---------------------------------------------------------------------------
+// One workgroup of 256 threads. A slot wants work when it is idle
+// (slot_id < 0) or its snapshot has finished: converged (frozen with no bad
+// pivot), failed (a non-positive pivot), or out of iterations. A finished
+// snapshot records its iteration count and outcome (1 converged, 0 not,
+// 2 non-positive pivot); the slots that want work take the next snapshots of
+// the stream in slot order (a prefix count, so the assignment is
+// deterministic) and start them with cleared flags, or go idle once the
+// stream is exhausted. retire[s] / refill[s] tell k_stream_copy which
+// snapshot leaves and which enters slot s (-1: none).
+__global__ void __launch_bounds__(256) k_stream_refill(Dev d, int32_t* slot_id, int32_t* next,
+                                                       int32_t* retire, int32_t* refill, int32_t* out_iters,
+                                                       int32_t* out_flag, int32_t n_total, int32_t max_iter) {
+  __shared__ int cnt[4];
+  __shared__ int base;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int K1 = d.n_area + 1;
+  if (tid == 0) base = *next;
+  __syncthreads();
+  for (int c0 = 0; c0 < d.n_snap; c0 += 256) {
+    const int s = c0 + tid;
+    int want = 0, leaving = -1;
+    if (s < d.n_snap) {
+      const int id = slot_id[s];
+      if (id < 0) {
+        want = 1;
+      } else {
+        int bad = 0;
+        for (int k = 0; k < K1; ++k) bad |= d.status[(int64_t)s * K1 + k];
+        const int act = d.active[s];
+        if (!act || bad || d.iters[s] >= max_iter) {
+          want = 1;
+          leaving = id;
+          out_iters[id] = d.iters[s];
+          out_flag[id] = bad ? 2 : (act ? 0 : 1);
+        }
+      }
+    }
+    const unsigned long long m = __ballot(want);
+    if (lane == 0) cnt[wv] = __popcll(m);
+    __syncthreads();
+    int rank = base + __popcll(m & ((1ull << lane) - 1ull));
+    for (int w = 0; w < wv; ++w) rank += cnt[w];
+    if (s < d.n_snap) {
+      retire[s] = leaving;
+      int entering = -1;
+      if (want) {
+        const bool take = rank < n_total;
+        entering = take ? rank : -1;
+        slot_id[s] = entering;
+        d.active[s] = take ? 1 : 0;
+        d.iters[s] = 0;
+        d.maxdx[s] = 0.0;
+        for (int k = 0; k < K1; ++k) d.status[(int64_t)s * K1 + k] = 0;
+      }
+      refill[s] = entering;
+    }
+    __syncthreads();
+    if (tid == 0) base += cnt[0] + cnt[1] + cnt[2] + cnt[3];
+    __syncthreads();
+  }
+  if (tid == 0) *next = base < n_total ? base : n_total;
+}
+
+// Grid (chunks, n_snap). Slot s hands the state of its finished snapshot to
+// vm_out / va_out [n_total][n_bus] and loads the entering snapshot's
+// measurements (zs [n_total][n_meas]) and starting state (vm0 / va0
+// [n_total][n_bus], flat start when vm0 is null; slack angle 0).
+__global__ void k_stream_copy(Dev d, const int32_t* retire, const int32_t* refill, const double* zs,
+                              const double* vm0, const double* va0, double* vm_out, double* va_out) {
+  const int s = blockIdx.y;
+  const int leaving = retire[s], entering = refill[s];
+  if (leaving < 0 && entering < 0) return;
+  const int stride = gridDim.x * blockDim.x;
+  const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
+  double2* xs = d.x + (int64_t)s * d.n_bus;
+  for (int i = i0; i < d.n_bus; i += stride) {
+    double2 v = xs[i];
+    if (leaving >= 0) {
+      vm_out[(int64_t)leaving * d.n_bus + i] = v.y;
+      va_out[(int64_t)leaving * d.n_bus + i] = v.x;
+    }
+    if (entering >= 0) {
+      const int64_t e = (int64_t)entering * d.n_bus + i;
+      v.x = (vm0 == nullptr || i == d.slack) ? 0.0 : va0[e];
+      v.y = vm0 == nullptr ? 1.0 : vm0[e];
+      xs[i] = v;
+    }
+  }
+  if (entering >= 0) {
+    const double* src = zs + (int64_t)entering * d.n_meas;
+    double* dst = const_cast<double*>(d.z) + (int64_t)s * d.n_meas;
+    for (int j = i0; j < d.n_meas; j += stride) dst[j] = src[j];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Launch wrappers
 // ---------------------------------------------------------------------------
 constexpr int AREA_NT = 256;   // level kernels over areas: many workgroups
@@ -1678,6 +1779,23 @@ hipError_t launch_unpack_state(const Dev& d, double* vm, double* va, hipStream_t
 hipError_t launch_reset_flags(const Dev& d, hipStream_t st) {
   const int n = d.n_snap * (d.n_area + 1);
   hipLaunchKernelGGL(k_reset_flags, dim3((n + 255) / 256), dim3(256), 0, st, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_refill(const Dev& d, int32_t* slot_id, int32_t* next, int32_t* retire,
+                                int32_t* refill, int32_t* out_iters, int32_t* out_flag, int32_t n_total,
+                                int32_t max_iter, hipStream_t st) {
+  hipLaunchKernelGGL(k_stream_refill, dim3(1), dim3(256), 0, st, d, slot_id, next, retire, refill, out_iters,
+                     out_flag, n_total, max_iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_copy(const Dev& d, const int32_t* retire, const int32_t* refill, const double* zs,
+                              const double* vm0, const double* va0, double* vm_out, double* va_out,
+                              hipStream_t st) {
+  // 8 chunks of 256 threads per slot cover the measurement copy (the larger part)
+  hipLaunchKernelGGL(k_stream_copy, dim3(8, (unsigned)d.n_snap), dim3(256), 0, st, d, retire, refill, zs, vm0,
+                     va0, vm_out, va_out);
   return hipGetLastError();
 }
 

@@ -41,6 +41,13 @@ hipError_t launch_pack_state(const Dev& d, const double* vm, const double* va, d
                              hipStream_t st);
 hipError_t launch_unpack_state(const Dev& d, double* vm, double* va, hipStream_t st);
 hipError_t launch_reset_flags(const Dev& d, hipStream_t st);
+// continuous batching (one refill workgroup, then the slots' copies)
+hipError_t launch_stream_refill(const Dev& d, int32_t* slot_id, int32_t* next, int32_t* retire,
+                                int32_t* refill, int32_t* out_iters, int32_t* out_flag, int32_t n_total,
+                                int32_t max_iter, hipStream_t st);
+hipError_t launch_stream_copy(const Dev& d, const int32_t* retire, const int32_t* refill, const double* zs,
+                              const double* vm0, const double* va0, double* vm_out, double* va_out,
+                              hipStream_t st);
 hipError_t allow_assemble_lds(size_t bytes, bool br_lds);
 
 }  // namespace mase

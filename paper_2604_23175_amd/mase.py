@@ -35,7 +35,7 @@ MAPS = {"boundary_flag": 0, "meas_area": 1, "gamma_vars": 2, "local_vars": 3,
 SYMBOLS = (
     "mase_default_options", "mase_create", "mase_destroy", "mase_last_error", "mase_strerror",
     "mase_set_measurements", "mase_set_measurements_dev", "mase_set_state", "mase_set_state_dev",
-    "mase_gn_iter", "mase_solve", "mase_state", "mase_state_dev", "mase_objective",
+    "mase_gn_iter", "mase_solve", "mase_solve_stream", "mase_state", "mase_state_dev", "mase_objective",
     "mase_eval_h_dev", "mase_info", "mase_export_map", "mase_export_pattern",
     "mase_stage_assemble", "mase_stage_condense", "mase_stage_gamma_assemble",
     "mase_stage_gamma_solve", "mase_stage_update", "mase_read_local_system", "mase_read_schur",
@@ -90,6 +90,8 @@ def load():
         "mase_set_state_dev": (ctypes.c_int, [P, P, P]),
         "mase_gn_iter": (ctypes.c_int, [P, f64p]),
         "mase_solve": (ctypes.c_int, [P, ctypes.c_double, ctypes.c_int32, i32p, i32p]),
+        "mase_solve_stream": (ctypes.c_int, [P, P, P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
+                                             P, P, i32p, i32p]),
         "mase_state": (ctypes.c_int, [P, f64p, f64p]),
         "mase_state_dev": (ctypes.c_int, [P, P, P]),
         "mase_objective": (ctypes.c_int, [P, f64p]),
@@ -268,6 +270,20 @@ class Mase:
         rc = self.lib.mase_solve(self.ctx, float(tol), int(max_iter),
                                  iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                  conv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        _check(rc, allow=(MASE_OK, MASE_NOT_CONVERGED))
+        return iters, conv.astype(bool)
+
+    def mase_solve_stream(self, z_dev, vm_out, va_out, vm0_dev=None, va0_dev=None, tol=1e-6, max_iter=10):
+        """Solves the n_total snapshots of z_dev [n_total][n_meas] through the
+        context's slots (continuous batching); states into vm_out / va_out
+        [n_total][n_bus] (device).  Returns per-snapshot iterations and flags."""
+        n_total = int(z_dev.shape[0])
+        iters = np.zeros(n_total, dtype=np.int32)
+        conv = np.zeros(n_total, dtype=np.int32)
+        rc = self.lib.mase_solve_stream(self.ctx, _dptr(z_dev), _dptr(vm0_dev), _dptr(va0_dev), n_total,
+                                        float(tol), int(max_iter), _dptr(vm_out), _dptr(va_out),
+                                        iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                        conv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
         _check(rc, allow=(MASE_OK, MASE_NOT_CONVERGED))
         return iters, conv.astype(bool)
 

@@ -103,6 +103,20 @@ def stats_table(path: str, title: str = "", command: str = "") -> str:
     return "\n".join(lines) + "\n"
 
 
+def last_dispatches(trace_csv: str, prefix: str, n: int) -> dict:
+    """Mean / min / max duration (us) of the last n dispatches of the kernel
+    whose short name starts with prefix, from a rocprofv3 kernel trace (the
+    benchmark's per-stage profiled pass is the last work of its run)."""
+    d = []
+    for r in csv.DictReader(open(trace_csv)):
+        if short_name(r["Kernel_Name"]).startswith(prefix):
+            d.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    d.sort()
+    w = [x[1] / 1e3 for x in d[-n:]]
+    return {"kernel_prefix": prefix, "dispatches": len(w), "mean_us": sum(w) / max(1, len(w)),
+            "min_us": min(w) if w else 0.0, "max_us": max(w) if w else 0.0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -115,8 +129,14 @@ def main():
     t.add_argument("write_csv")
     t.add_argument("--copy-mib", type=int, required=True)
     t.add_argument("--out", required=True)
+    ls = sub.add_parser("last")
+    ls.add_argument("trace_csv")
+    ls.add_argument("prefix")
+    ls.add_argument("n", type=int)
     a = ap.parse_args()
-    if a.cmd == "stats":
+    if a.cmd == "last":
+        print(json.dumps(last_dispatches(a.trace_csv, a.prefix, a.n)))
+    elif a.cmd == "stats":
         print(stats_table(a.csv, a.title, a.command), end="")
     else:
         res = traffic(a.fetch_csv, a.write_csv, a.copy_mib)

@@ -66,3 +66,38 @@ def test_partition_extremes_sampled_parity(name):
         assert ref["converged"] and iters[i] == ref["iters"]
         assert_state_close(vm[i], va[i], ref["vm"], ref["va"], 1e-8)
     m.close()
+
+
+def test_stream_full_size_matches_batched_and_oracle():
+    # the benchmark's stream configuration: 64 slots on the 9241-bus grid,
+    # a stream longer than the slots (every snapshot bitwise equal to its
+    # batched solve), sampled against the oracle
+    import torch
+    say("stream full size c2")
+    dev = torch.device("cuda:0")
+    from paper_2604_23175_amd import mase
+    c = Case("c2", 96, seed=7)
+    m = mase.Mase.from_grid(c.g, c.t, c.a, c.s, 64, slack=c.slack)
+    n = c.z.shape[0]
+    vm = torch.empty((n, c.g.n_bus), dtype=torch.float64, device=dev)
+    va = torch.empty_like(vm)
+    it, conv = m.mase_solve_stream(torch.tensor(c.z, device=dev), vm, va, None, None, 1e-6, 10)
+    assert conv.all(), it
+    vm, va = vm.cpu().numpy(), va.cpu().numpy()
+    for i0 in (0, 64):
+        idx = list(range(i0, min(n, i0 + 64)))
+        pad = idx + [idx[-1]] * (64 - len(idx))
+        m.mase_set_measurements(c.z[pad])
+        m.mase_set_state()
+        bit, bconv = m.mase_solve(1e-6, 10)
+        bvm, bva = m.mase_state()
+        k = len(idx)
+        np.testing.assert_array_equal(it[idx], bit[:k])
+        np.testing.assert_array_equal(vm[idx], bvm[:k])
+        np.testing.assert_array_equal(va[idx], bva[:k])
+    for i in (3, 70, 95):
+        say("  oracle snapshot", i)
+        ref = c.oracle_solve(i)
+        assert ref["converged"] and it[i] == ref["iters"]
+        assert_state_close(vm[i], va[i], ref["vm"], ref["va"], 1e-8)
+    m.close()

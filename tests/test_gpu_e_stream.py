@@ -1,0 +1,150 @@
+"""GPU continuous batching (mase_solve_stream) against the batched solve and the oracle.
+
+* every snapshot of a stream longer than the slot count ends bitwise equal
+  (state and iteration count) to the same snapshot solved by mase_solve in a
+  batch on the same context from the same start: a snapshot's arithmetic
+  does not depend on its slot or on the other snapshots in flight;
+* a sample of the stream matches the oracle's centralized Gauss-Newton to
+  1e-8 relative with the oracle's iteration count;
+* given starting states are used; streams shorter than the slot count and
+  empty streams; the iteration cap (every snapshot unconverged after
+  max_iter steps, states equal to the batched solve's); an unobservable area
+  drains the stream and reports MASE_ERR_NOT_POSDEF.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import Case, assert_state_close, say
+from paper_2604_23175_amd import mase
+
+DEV = torch.device("cuda:0") if torch.cuda.is_available() else None
+
+pytestmark = pytest.mark.gpu
+
+
+def batched_reference(m, z, vm0=None, va0=None, tol=1e-6, max_iter=10):
+    """Each chunk of n_snap snapshots solved by mase_solve on the same context
+    (the last chunk padded with copies of its last snapshot)."""
+    S, n = m.n_snap, z.shape[0]
+    vm = np.zeros((n, m.n_bus))
+    va = np.zeros((n, m.n_bus))
+    it = np.zeros(n, dtype=np.int32)
+    cv = np.zeros(n, dtype=bool)
+    for i0 in range(0, n, S):
+        idx = list(range(i0, min(n, i0 + S)))
+        pad = idx + [idx[-1]] * (S - len(idx))
+        m.mase_set_measurements_dev(torch.tensor(z[pad], device=DEV))
+        if vm0 is None:
+            m.mase_set_state_dev(None, None)
+        else:
+            m.mase_set_state_dev(torch.tensor(vm0[pad], device=DEV), torch.tensor(va0[pad], device=DEV))
+        iters, conv = m.mase_solve(tol, max_iter)
+        v, a = m.mase_state()
+        k = len(idx)
+        vm[idx], va[idx], it[idx], cv[idx] = v[:k], a[:k], iters[:k], conv[:k]
+    return vm, va, it, cv
+
+
+def run_stream(m, z, vm0=None, va0=None, tol=1e-6, max_iter=10):
+    n = z.shape[0]
+    zd = torch.tensor(z, device=DEV)
+    vm = torch.full((n, m.n_bus), -7.0, dtype=torch.float64, device=DEV)
+    va = torch.full_like(vm, -7.0)
+    v0 = None if vm0 is None else torch.tensor(vm0, device=DEV)
+    a0 = None if va0 is None else torch.tensor(va0, device=DEV)
+    iters, conv = m.mase_solve_stream(zd, vm, va, v0, a0, tol, max_iter)
+    torch.cuda.synchronize()
+    return vm.cpu().numpy(), va.cpu().numpy(), iters, conv
+
+
+@pytest.mark.parametrize("name,slots,n_total", [("k5", 3, 11), ("c1", 8, 21), ("c1", 8, 8)])
+def test_stream_bitwise_equal_to_batched(name, slots, n_total):
+    say("stream vs batched", name, slots, n_total)
+    c = Case(name, n_total, seed=31)
+    m = mase.Mase.from_grid(c.g, c.t, c.a, c.s, slots, slack=c.slack)
+    vm, va, it, cv = run_stream(m, c.z)
+    rvm, rva, rit, rcv = batched_reference(m, c.z)
+    np.testing.assert_array_equal(it, rit)
+    np.testing.assert_array_equal(cv, rcv)
+    np.testing.assert_array_equal(vm, rvm)
+    np.testing.assert_array_equal(va, rva)
+    assert cv.all()
+    for i in (0, n_total // 2, n_total - 1):
+        ref = c.oracle_solve(i)
+        assert ref["converged"] and it[i] == ref["iters"], (i, it[i], ref["iters"])
+        assert_state_close(vm[i], va[i], ref["vm"], ref["va"], 1e-8)
+    m.close()
+
+
+def test_stream_given_starting_states():
+    say("stream warm states")
+    c = Case("k5", 7, seed=32)
+    rng = np.random.default_rng(5)
+    vm0 = c.vm_true + rng.normal(0.0, 0.01, c.vm_true.shape)
+    va0 = c.va_true + rng.normal(0.0, 0.02, c.va_true.shape)
+    m = mase.Mase.from_grid(c.g, c.t, c.a, c.s, 3, slack=c.slack)
+    vm, va, it, cv = run_stream(m, c.z, vm0, va0)
+    rvm, rva, rit, rcv = batched_reference(m, c.z, vm0, va0)
+    np.testing.assert_array_equal(it, rit)
+    np.testing.assert_array_equal(vm, rvm)
+    np.testing.assert_array_equal(va, rva)
+    assert cv.all()
+    m.close()
+
+
+def test_stream_shorter_than_slots_and_empty():
+    say("stream short / empty")
+    c = Case("k5", 2, seed=33)
+    m = mase.Mase.from_grid(c.g, c.t, c.a, c.s, 5, slack=c.slack)
+    vm, va, it, cv = run_stream(m, c.z)
+    assert cv.all()
+    for i in range(2):
+        ref = c.oracle_solve(i)
+        assert it[i] == ref["iters"]
+        assert_state_close(vm[i], va[i], ref["vm"], ref["va"], 1e-8)
+    empty = np.zeros((0, c.z.shape[1]))
+    _, _, it0, cv0 = run_stream(m, empty)
+    assert it0.size == 0 and cv0.size == 0
+    # a later batched solve on the same context still works
+    m.mase_set_measurements(np.concatenate([c.z, c.z, c.z[:1]]))
+    m.mase_set_state()
+    iters, conv = m.mase_solve(1e-6, 10)
+    assert conv.all()
+    m.close()
+
+
+def test_stream_iteration_cap():
+    say("stream iteration cap")
+    c = Case("k5", 5, seed=34)
+    m = mase.Mase.from_grid(c.g, c.t, c.a, c.s, 2, slack=c.slack)
+    vm, va, it, cv = run_stream(m, c.z, max_iter=2)
+    rvm, rva, rit, rcv = batched_reference(m, c.z, max_iter=2)
+    assert not cv.any() and (it == 2).all()
+    np.testing.assert_array_equal(rit, it)
+    np.testing.assert_array_equal(vm, rvm)
+    np.testing.assert_array_equal(va, rva)
+    m.close()
+
+
+def test_stream_unobservable_area_reports_not_posdef():
+    say("stream not posdef")
+    c = Case("k5", 4, seed=35)
+    w = 1.0 / c.s ** 2
+    w[c.A.meas_area == 2] = 0.0
+    m = mase.Mase.from_grid(c.g, c.t, c.a, c.s, 3, slack=c.slack)
+    m.mase_set_measurements(np.concatenate([c.z[:3]]), w)
+    with pytest.raises(mase.MaseError) as e:
+        run_stream(m, c.z)
+    assert e.value.code == mase.MASE_ERR_NOT_POSDEF
+    m.close()
+
+
+def test_stream_needs_batched_schedule():
+    say("stream plain rejected")
+    c = Case("c0", 2, seed=36)
+    m = mase.Mase.from_grid(c.g, c.t, c.a, c.s, 2, slack=c.slack, batched=False)
+    with pytest.raises(mase.MaseError) as e:
+        run_stream(m, c.z)
+    assert e.value.code == mase.MASE_ERR_ARG
+    m.close()
