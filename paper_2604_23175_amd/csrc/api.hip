@@ -800,6 +800,8 @@ void mase_destroy(mase_ctx* c) {
     if (c->h_maxdx) (void)hipHostFree(c->h_maxdx);  // also holds h_active, h_status, h_iters
     if (c->h_tol) (void)hipHostFree(c->h_tol);
     if (c->st_out) (void)hipFree(c->st_out);
+    if (c->h_st_active) (void)hipHostFree(c->h_st_active);
+    for (auto e : c->st_ev) if (e) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   }
   delete c;
@@ -1202,42 +1204,85 @@ int mase_solve_stream(mase_ctx* c, const double* z_dev, const double* vm0_dev, c
   if (!c->have_z)
     HIPTRY(hipMemcpyAsync((void*)c->d.w, c->w_default, sizeof(double) * c->plan.n_meas, hipMemcpyDeviceToDevice,
                           c->stream));
-  auto refill_slots = [&]() -> int {
-    HIPTRY(launch_stream_refill(c->d, slot_id, next, retire, refill, out_iters, out_flag, nt, max_iter,
-                                c->stream));
-    HIPTRY(launch_stream_copy(c->d, retire, refill, z_dev, vm0_dev, va0_dev, vm_dev, va_dev, c->stream));
-    return read_flags(c);
-  };
-  if ((rc = refill_slots())) return rc;
+  HIPTRY(launch_stream_refill(c->d, slot_id, next, retire, refill, out_iters, out_flag, nt, max_iter, c->stream));
+  HIPTRY(launch_stream_copy(c->d, retire, refill, z_dev, vm0_dev, va0_dev, vm_dev, va_dev, c->stream));
+  if ((rc = read_flags(c))) return rc;
   c->have_z = true;
   if (c->opt.autotune && !c->tuned && c->opt.use_graph && !c->prof)
     if ((rc = autotune(c)) || (rc = read_flags(c))) return rc;
-  // every busy slot advances one iteration per pass and leaves after at most
-  // max_iter, so the stream needs at most ceil(n_total / S) * max_iter passes
-  const int64_t limit = ((n_total + S - 1) / S) * (int64_t)max_iter + 1;
-  int64_t pass = 0;
-  for (;;) {
-    int nact = 0;
-    for (int s = 0; s < S; ++s) nact += c->h_active[s] != 0;
-    if (nact == 0) break;
-    if (++pass > limit) return fail(MASE_ERR_STATE, "stream solve did not drain");
+  // while snapshots wait, every pass advances all S slots by one of at most
+  // n_total * max_iter snapshot-iterations; after the last one has entered,
+  // at most max_iter passes remain
+  const int64_t limit = (n_total * max_iter + S - 1) / S + max_iter + 1;
+  auto launch_pass = [&]() -> int {
     if (c->opt.use_graph && !c->prof) {
       if (!c->gexec) {
         HIPTRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-        rc = launch_batched_iteration(c, c->stream);
+        int e0 = launch_batched_iteration(c, c->stream);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(c->stream, &g);
-        if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+        if (e0) { if (g) (void)hipGraphDestroy(g); return e0; }
         if (e != hipSuccess) return fail(MASE_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
         c->graph = g;
         HIPTRY(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
       }
       HIPTRY(hipGraphLaunch(c->gexec, c->stream));
     } else {
-      if ((rc = launch_batched_iteration(c, c->stream))) return rc;
+      int e0 = launch_batched_iteration(c, c->stream);
+      if (e0) return e0;
     }
-    if ((rc = refill_slots())) return rc;
-    if ((rc = accumulate_profile(c, nact))) return rc;
+    HIPTRY(launch_stream_refill(c->d, slot_id, next, retire, refill, out_iters, out_flag, nt, max_iter,
+                                c->stream));
+    HIPTRY(launch_stream_copy(c->d, retire, refill, z_dev, vm0_dev, va0_dev, vm_dev, va_dev, c->stream));
+    return 0;
+  };
+  auto count_active = [&](const int32_t* a) {
+    int n = 0;
+    for (int s = 0; s < S; ++s) n += a[s] != 0;
+    return n;
+  };
+  if (c->opt.use_graph && !c->prof) {
+    // one pass always queued ahead: pass j + 1 is enqueued before the host
+    // waits for the active flags of pass j (two pinned flag buffers, two
+    // events), so the device never idles on the host's turnaround. A pass
+    // enqueued after the stream has drained finds every slot idle and
+    // changes nothing.
+    if (!c->h_st_active) {
+      void* hp = nullptr;
+      HIPTRY(hipHostMalloc(&hp, sizeof(int32_t) * 2 * (size_t)S, hipHostMallocDefault));
+      c->h_st_active = static_cast<int32_t*>(hp);
+      for (auto& e : c->st_ev) HIPTRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    auto enqueue = [&](int64_t j) -> int {
+      if ((rc = launch_pass())) return rc;
+      HIPTRY(hipMemcpyAsync(c->h_st_active + (j & 1) * S, c->d.active, sizeof(int32_t) * S, hipMemcpyDeviceToHost,
+                            c->stream));
+      HIPTRY(hipEventRecord(c->st_ev[j & 1], c->stream));
+      return 0;
+    };
+    if (count_active(c->h_active) > 0) {
+      if ((rc = enqueue(0))) return rc;
+      for (int64_t j = 0;; ++j) {
+        if (j + 1 > limit) {
+          (void)hipStreamSynchronize(c->stream);
+          return fail(MASE_ERR_STATE, "stream solve did not drain");
+        }
+        if ((rc = enqueue(j + 1))) return rc;
+        HIPTRY(hipEventSynchronize(c->st_ev[j & 1]));
+        if (count_active(c->h_st_active + (j & 1) * S) == 0) break;
+      }
+    }
+    if ((rc = read_flags(c))) return rc;
+  } else {
+    int64_t pass = 0;
+    for (;;) {
+      const int nact = count_active(c->h_active);
+      if (nact == 0) break;
+      if (++pass > limit) return fail(MASE_ERR_STATE, "stream solve did not drain");
+      if ((rc = launch_pass())) return rc;
+      if ((rc = read_flags(c))) return rc;
+      if ((rc = accumulate_profile(c, nact))) return rc;
+    }
   }
   std::vector<int32_t> h((size_t)2 * n_total);
   HIPTRY(hipMemcpyAsync(h.data(), out_iters, sizeof(int32_t) * n_total, hipMemcpyDeviceToHost, c->stream));

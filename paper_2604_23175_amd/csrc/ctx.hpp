@@ -63,6 +63,8 @@ struct mase_ctx {
   int32_t* st_slots = nullptr;
   int32_t* st_out = nullptr;
   int64_t st_out_cap = 0;
+  int32_t* h_st_active = nullptr;  // [2][n_snap] pinned: active flags of alternate passes
+  hipEvent_t st_ev[2] = {};
   // per-stage timing
   bool prof = false;
   hipEvent_t pev[2 * MASE_N_STAGE] = {};

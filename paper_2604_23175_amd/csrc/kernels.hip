@@ -662,7 +662,7 @@ __global__ void __launch_bounds__(256) k_gamma_gather(Dev d, int s0, int nslot) 
 // ---------------------------------------------------------------------------
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int DENSE_NT = 512;
+constexpr int DENSE_NT = 1024;
 constexpr int PANEL_PITCH = 17;  // doubles per staged panel row (odd: no LDS bank conflicts)
 
 template <bool LDS_PANEL>
@@ -824,7 +824,7 @@ __global__ void __launch_bounds__(DENSE_NT) k_dense_chol(Dev d, int s0) {
 // MFMA: nb/16 times fewer read-modify-write rounds over the trailing matrix
 // in HBM than 16-column steps need.  The rhs stays in LDS throughout.
 // ---------------------------------------------------------------------------
-constexpr int DW_NT = 512;
+constexpr int DW_NT = 1024;
 
 __global__ void __launch_bounds__(DW_NT) k_dense_wide(Dev d, int s0, int nb) {
   const int s = s0 + blockIdx.x;
