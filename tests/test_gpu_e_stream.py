@@ -9,7 +9,9 @@
 * given starting states are used; streams shorter than the slot count and
   empty streams; the iteration cap (every snapshot unconverged after
   max_iter steps, states equal to the batched solve's); an unobservable area
-  drains the stream and reports MASE_ERR_NOT_POSDEF.
+  drains the stream and reports MASE_ERR_NOT_POSDEF;
+* the stream without graph capture equals the graph-replayed one bitwise, and
+  a context that autotunes inside its first stream call reaches the oracle.
 """
 import numpy as np
 import pytest
@@ -147,4 +149,29 @@ def test_stream_needs_batched_schedule():
     with pytest.raises(mase.MaseError) as e:
         run_stream(m, c.z)
     assert e.value.code == mase.MASE_ERR_ARG
+    m.close()
+
+
+def test_stream_schedules_and_autotune(tmp_path):
+    # the stream without graph capture (direct launches, one host check per
+    # pass) equals the graph-replayed stream bitwise; a context that tunes
+    # inside its first stream call reaches the oracle's states
+    say("stream schedules / autotune")
+    c = Case("c1", 11, seed=37)
+    out = []
+    for kw in (dict(), dict(use_graph=False)):
+        m = mase.Mase.from_grid(c.g, c.t, c.a, c.s, 4, slack=c.slack, **kw)
+        out.append(run_stream(m, c.z))
+        m.close()
+    for a, b in zip(out[0], out[1]):
+        np.testing.assert_array_equal(a, b)
+    m = mase.Mase.from_grid(c.g, c.t, c.a, c.s, 4, slack=c.slack, autotune=True,
+                            tune_cache=str(tmp_path / "tune.txt"))
+    vm, va, it, cv = run_stream(m, c.z)
+    assert cv.all()
+    assert (tmp_path / "tune.txt").exists()
+    for i in (0, 5, 10):
+        ref = c.oracle_solve(i)
+        assert it[i] == ref["iters"]
+        assert_state_close(vm[i], va[i], ref["vm"], ref["va"], 1e-8)
     m.close()
