@@ -656,6 +656,9 @@ __global__ void __launch_bounds__(256) k_gamma_gather(Dev d, int s0, int nslot) 
 // one wave (wave_chol16_inv4, which also forms its inverse), the panel below
 // is multiplied by that inverse on MFMA, and the symmetric trailing update
 // A_ij -= L_ik L_jk^T runs on v_mfma_f64_16x16x4f64, one 16x16 tile per wave.
+// With one step of lookahead: the next panel's column is updated first, then
+// wave 0 factors the next diagonal block while the other waves finish the
+// trailing update (every tile still takes the updates in step order).
 // The forward solve rides along; the back solve runs block by block from the
 // bottom.  The block is column-major with leading dimension n (a multiple of
 // 16); rows and columns past the live size are set to the identity first.
@@ -692,25 +695,57 @@ __global__ void __launch_bounds__(DENSE_NT) k_dense_chol(Dev d, int s0) {
     for (int r = (c > nlive ? c : nlive); r < n; ++r) A[(int64_t)c * n + r] = (r == c) ? 1.0 : 0.0;
   __syncthreads();
   const int nb = n / 16;
-  for (int k = 0; k < nb; ++k) {
+  // the diagonal block of step k to LDS, then wave 0 factors it, solves y
+  // and inverts L_kk (the caller synchronises before and after)
+  auto load_diag = [&](int k, int first, int stride) {
     const int c0 = 16 * k;
-    // diagonal block to LDS; wave 0 factors it, solves y and inverts L_kk
-    for (int i = tid; i < 256; i += nt) {
+    for (int i = first; i < 256; i += stride) {
       const int r = i & 15, m = i >> 4;
       Dk[m * 17 + r] = (r >= m) ? A[(int64_t)(c0 + m) * n + c0 + r] : 0.0;
     }
-    __syncthreads();
-    if (wv == 0) {
-      const bool ok = wave_chol16_inv4(Dk, 17, 0, bl + c0, Linv, cxb);
-      if (!ok && lane == 0) bad = 1;
+  };
+  // A_IJ -= L_Ik L_Jk^T for the 16x16 tile at rows ri, columns rj (global
+  // offsets), computed transposed (rows J x rows I): lane li holds row ri + li,
+  // so the accumulator's global accesses run down a column.
+  // v_mfma_f64_16x16x4f64 operands: lane l holds A[l%16][l/16] and
+  // B[l/16][l%16]; accumulator element q of lane l is D[4q + l/16][l%16].
+  auto tile_load = [&](int ri, int rj, d4& acc) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = A[(int64_t)(rj + 4 * q + lk) * n + ri + li];
+  };
+  auto tile_update = [&](int c0, int ri, int rj, d4& acc) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double a, bb;
+      if (LDS_PANEL) {
+        a = -Lp[(rj - c0 - 16 + li) * PANEL_PITCH + 4 * q + lk];
+        bb = Lp[(ri - c0 - 16 + li) * PANEL_PITCH + 4 * q + lk];
+      } else {
+        a = -A[(int64_t)(c0 + 4 * q + lk) * n + rj + li];
+        bb = A[(int64_t)(c0 + 4 * q + lk) * n + ri + li];
+      }
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
     }
-    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) A[(int64_t)(rj + 4 * q + lk) * n + ri + li] = acc[q];
+  };
+  // step 0's diagonal block
+  load_diag(0, tid, nt);
+  __syncthreads();
+  if (wv == 0) {
+    const bool ok = wave_chol16_inv4(Dk, 17, 0, bl, Linv, cxb);
+    if (!ok && lane == 0) bad = 1;
+  }
+  __syncthreads();
+  for (int k = 0; k < nb; ++k) {
+    const int c0 = 16 * k;
+    // (1) L_kk back to the block; rows below: X^T = L_kk^-1 A^T on MFMA, one
+    // 16-row tile per wave; lane li holds row ri + li, so the accesses run
+    // down columns
     for (int i = tid; i < 256; i += nt) {
       const int r = i & 15, m = i >> 4;
       if (r >= m) A[(int64_t)(c0 + m) * n + c0 + r] = Dk[m * 17 + r];
     }
-    // rows below the block: X^T = L_kk^-1 A^T on MFMA, one 16-row tile per
-    // wave; lane li holds row ri + li, so the accesses run down columns
     for (int t = wv; t < nb - k - 1; t += nw) {
       const int ri = c0 + 16 + 16 * t;
       d4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -727,6 +762,9 @@ __global__ void __launch_bounds__(DENSE_NT) k_dense_chol(Dev d, int s0) {
       }
     }
     __syncthreads();
+    if (k + 1 == nb) break;
+    // (2) rhs of the rows below, and the next panel's column of tiles
+    // (I, k + 1), I > k, which the next diagonal factorisation needs first
     for (int row = c0 + 16 + tid; row < n; row += nt) {
       double acc = 0.0;
 #pragma unroll
@@ -734,51 +772,47 @@ __global__ void __launch_bounds__(DENSE_NT) k_dense_chol(Dev d, int s0) {
         acc += (LDS_PANEL ? Lp[(row - c0 - 16) * PANEL_PITCH + c] : A[(int64_t)(c0 + c) * n + row]) * bl[c0 + c];
       bl[row] -= acc;
     }
-    // trailing update on MFMA: tiles (I, J), k < J <= I, one tile per wave.
-    // v_mfma_f64_16x16x4f64 operands: lane l holds A[l%16][l/16] and
-    // B[l/16][l%16]; accumulator element q of lane l is D[4q + l/16][l%16].
-    // Each wave takes TB tiles per pass: their accumulators are loaded
-    // together so the global round trips overlap.
-    const int m = nb - k - 1;
-    const int ntile = m * (m + 1) / 2;
-    constexpr int TB = 4;
-    for (int t0 = wv; t0 < ntile; t0 += nw * TB) {
-      int ri[TB], rj[TB];
-      d4 acc[TB];
+    for (int t = wv; t < nb - k - 1; t += nw) {
+      const int ri = c0 + 16 + 16 * t, rj = c0 + 16;
+      d4 acc;
+      tile_load(ri, rj, acc);
+      tile_update(c0, ri, rj, acc);
+    }
+    __syncthreads();
+    // (3) lookahead: wave 0 factors the next diagonal block while the other
+    // waves finish this step's trailing update, tiles (I, J) with
+    // k + 1 < J <= I; each wave loads TB tiles together so the global round
+    // trips overlap. Every tile still takes the steps' updates in step order.
+    if (wv == 0) {
+      load_diag(k + 1, lane, 64);
+      wave_lds_sync();
+      const bool ok = wave_chol16_inv4(Dk, 17, 0, bl + c0 + 16, Linv, cxb);
+      if (!ok && lane == 0) bad = 1;
+    } else {
+      const int m = nb - k - 2;
+      const int ntile = m * (m + 1) / 2;
+      constexpr int TB = 4;
+      const int nwt = nw - 1;
+      for (int t0 = wv - 1; t0 < ntile; t0 += nwt * TB) {
+        int ri[TB], rj[TB];
+        d4 acc[TB];
 #pragma unroll
-      for (int b = 0; b < TB; ++b) {
-        const int t = t0 + b * nw;
-        ri[b] = -1;
-        if (t < ntile) {
-          int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-          while (I * (I + 1) / 2 > t) --I;
-          while ((I + 1) * (I + 2) / 2 <= t) ++I;
-          const int J = t - I * (I + 1) / 2;
-          ri[b] = 16 * (k + 1 + I);
-          rj[b] = 16 * (k + 1 + J);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) acc[b][q] = A[(int64_t)(rj[b] + 4 * q + lk) * n + ri[b] + li];
-        }
-      }
-#pragma unroll
-      for (int b = 0; b < TB; ++b) {
-        if (ri[b] < 0) continue;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          double a, bb;
-          // computed transposed (rows J x rows I): lane li holds row ri + li,
-          // so the accumulator's global accesses run down a column
-          if (LDS_PANEL) {
-            a = -Lp[(rj[b] - c0 - 16 + li) * PANEL_PITCH + 4 * q + lk];
-            bb = Lp[(ri[b] - c0 - 16 + li) * PANEL_PITCH + 4 * q + lk];
-          } else {
-            a = -A[(int64_t)(c0 + 4 * q + lk) * n + rj[b] + li];
-            bb = A[(int64_t)(c0 + 4 * q + lk) * n + ri[b] + li];
+        for (int bq = 0; bq < TB; ++bq) {
+          const int t = t0 + bq * nwt;
+          ri[bq] = -1;
+          if (t < ntile) {
+            int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+            while (I * (I + 1) / 2 > t) --I;
+            while ((I + 1) * (I + 2) / 2 <= t) ++I;
+            const int J = t - I * (I + 1) / 2;
+            ri[bq] = 16 * (k + 2 + I);
+            rj[bq] = 16 * (k + 2 + J);
+            tile_load(ri[bq], rj[bq], acc[bq]);
           }
-          acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc[b], 0, 0, 0);
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) A[(int64_t)(rj[b] + 4 * q + lk) * n + ri[b] + li] = acc[b][q];
+        for (int bq = 0; bq < TB; ++bq)
+          if (ri[bq] >= 0) tile_update(c0, ri[bq], rj[bq], acc[bq]);
       }
     }
     __syncthreads();
