@@ -115,7 +115,8 @@ def k_sweep(ks, steps, warmup):
         sizes = np.bincount(g.bus_area, minlength=k)
         rec = {"n_area": k, "area_buses_min": int(sizes.min()), "area_buses_max": int(sizes.max())}
         try:
-            ctx = mase.Mase.from_grid(g, t, a, s, N_SNAP)
+            ctx = mase.Mase.from_grid(g, t, a, s, N_SNAP, autotune=True,
+                                      tune_cache=os.path.join(tempfile.gettempdir(), "mase_autotune.txt"))
         except mase.MaseError as e:
             rec["error"] = str(e)
             print(json.dumps(rec), flush=True)
@@ -147,11 +148,23 @@ def k_sweep(ks, steps, warmup):
             ctx.mase_solve(TOL, MAX_ITER)
         prof = ctx.mase_profile_read()
         ctx.mase_profile(False)
+        # the same steps as one stream through the 64 slots (continuous batching)
+        zs = z.repeat(steps, 1).contiguous()
+        vs = torch.empty((N_SNAP * steps, g.n_bus), dtype=torch.float64, device=dev)
+        as_ = torch.empty_like(vs)
+        ctx.mase_solve_stream(zs, vs, as_, None, None, TOL, MAX_ITER)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, sconv = ctx.mase_solve_stream(zs, vs, as_, None, None, TOL, MAX_ITER)
+        torch.cuda.synchronize()
+        sdt = time.perf_counter() - t1
+        del zs, vs, as_
         total = sum(v["ms"] for v in prof.values())
         gam = sum(prof[k2]["ms"] for k2 in gamma_stages if k2 in prof)
         rec.update({"n_gamma": ctx.mase_info("n_gamma"), "boundary_buses": ctx.mase_info("n_boundary_bus"),
                     "snapshots_per_s": N_SNAP * steps / dt, "mean_iters": its / (N_SNAP * steps),
                     "all_converged": bool(conv.all()),
+                    "stream_snapshots_per_s": N_SNAP * steps / sdt, "stream_all_converged": bool(sconv.all()),
                     "boundary_share": gam / total if total > 0 else None,
                     "stages_ms_per_step": {k2: v["ms"] / steps for k2, v in prof.items() if v["launches"]}})
         print(json.dumps(rec), flush=True)
