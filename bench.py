@@ -5,19 +5,27 @@ Workload: the synthetic 9241-bus / 16049-branch grid in 32 areas (stand-in
 for PEGASE-9241), 64 snapshots per batch drifted from the base state (|V|
 jitter N(0, 0.003), theta jitter N(0, 0.005)) with fresh measurement noise,
 full measurement set (|V|, P/Q injections at every bus, P/Q flows at both
-branch ends).  A step solves the whole batch from its starting point to
-max |dx| < 1e-6 (at most 10 Gauss-Newton iterations) and writes the states to
-device memory.  Measurements are resident in HBM before the timed region.
+branch ends).  `--workload c3` runs the 10000-bus / 12706-branch grid in 16
+areas instead.
 
-`value` is the continuous-batching path: the K steps' K x 64 snapshots pass
-through 64 slots (all areas x slots per launch, hipGraph-captured iteration),
-and a slot whose snapshot has converged takes the next one at once, so no
-iteration runs for a batch's last few snapshots alone.  The same steps as
-separate batches (`batched_warm`, `batched_flat`) are reported beside it.
-Printed as one JSON line: that path as `value`, the plain per-area / per-snapshot
-schedule on the same batch as `plain`, per-kernel times from HIP events
-recorded around each stage kernel inside the timed region, the roofline of the
-dominant kernel, and the CPU oracle timed on a bounded sample.
+`value` times the whole path as the paper does (Section 5.1: measurements
+in, states out): the K steps' K x 64 snapshots start in pinned host memory
+and end there.  They pass through the context's 64 slots (continuous
+batching, all areas x slots per launch, hipGraph-captured iteration): each
+chunk of 64 measurement vectors is uploaded on a copy stream ahead of the
+stream position and each chunk of solved states is downloaded as soon as its
+snapshots have left their slots, so the copies overlap the iterations.  A
+snapshot counts as solved at max |dx| < 1e-6 within 10 Gauss-Newton
+iterations.  The learned warm start is trained on held-out drift chains and
+its acceptance cap calibrated on others; when the cap rejects every
+prediction the network is not run and the workload says so.
+
+Also printed: the same stream with measurements and states resident in HBM,
+the steps as separate batches, the plain per-area / per-snapshot schedule,
+per-kernel times from HIP events around each stage kernel, the roofline of
+the dominant kernel, and the CPU oracle (centralized FP64 Gauss-Newton) on
+one host core and on all host cores, plus a single 2869-bus snapshot on the
+GPU and on the oracle (the paper's single-snapshot protocol).
 """
 import argparse
 import hashlib
@@ -36,45 +44,93 @@ HBM_PEAK = 8.0e12       # B/s, MI355X HBM3E
 FP64_PEAK = 78.6e12     # flop/s, MI355X dense FP64 (vector and matrix)
 TOL, MAX_ITER, N_SNAP = 1e-6, 10, 64
 WORKLOAD = "c2"
+WORKLOAD_NAMES = {"c2": "9241-bus/16049-branch synthetic grid, 32 areas",
+                  "c3": "10000-bus/12706-branch synthetic grid, 16 areas"}
 
 
-def make_inputs(n_snap, seed=0):
+def make_inputs(n_snap, seed=0, workload=None):
     from gridgen import synth
-    g = synth.make_config(WORKLOAD)
+    g = synth.make_config(workload or WORKLOAD)
     t, a, s = synth.measurement_set(g.n_bus, g.n_branch)
     b = synth.make_batch(g, n_snap, seed)
     va = b.va_true - b.va_true[:, [g.slack]]
     return g, t, a, s, b.vm_true, va, b.eps
 
 
-def cpu_leg(budget_s):
-    """Oracle (centralized numpy/scipy GN) on a bounded sample, one thread."""
+def cpu_leg(spec):
+    """Oracle (centralized numpy/scipy GN) on the snapshots `spec` names,
+    in this process (the parent pins its BLAS to one thread).
+    spec: "<workload>:<first>:<step>:<count>:<repeats>"."""
     from oracle import network as nw
     from oracle import wls
-    g, t, a, s, vm, va, eps = make_inputs(N_SNAP)
+    wl, first, step, count, reps = spec.split(":")
+    first, step, count, reps = int(first), int(step), int(count), int(reps)
+    n = N_SNAP if wl in ("c2", "c3") else 1
+    g, t, a, s, vm, va, eps = make_inputs(n, workload=wl)
     net = nw.from_grid(g, t, a, s)
-    done, iters = 0, 0
-    t0 = time.perf_counter()
-    for i in range(N_SNAP):
-        z = nw.measurements(net, vm[i], va[i], eps[i])
-        out = wls.gauss_newton(net, z, tol=TOL, max_iter=MAX_ITER)
-        done += 1
-        iters += out["iters"]
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    print(json.dumps({"snapshots": done, "seconds": dt, "iters": iters}))
+    idx = list(range(first, n, step))[:count]
+    zs = [nw.measurements(net, vm[i], va[i], eps[i]) for i in idx]
+    times, iters = [], 0
+    for r in range(reps):
+        t0 = time.perf_counter()
+        for z in zs:
+            out = wls.gauss_newton(net, z, tol=TOL, max_iter=MAX_ITER)
+            if r == 0:
+                iters += out["iters"]
+        times.append(time.perf_counter() - t0)
+    print(json.dumps({"snapshots": len(idx), "seconds": times, "iters": iters}))
 
 
-def run_cpu_baseline(budget_s):
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _spawn_cpu(spec):
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-leg", str(budget_s)],
-                         capture_output=True, text=True, env=env, check=True)
-    r = json.loads(out.stdout.strip().splitlines()[-1])
-    return {"value": r["snapshots"] / r["seconds"], "unit": "snapshots/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {r['snapshots']} of the {N_SNAP} snapshots of the benchmark batch, flat start, "
-                      f"centralized FP64 GN with scipy splu, {r['iters']} GN iterations in {r['seconds']:.1f} s, "
-                      "one thread (OMP/OPENBLAS/MKL_NUM_THREADS=1)"}
+    return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-leg", spec],
+                            stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env)
+
+
+def _collect(p):
+    out, err = p.communicate()
+    if p.returncode != 0:
+        raise RuntimeError(f"oracle process failed: {err[-2000:]}")
+    return json.loads(out.strip().splitlines()[-1])
+
+
+def run_cpu_baseline(workload):
+    """The oracle on the benchmark batch: all 64 snapshots on one core, then
+    on every core of this process's CPU set (one process per core, snapshots
+    dealt round-robin, BLAS threads 1); and one 2869-bus snapshot, mean of
+    runs 2-11 (the paper's protocol, Section 5.1)."""
+    cores = len(os.sched_getaffinity(0))
+    one = _collect(_spawn_cpu(f"{workload}:0:1:{N_SNAP}:1"))
+    t1 = one["seconds"][0]
+    t0 = time.perf_counter()
+    procs = [_spawn_cpu(f"{workload}:{r}:{cores}:{N_SNAP}:1") for r in range(min(cores, N_SNAP))]
+    res = [_collect(p) for p in procs]
+    wall = time.perf_counter() - t0
+    span = max(r["seconds"][0] for r in res)
+    single = _collect(_spawn_cpu("c1:0:1:1:11"))
+    t_single = sum(single["seconds"][1:]) / 10
+    return {"value": N_SNAP / t1, "unit": "snapshots/s", "cores": 1, "kind": "oracle",
+            "sample": f"all {N_SNAP} snapshots of the benchmark batch on one host core, flat start, centralized "
+                      f"FP64 GN with scipy splu, {one['iters']} GN iterations in {t1:.1f} s "
+                      "(OMP/OPENBLAS/MKL_NUM_THREADS=1)",
+            "cpu_model": _cpu_model(), "host_cores_available": cores,
+            "all_cores": {"value": N_SNAP / span, "unit": "snapshots/s", "cores": len(res),
+                          "processes": len(res), "solve_span_s": span, "wall_s_with_startup": wall,
+                          "note": "one process per core, snapshots dealt round-robin, BLAS threads 1; value "
+                                  "from the slowest process's solve time (grid set-up excluded)"},
+            "single_snapshot_c1": {"ms": 1e3 * t_single, "iters": single["iters"],
+                                   "note": "2869-bus grid, one snapshot, mean of runs 2-11, one core"}}
 
 
 def traffic_for(kernel):
@@ -274,15 +330,81 @@ def local_sweep(ls, steps, warmup):
             ctx.close()
 
 
+def warm_rank_bound(n_chain=313, chain_len=64, hidden=256):
+    """Lower bound of the warm-start network's standardised training loss set
+    by its shape alone.  The output layer maps the last 256 hidden units
+    affinely, so every prediction of an area lies in an affine subspace of at
+    most 256 dimensions; the mean squared error of any such map over a set of
+    targets is at least the variance outside the targets' leading 256
+    principal directions.  Computed per area on the training chains' true
+    states (standardised per variable as in training), summed and divided by
+    the total output count.  CPU only."""
+    import numpy as np
+    from gridgen import synth
+    from paper_2604_23175_amd import warmstart as ws
+    g = synth.make_config(WORKLOAD)
+    vm, va, _ = synth.make_chains(g, n_chain, chain_len, ws.TRAIN_SEED)
+    va = va - va[:, [g.slack]]
+    tail_total, n_out_total, per_area = 0.0, 0, []
+    for k in range(g.n_area):
+        own = np.nonzero(g.bus_area == k)[0]
+        cols = [va[:, own[own != g.slack]], vm[:, own]]
+        Y = np.concatenate(cols, axis=1)
+        sd = Y.std(0)
+        Y = (Y - Y.mean(0)) / np.where(sd > 1e-6, sd, 1.0)
+        lam = np.sort(np.linalg.eigvalsh(Y.T @ Y / Y.shape[0]))[::-1]
+        tail = float(lam[hidden:].sum())
+        tail_total += tail
+        n_out_total += Y.shape[1]
+        per_area.append({"area": k, "outputs": int(Y.shape[1]), "mse_floor": tail / Y.shape[1]})
+    print(json.dumps({"workload": WORKLOAD_NAMES[WORKLOAD], "training_snapshots": int(vm.shape[0]),
+                      "hidden": hidden, "mse_floor_rank_affine": tail_total / n_out_total,
+                      "areas_with_more_outputs_than_hidden": sum(a["outputs"] > hidden for a in per_area),
+                      "per_area": per_area}))
+
+
+def single_snapshot_gpu(dev):
+    """The paper's protocol on the GPU: one 2869-bus snapshot (8 areas), host
+    measurements in, host states out, mean of runs 2-11 (Section 5.1)."""
+    from gridgen import synth
+    from oracle import network as nw  # noqa: F401  (not used: z from the library's own h)
+    from paper_2604_23175_amd import mase
+    import torch
+    g, t, a, s, vm, va, eps = make_inputs(1, workload="c1")
+    out = {}
+    for label, kw in (("batched", {}), ("plain", {"batched": False})):
+        ctx = mase.Mase.from_grid(g, t, a, s, 1, **kw)
+        h = torch.empty((1, t.size), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        ctx.mase_eval_h_dev(torch.tensor(vm, device=dev), torch.tensor(va, device=dev), h)
+        torch.cuda.synchronize()
+        z = (h + torch.tensor(s, device=dev) * torch.tensor(eps, device=dev)).cpu().numpy()
+        times, its = [], 0
+        for r in range(11):
+            t0 = time.perf_counter()
+            ctx.mase_set_measurements(z)
+            ctx.mase_set_state()
+            it, conv = ctx.mase_solve(TOL, MAX_ITER)
+            ctx.mase_state()
+            times.append(time.perf_counter() - t0)
+            its = int(it[0])
+        out[label] = {"ms": 1e3 * sum(times[1:]) / 10, "iters": its, "converged": bool(conv.all())}
+        ctx.close()
+    out["note"] = ("2869-bus synthetic grid, 8 areas, one snapshot, host z in and host states out, mean of "
+                   "runs 2-11; the paper's 24.7 ms for PEGASE-2869 (K = 6, RTX 4080, Table 1) is context only")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOAD_NAMES))
     ap.add_argument("--plain-steps", type=int, default=1)
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--warm-chains", type=int, default=313,
                     help="64-snapshot drift chains solved to train the warm start (0: flat start only)")
     ap.add_argument("--warm-epochs", type=int, default=20)
@@ -297,10 +419,18 @@ def main():
     ap.add_argument("--local-sweep", default=None,
                     help="comma-separated local-step counts (boundary held, Eq. 6) before each condensed "
                          "step; the first should be 0 (one JSON line each)")
-    ap.add_argument("--cpu-leg", type=float, default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--warm-rank-bound", action="store_true",
+                    help="lower bound of the standardised training MSE of any network whose output layer is "
+                         "affine in 256 hidden units, from the training targets (CPU only)")
+    ap.add_argument("--cpu-leg", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    global WORKLOAD
+    WORKLOAD = args.workload
     if args.cpu_leg is not None:
         cpu_leg(args.cpu_leg)
+        return
+    if args.warm_rank_bound:
+        warm_rank_bound()
         return
     if args.masking:
         masking(args.steps, args.warmup)
@@ -352,7 +482,7 @@ def main():
 
     # learned warm start: train on plain-solver solutions of independent drift
     # chains (never the benchmark batch), outside the timed region
-    mlp, train_info = None, None
+    mlp, train_info, cap = None, None, float("-inf")
     if args.warm_chains > 0:
         from paper_2604_23175_amd import warmstart as ws
         t_tr = time.perf_counter()
@@ -366,14 +496,16 @@ def main():
                       "seconds": time.perf_counter() - t_tr}
         del zt, vmt_, vat_
         # acceptance cap from held-out chains (never the benchmark batch)
-        _, train_info["acceptance_calibration"] = ws.calibrate_accept_cap(ctx, mlp, g, s, dev)
+        cap, train_info["acceptance_calibration"] = ws.calibrate_accept_cap(ctx, mlp, g, s, dev)
         ctx.mase_set_measurements_dev(z)
         torch.cuda.synchronize()
+    # the network runs only when its cap can accept a prediction
+    warm = mlp is not None and cap > float("-inf")
 
     accepted_count = [0, 0]
 
-    def step(c, warm=False):
-        if warm:
+    def step(c, use_warm=False):
+        if use_warm:
             acc = mase.mase_warm_start(c, mlp)
             accepted_count[0] += int(acc.sum())
             accepted_count[1] += acc.size
@@ -383,30 +515,34 @@ def main():
         c.mase_state_dev(vm_out, va_out)
         return iters, conv
 
-    def timed(c, steps, warm=False):
+    def timed(c, steps, use_warm=False):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         n_it, ok = 0, True
         for _ in range(steps):
-            iters, conv = step(c, warm)
+            iters, conv = step(c, use_warm)
             n_it += int(iters.sum())
             ok &= bool(conv.all())
         torch.cuda.synchronize()
         return time.perf_counter() - t0, n_it, ok
 
-    warm = mlp is not None
     # continuous batching: the K steps' batches as one stream of K x 64
-    # snapshots through the context's 64 slots; with the warm start, each
-    # batch's starting states come from the network (with rejection) first
+    # snapshots through the context's 64 slots
     n_stream = N_SNAP * args.steps
     z_stream = z.repeat(args.steps, 1).contiguous()
     vm_s = torch.empty((n_stream, g.n_bus), dtype=torch.float64, device=dev)
     va_s = torch.empty_like(vm_s)
     vm0_s = torch.empty_like(vm_s) if warm else None
     va0_s = torch.empty_like(vm_s) if warm else None
+    # host ends: pinned measurements in, pinned states out, device workspace
+    z_host = z_stream.cpu().pin_memory()
+    vm_h = torch.empty((n_stream, g.n_bus), dtype=torch.float64).pin_memory()
+    va_h = torch.empty_like(vm_h).pin_memory()
+    work = torch.empty(ctx.mase_stream_host_work(n_stream, False), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
 
-    def stream(c, warm):
-        if warm:
+    def stream_device(c, use_warm):
+        if use_warm:
             for k in range(args.steps):
                 acc = mase.mase_warm_start(c, mlp)
                 accepted_count[0] += int(acc.sum())
@@ -419,49 +555,57 @@ def main():
         c.mase_set_measurements_dev(z)
         return iters, conv
 
-    def timed_stream(c, warm):
+    def stream_host(c):
+        iters, conv = c.mase_solve_stream_host(z_host, vm_h, va_h, work, None, None, TOL, MAX_ITER)
+        c.mase_set_measurements_dev(z)
+        return iters, conv
+
+    def stream_host_warm(c):
+        # the network needs the measurements on the device: upload, predict
+        # batch by batch (with rejection), then the device stream, download
+        z_stream.copy_(z_host, non_blocking=True)
+        torch.cuda.synchronize()
+        iters, conv = stream_device(c, True)
+        vm_h.copy_(vm_s, non_blocking=True)
+        va_h.copy_(va_s, non_blocking=True)
+        torch.cuda.synchronize()
+        return iters, conv
+
+    def timed_call(fn, *a):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        iters, conv = stream(c, warm)
+        iters, conv = fn(*a)
         torch.cuda.synchronize()
         return time.perf_counter() - t0, int(iters.sum()), bool(conv.all())
 
+    headline = (lambda c: stream_host_warm(c)) if warm else stream_host
     for _ in range(args.warmup):
         step(ctx, warm)
         step(ctx, False)
-    stream(ctx, warm)
-    # headline: continuous batching (+ warm start when trained), graph-replayed iterations
+    headline(ctx)
+    stream_device(ctx, False)
+    # headline: host to host, continuous batching (+ warm start when its cap can accept)
     accepted_count[:] = [0, 0]
-    dt, tot_iters, all_conv = timed_stream(ctx, warm)
+    dt, tot_iters, all_conv = timed_call(headline, ctx)
     value = n_stream / dt
-    acc_frac = accepted_count[0] / max(1, accepted_count[1])
-    sdt, s_iters, s_conv = timed_stream(ctx, False)
+    acc_frac = accepted_count[0] / max(1, accepted_count[1]) if warm else 0.0
+    vm_hs, va_hs = vm_h.numpy().copy(), va_h.numpy().copy()
+    # the same stream with measurements and states resident in HBM
+    ddt, d_iters, d_conv = timed_call(stream_device, ctx, False)
     vm_st, va_st = vm_s.cpu().numpy(), va_s.cpu().numpy()
+    host_same = bool(np.array_equal(vm_hs, vm_st) and np.array_equal(va_hs, va_st)) if not warm else None
     # the same steps as separate batches (+ warm start), then flat start
-    bdt, b_iters, b_conv = timed(ctx, args.steps, warm)
+    bdt, b_iters, b_conv = timed(ctx, args.steps, warm) if warm else (None, None, None)
     fdt, f_iters, f_conv = timed(ctx, args.steps, False)
     vm_b, va_b = vm_out.cpu().numpy(), va_out.cpu().numpy()
     stream_same = bool(np.array_equal(vm_st, np.tile(vm_b, (args.steps, 1)))
                        and np.array_equal(va_st, np.tile(va_b, (args.steps, 1))))
-    # the same flat-start steps with host buffers at the boundary: measurements
-    # uploaded and states downloaded through PCIe inside the timed region
-    z_host = z.cpu().numpy()
-    ctx.mase_set_measurements(z_host)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ctx.mase_set_measurements(z_host)
-        ctx.mase_set_state()
-        ctx.mase_solve(TOL, MAX_ITER)
-        ctx.mase_state()
-    torch.cuda.synchronize()
-    hdt = time.perf_counter() - t0
     ctx.mase_set_measurements_dev(z)
     torch.cuda.synchronize()
-    # the headline stream again with a HIP event pair around every stage kernel
+    # the device stream again with a HIP event pair around every stage kernel
     # (direct launches: event pairs inside a graph cannot be timed)
     ctx.mase_profile(True)
-    pdt_prof, _, _ = timed_stream(ctx, warm)
+    pdt_prof, _, _ = timed_call(stream_device, ctx, False)
     prof = ctx.mase_profile_read()
     ctx.mase_profile(False)
     info = {k: ctx.mase_info(k) for k in mase.INFO}
@@ -485,8 +629,10 @@ def main():
         plain = {"value": N_SNAP * args.plain_steps / pdt, "unit": "snapshots/s",
                  "ms_per_step": 1e3 * pdt / args.plain_steps,
                  "gn_iters_per_s": p_iters / pdt, "states_bitwise_equal_to_batched_flat": same,
-                 "schedule": "one snapshot at a time, flat start, per-area launches on 32 streams, no graph"}
+                 "schedule": "one snapshot at a time, flat start, per-area launches on per-area streams, "
+                             "no graph, measurements and states resident in HBM"}
         pc.close()
+    single = None if args.no_single or WORKLOAD != "c2" else single_snapshot_gpu(dev)
 
     # roofline of the dominant kernel (largest accumulated time in the timed region)
     # per-snapshot algorithmic work of each kernel and the roofline that bounds it
@@ -494,7 +640,7 @@ def main():
                 "backsolve": ("hbm", info["bytes_backsolve"]), "gamma_dense": ("mfma", info["flops_dense"]),
                 "gamma_sparse": ("alu", info["flops_gamma_sparse"])}
     stages = {k: v for k, v in prof.items() if v["launches"]}
-    kernel_names = {"assemble": "k_assemble", "condense": "k_eliminate<256", "backsolve": "k_backsolve<256",
+    kernel_names = {"assemble": "k_assemble", "condense": "k_eliminate", "backsolve": "k_backsolve",
                     "gamma_dense": "k_dense",
                     "gamma_sparse": "k_gamma_snode" if info["gamma_supernodal"] else "k_eliminate<1024"}
     dom = max((k for k in stages if k in per_unit), key=lambda k: stages[k]["ms"])
@@ -519,42 +665,54 @@ def main():
             pk = HBM_PEAK if b == "hbm" else FP64_PEAK
             others[k] = {"bound": b, "avg_launch_ms": am, "frac": ach / pk}
 
-    cpu = None if args.no_cpu else run_cpu_baseline(args.cpu_budget)
+    cpu = None if args.no_cpu else run_cpu_baseline(WORKLOAD)
+    if warm:
+        ws_label = "learned warm start with rejection (cap calibrated on held-out chains)"
+        ws_cfg = "ran"
+    elif mlp is not None:
+        ws_label = "flat start: the learned warm start was trained, but its calibrated cap rejects every " \
+                   "prediction (cap -inf), so the network is not run"
+        ws_cfg = "network not run (cap -inf)"
+    else:
+        ws_label = "flat start (no warm start trained)"
+        ws_cfg = "not trained"
     out = {
         "metric": METRIC, "value": value, "unit": "snapshots/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "9241-bus/16049-branch synthetic grid, 32 areas, 64 snapshots per batch, "
-                               + ("learned warm start with rejection, " if warm else "flat start, ")
-                               + "continuous batching through 64 slots + hipGraph, sparse boundary solve",
+        "config": {"workload": f"{WORKLOAD_NAMES[WORKLOAD]}, 64 snapshots per batch, {args.steps} batches as one "
+                               "stream, pinned host measurements in and host states out (uploads and downloads "
+                               "overlapped with the iterations), continuous batching through 64 slots + "
+                               f"hipGraph, sparse boundary solve; {ws_label}",
                    "n_bus": g.n_bus, "n_branch": g.n_branch, "n_area": g.n_area, "snapshots": N_SNAP,
                    "n_meas": int(t.size), "n_gamma": info["n_gamma"], "tol": TOL, "max_iter": MAX_ITER,
-                   "warm_start": warm,
+                   "warm_start": ws_cfg,
                    "schedule": {"pipeline_groups": info["pipeline_groups"],
                                 "boundary_elimination": "supernodal" if info["gamma_supernodal"] else "levels",
                                 "boundary_subtree_groups": info["gamma_subtree_groups"],
                                 "boundary_dense_panel_columns": info["gamma_dense_panel"],
                                 "chosen_by": "autotuner"}},
         "gn_iters_per_s": tot_iters / dt, "all_converged": all_conv,
-        "warm_start": None if not warm else {"accepted_fraction": acc_frac, "training": train_info},
-        "stream_flat": {"value": n_stream / sdt, "unit": "snapshots/s", "ms_per_step": 1e3 * sdt / args.steps,
-                        "mean_iters": s_iters / n_stream, "all_converged": s_conv,
-                        "states_bitwise_equal_to_batched_flat": stream_same},
+        "warm_start": None if mlp is None else {"network_run": warm, "accepted_fraction": acc_frac,
+                                                "training": train_info},
+        "stream_device_resident": {"value": n_stream / ddt, "unit": "snapshots/s",
+                                   "ms_per_step": 1e3 * ddt / args.steps, "mean_iters": d_iters / n_stream,
+                                   "all_converged": d_conv, "host_states_bitwise_equal": host_same,
+                                   "states_bitwise_equal_to_batched_flat": stream_same,
+                                   "note": "measurements resident in HBM before the timer, states left in HBM"},
         "batched_warm": None if not warm else {
             "value": N_SNAP * args.steps / bdt, "unit": "snapshots/s", "ms_per_step": 1e3 * bdt / args.steps,
-            "mean_iters": b_iters / (N_SNAP * args.steps), "all_converged": b_conv,
-            "note": "each step a separate 64-snapshot batch: the batch iterates until its last snapshot converges"},
+            "mean_iters": b_iters / (N_SNAP * args.steps), "all_converged": b_conv},
         "batched_flat": {"value": N_SNAP * args.steps / fdt, "unit": "snapshots/s",
                          "ms_per_step": 1e3 * fdt / args.steps, "mean_iters": f_iters / (N_SNAP * args.steps),
-                         "gn_iters_per_s": f_iters / fdt, "all_converged": f_conv},
-        "batched_flat_host_buffers": {"value": N_SNAP * args.steps / hdt, "unit": "snapshots/s",
-                                      "ms_per_step": 1e3 * hdt / args.steps,
-                                      "note": "z uploaded and states downloaded (pageable host memory) "
-                                              "inside the timed region"},
-        "profiled_pass": {"value": N_SNAP * args.steps / pdt_prof, "unit": "snapshots/s",
-                          "note": "same steps, kernels launched directly with HIP events around each"},
-        "mean_iters": tot_iters / (N_SNAP * args.steps),
+                         "gn_iters_per_s": f_iters / fdt, "all_converged": f_conv,
+                         "note": "each step a separate 64-snapshot batch resident in HBM: the batch iterates "
+                                 "until its last snapshot converges"},
+        "profiled_pass": {"value": n_stream / pdt_prof, "unit": "snapshots/s",
+                          "note": "device-resident stream, kernels launched directly with HIP events around each"},
+        "mean_iters": tot_iters / n_stream,
         "plain": plain, "speedup_vs_plain": (value / plain["value"]) if plain else None,
+        "single_snapshot_c1_gpu": single,
         "stages_ms_per_step": {k: v["ms"] / args.steps for k, v in stages.items()},
         "roofline": roofline, "roofline_other_kernels": others, "cpu_baseline": cpu,
     }

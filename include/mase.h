@@ -193,7 +193,9 @@ int mase_set_state_dev(mase_ctx* ctx, const double* vm_dev, const double* va_dev
  * solve, scatter-back, interior recovery, x += dx.  max_abs_dx [n_snap]
  * (host, may be NULL) receives max_i |dx_i| of each snapshot (0 for frozen
  * snapshots).  Snapshots whose step is below the tolerance of the last
- * mase_solve (default 1e-6) are frozen afterwards.
+ * mase_solve (default 1e-6) are frozen afterwards.  A snapshot that hits a
+ * non-positive pivot is frozen without an update; the others are updated,
+ * max_abs_dx is written, and the call returns MASE_ERR_NOT_POSDEF.
  */
 int mase_gn_iter(mase_ctx* ctx, double* max_abs_dx);
 
@@ -202,7 +204,10 @@ int mase_gn_iter(mase_ctx* ctx, double* max_abs_dx);
  * max_iter iterations (the paper caps Gauss-Newton at 10, Section 5.1).
  * iters [n_snap] and converged [n_snap] (host, may be NULL) receive the
  * per-snapshot step count and flag.  Returns MASE_NOT_CONVERGED if any
- * snapshot did not converge.
+ * snapshot did not converge.  A snapshot whose G_ii^k or S_Gamma has a
+ * non-positive pivot is frozen at the state before that iteration (its
+ * converged flag is 0) while the others iterate on; the call then returns
+ * MASE_ERR_NOT_POSDEF with iters and converged written for every snapshot.
  */
 int mase_solve(mase_ctx* ctx, double tol, int32_t max_iter, int32_t* iters,
                int32_t* converged);
@@ -241,6 +246,31 @@ int mase_solve(mase_ctx* ctx, double tol, int32_t max_iter, int32_t* iters,
 int mase_solve_stream(mase_ctx* ctx, const double* z_dev, const double* vm0_dev, const double* va0_dev,
                       int64_t n_total, double tol, int32_t max_iter, double* vm_dev, double* va_dev,
                       int32_t* iters, int32_t* converged);
+
+/*
+ * mase_solve_stream with host buffers at both ends, the solve timed end to
+ * end as in Section 5.1 (measurements in, states out): z_host
+ * [n_total][n_meas] is uploaded in chunks of n_snap snapshots on a copy
+ * stream (default priority) ahead of the stream position, so the copies
+ * overlap the iterations of earlier snapshots, and the solved states go to
+ * vm_host, va_host [n_total][n_bus] chunk by chunk as soon as every snapshot
+ * of a chunk has left its slot.  vm0_host, va0_host [n_total][n_bus]: starting
+ * states, or both NULL for flat start.  Host buffers should be pinned
+ * (hipHostMalloc) for the copies to overlap; pageable memory is correct but
+ * serialises them.  work_dev: caller-owned device workspace of work_len
+ * doubles, at least mase_stream_host_work(ctx, n_total, vm0_host != NULL),
+ * that holds the device copies of z, the starting states and the results.
+ * iters, converged, arguments, return codes and results as in
+ * mase_solve_stream (bitwise equal states).  Host buffers must stay valid
+ * until the call returns.
+ */
+int mase_solve_stream_host(mase_ctx* ctx, const double* z_host, const double* vm0_host, const double* va0_host,
+                           int64_t n_total, double tol, int32_t max_iter, double* vm_host, double* va_host,
+                           int32_t* iters, int32_t* converged, double* work_dev, int64_t work_len);
+
+/* Doubles of device workspace mase_solve_stream_host needs for n_total
+ * snapshots (with_start != 0: starting states given); -1 on a bad argument. */
+int64_t mase_stream_host_work(const mase_ctx* ctx, int64_t n_total, int32_t with_start);
 
 /* Current state vm, va [n_snap][n_bus] (host / device). */
 int mase_state(mase_ctx* ctx, double* vm, double* va);
@@ -392,8 +422,11 @@ enum {
   MASE_INFO_GAMMA_SUBTREE_GROUPS, /* workgroups per snapshot of the supernodal boundary
                                      elimination: groups of independent elimination subtrees
                                      (the environment variable MASE_SNODE_GROUPS caps it) */
-  MASE_INFO_GAMMA_DENSE_PANEL     /* columns per LDS panel of the boundary system's dense block
+  MASE_INFO_GAMMA_DENSE_PANEL,    /* columns per LDS panel of the boundary system's dense block
                                      (0: panels read from HBM); the autotuner may change it */
+  MASE_INFO_AREA_LDS              /* areas whose elimination holds their packed storage in LDS (the
+                                     others run the level engine over HBM; the environment
+                                     variable MASE_AREA_LDS=0 selects it for all) */
 };
 int mase_info(const mase_ctx* ctx, int32_t what, int64_t* value);
 

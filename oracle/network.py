@@ -20,11 +20,11 @@ has n = 2N - 1 entries: the paper's PEGASE-2869 count 5737 = 2*2869 - 1
 (Section 5.2) fixes this reading.  Column order of H: theta of every non-slack
 bus in bus order, then |V| of every bus in bus order.
 
-Pins (tests/test_oracle_network.py): lossless-line closed forms and a hand-derived
-2-bus case (tests/golden/two_bus.json), the complex-power definition
-S = V conj(Y V) computed with complex arithmetic, Kirchhoff's current law
-(injection = sum of flows leaving the bus), finite-difference and
-complex-step Jacobians.
+Pins (tests/test_oracle_network.py): closed forms of a lossless 2-bus line
+(r = 0, b = 0: P_f = V_f V_t sin(theta_ft) / x and the matching Q_f, P_t, Q_t),
+the complex-power definition S = V conj(Y V) computed with complex arithmetic,
+Kirchhoff's current law (injection = sum of flows leaving the bus),
+finite-difference and complex-step Jacobians.
 """
 from __future__ import annotations
 

@@ -89,14 +89,21 @@ int upload_plan(mase_ctx* c) {
   std::vector<SysMeta> sm(K + 1);
   std::vector<AreaMeta> am(K);
   std::vector<int32_t> gbus, cd_ptr, up_ptr, rb_ptr, bs_ptr;
-  std::vector<I4> cd_items, up_tgt, rb_tgt, bs_items;
-  std::vector<I2> up_con, rb_con, bs_con;
+  std::vector<I4> cd_items, up_tgt, rb_tgt, bs_items, up_tgt_img;
+  std::vector<I2> up_con, rb_con, bs_con, up_con_img, rb_con_img;
+  // the areas' elimination runs in LDS when every area fits (MASE_AREA_LDS=0
+  // selects the level engine over HBM)
+  {
+    const char* env = getenv("MASE_AREA_LDS");
+    c->area_lds = p.lds_areas && !(env && env[0] == '0');
+  }
   for (int i = 0; i <= K; ++i) {
     const SysPlan& s = p.sys[i];
     SysMeta m{};
     m.nn = s.nn; m.ne = s.ne; m.nt = s.nt; m.ld = s.ld;
     m.tail_off = s.tail_off; m.nval = s.nval; m.pin_off = s.pin_off; m.nlev = s.nlev;
     m.val_off = p.val_off[i]; m.rhs_off = p.rhs_off[i];
+    m.asm_pin = s.pin_off;
     m.gbus = (int32_t)gbus.size();
     gbus.insert(gbus.end(), s.gbus.begin(), s.gbus.end());
     m.cd_ptr = (int32_t)cd_ptr.size();
@@ -109,7 +116,13 @@ int upload_plan(mase_ctx* c) {
       const int32_t base = (t.y & UP_SINGLE) ? 0 : (int32_t)up_con.size();
       up_tgt.push_back({t.x, t.y, t.z + base, t.w + base});
     }
+    for (const I4& t : s.up_tgt_img) {
+      const int32_t base = (t.y & UP_SINGLE) ? 0 : (int32_t)up_con_img.size();
+      up_tgt_img.push_back({t.x, t.y, t.z + base, t.w + base});
+    }
     up_con.insert(up_con.end(), s.up_con.begin(), s.up_con.end());
+    up_con_img.insert(up_con_img.end(), s.up_con_img.begin(), s.up_con_img.end());
+    rb_con_img.insert(rb_con_img.end(), s.rb_con_img.begin(), s.rb_con_img.end());
     m.rb_ptr = (int32_t)rb_ptr.size();
     append_rebased(rb_ptr, s.rb_ptr, (int32_t)rb_tgt.size());
     for (const I4& t : s.rb_tgt)
@@ -129,6 +142,7 @@ int upload_plan(mase_ctx* c) {
   std::vector<I4> rslot;
   std::vector<I4> scon, rcon;  // contributions with their row record inline
   std::vector<int32_t> slot_rhs;  // per slot: 2 v for the diagonal slot of bus v, else -1
+  std::vector<int32_t> cimg;      // per compact G block: its packed offset
   size_t lds = 0;
   for (int k = 0; k < K; ++k) {
     const AreaTemplates& t = p.tpl[k];
@@ -136,7 +150,8 @@ int upload_plan(mase_ctx* c) {
     a.nn = p.sys[k].nn;
     a.nbr = (int32_t)t.br_lf.size();
     a.nrow = (int32_t)t.row_type.size();
-    a.nslot = (int32_t)t.slot.size();
+    a.nslot = (c->area_lds && t.lds_split > 0) ? (int32_t)(t.cslot.size() + t.tslot.size())
+                                                : (int32_t)t.slot.size();
     a.br = (int32_t)br_lf.size();
     br_lf.insert(br_lf.end(), t.br_lf.begin(), t.br_lf.end());
     br_lt.insert(br_lt.end(), t.br_lt.begin(), t.br_lt.end());
@@ -152,22 +167,51 @@ int upload_plan(mase_ctx* c) {
     row_meas.insert(row_meas.end(), t.row_meas.begin(), t.row_meas.end());
     for (size_t r = 0; r < t.row_type.size(); ++r) rowrec.push_back({t.row_type[r], t.row_loc[r], t.row_meas[r], 0});
     // slots in order of decreasing contribution count, so that the lanes of
-    // a wave carry similar loads (each slot writes its own storage)
+    // a wave carry similar loads (each slot writes its own storage).  For the
+    // elimination in LDS the assembly writes the compact G blocks (offsets
+    // relative to the area's value base) and the Schur-block slots of an area
+    // that keeps that block in HBM; else every slot of the packed storage.
     a.slot = (int32_t)slot.size();
+    a.gc_rel = p.gc_off[k] - p.val_off[k];
+    a.n_cslot = 0;
+    a.cimg = (int32_t)cimg.size();
+    a.split = 0;
     {
-      std::vector<int> ord(t.slot.size());
+      std::vector<I4> src;      // slot records with final offsets
+      std::vector<int32_t> img; // packed offset of each
+      if (c->area_lds && t.lds_split > 0) {
+        for (size_t i = 0; i < t.cslot.size(); ++i) {
+          const I4& q = t.cslot[i];
+          src.push_back({q.x + a.gc_rel, q.y, q.z, q.w});
+          img.push_back(t.cimg[i]);
+          if (t.cimg[i] == p.sys[k].pin_off) sm[k].asm_pin = q.x + a.gc_rel;
+        }
+        for (const I4& q : t.tslot) {
+          src.push_back(q);
+          img.push_back(q.x);
+        }
+        a.n_cslot = (int32_t)t.cslot.size();
+        a.split = t.lds_split;
+        cimg.insert(cimg.end(), t.cimg.begin(), t.cimg.end());
+      } else {
+        for (const I4& q : t.slot) {
+          src.push_back(q);
+          img.push_back(q.x);
+        }
+      }
+      std::vector<int> ord(src.size());
       for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
       std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
-        return t.slot[x].w - t.slot[x].z > t.slot[y].w - t.slot[y].z;
+        return src[x].w - src[x].z > src[y].w - src[y].z;
       });
       // a diagonal slot (v, v) also yields b_v: its contributions with equal
       // roles are exactly bus v's rhs contributions, in the same order
       std::unordered_map<int32_t, int32_t> diag_bus;
       for (int v = 0; v < p.sys[k].nn; ++v) diag_bus[p.sys[k].blk_off(v, v)] = v;
       for (int i : ord) {
-        const I4& s = t.slot[i];
-        slot.push_back({s.x, s.y, s.z + (int32_t)scon.size(), s.w + (int32_t)scon.size()});
-        slot_rhs.push_back(s.y < 0 ? 2 * diag_bus.at(s.x) : -1);
+        const I4& q = src[i];
+        slot.push_back({q.x, q.y, q.z + (int32_t)scon.size(), q.w + (int32_t)scon.size()});
+        slot_rhs.push_back(q.y < 0 ? 2 * diag_bus.at(img[i]) : -1);
       }
     }
     for (const I2& cc : t.scon)
@@ -267,6 +311,46 @@ int upload_plan(mase_ctx* c) {
   d.vstride = p.vstride; d.rstride = p.rstride;
   int rc = 0;
 #define UP(field, vec) if ((rc = upload(c, vec, &d.field))) return rc
+  if (c->area_lds) {
+    // launch order: largest LDS need first; consecutive areas with the same
+    // workgroups per CU share a launch (the LDS size is per launch)
+    // areas that do not fit (split 0) come first and run the level engine
+    std::vector<int32_t>& ord = c->plan.area_order;
+    auto need = [&](int k) {
+      return am[k].split > 0 ? 8 * ((size_t)am[k].split + 2 * (size_t)p.sys[k].nn) : SIZE_MAX;
+    };
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return need(x) > need(y); });
+    const size_t per_cu = 8 * (size_t)AREA_LDS_DOUBLES;
+    const char* ntenv = getenv("MASE_ELIM_NT");
+    const int nt_force = ntenv ? atoi(ntenv) : 0;
+    size_t lds_max = 0;
+    int q = 0;
+    while (q < K && am[ord[q]].split == 0) ++q;
+    if (q > 0) c->el_class.push_back({0, q, 0, 0, false});
+    while (q < K) {
+      const int k0 = ord[q];
+      const size_t b0 = need(k0);
+      const int wpc = (int)std::min<size_t>(8, std::max<size_t>(1, per_cu / b0));
+      int r = q;
+      bool tail = false;
+      while (r < K && (int)std::min<size_t>(8, std::max<size_t>(1, per_cu / need(ord[r]))) == wpc) {
+        tail |= am[ord[r]].split < p.sys[ord[r]].nval;
+        ++r;
+      }
+      const int nt = (nt_force == 256 || nt_force == 512 || nt_force == 1024) ? nt_force
+                     : wpc == 1 ? 1024 : (wpc <= 4 ? 512 : 256);
+      c->el_class.push_back({q, r - q, b0, nt, tail});
+      lds_max = std::max(lds_max, b0);
+      q = r;
+    }
+
+    if (lds_max > (size_t)maxlds) {
+      c->el_class.clear();
+      c->area_lds = false;
+      return fail(MASE_ERR_ARG, "an area's elimination needs more LDS than the device allows");
+    }
+    if (lds_max > 65536) HIPTRY(allow_elim_lds(lds_max));
+  }
   UP(sys, sm); UP(area, am); UP(area_order, p.area_order); UP(gbus, gbus);
   UP(br_lf, br_lf); UP(br_lt, br_lt); UP(br_g, br_g); UP(br_bs, br_bs); UP(br_hb, br_hb);
   UP(inc_ptr, inc_ptr); UP(inc_end, inc_end);
@@ -275,6 +359,7 @@ int upload_plan(mase_ctx* c) {
   UP(cd_ptr, cd_ptr); UP(up_ptr, up_ptr); UP(rb_ptr, rb_ptr); UP(bs_ptr, bs_ptr);
   UP(cd_items, cd_items); UP(up_tgt, up_tgt); UP(up_con, up_con);
   UP(rb_tgt, rb_tgt); UP(rb_con, rb_con); UP(bs_items, bs_items); UP(bs_con, bs_con);
+  UP(up_tgt_img, up_tgt_img); UP(up_con_img, up_con_img); UP(rb_con_img, rb_con_img); UP(cimg, cimg);
   {
     const SysPlan& gs = p.sys[K];
     d.n_sn = (int32_t)gs.sn.size();
@@ -334,6 +419,10 @@ int upload_plan(mase_ctx* c) {
   c->h_iters = c->h_status + S * (K + 1);
   HIPTRY(hipHostMalloc((void**)&c->h_tol, sizeof(double), hipHostMallocDefault));
   c->h_tol[0] = 1e-6;
+  // stream solve: active flags and stream positions of two alternate passes
+  HIPTRY(hipHostMalloc((void**)&c->h_st_active, sizeof(int32_t) * (2 * (size_t)S + 4), hipHostMallocDefault));
+  c->h_st_pos = c->h_st_active + 2 * S;
+  for (auto& e : c->st_ev) HIPTRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   HIPTRY(hipMemcpy(c->dtol, c->h_tol, sizeof(double), hipMemcpyHostToDevice));
 
   if (c->lds_asm > (size_t)maxlds)
@@ -363,6 +452,22 @@ struct StageMark {
 
 bool snapshot_bad(const mase_ctx* c, int s);
 
+// The areas' elimination (stage 2) for the areas at positions [a0, a0 + na)
+// of area_order and snapshots [s0, s0 + ns): held in LDS class by class, or
+// the level engine over HBM.
+hipError_t launch_area_eliminate(const mase_ctx* c, int a0, int na, int s0, int ns, hipStream_t st) {
+  if (!c->area_lds) return launch_eliminate(c->d, a0, na, s0, ns, c->lds_el_area, st);
+  for (const auto& cl : c->el_class) {
+    const int lo = std::max(a0, cl.a0), hi = std::min(a0 + na, cl.a0 + cl.na);
+    if (lo >= hi) continue;
+    // nt 0: areas too large for LDS, on the level engine
+    const hipError_t e = cl.nt ? launch_elim_lds(c->d, lo, hi - lo, s0, ns, cl.lds, cl.nt, cl.tail_hbm, st)
+                               : launch_eliminate(c->d, lo, hi - lo, s0, ns, c->lds_el_area, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // Stages 1-2 (assembly, condensation) for snapshots [s0, s0 + ns), after
 // the iteration's local steps (Eq. 6: each area's internal variables take
 // GN steps with its boundary held; same kernels, dx_b = 0).
@@ -373,7 +478,7 @@ int launch_area_part(mase_ctx* c, hipStream_t st, int s0, int ns) {
     StageMark m(c, st, MASE_STAGE_LOCAL);
     for (int l = 0; l < c->opt.local_steps; ++l) {
       HIPTRY(launch_assemble(d, 0, K, s0, ns, MODE_ASSEMBLE, c->lds_asm, c->br_lds, st));
-      HIPTRY(launch_eliminate(d, 0, K, s0, ns, c->lds_el_area, st));
+      HIPTRY(launch_area_eliminate(c, 0, K, s0, ns, st));
       HIPTRY(launch_backsolve(d, 0, K, s0, ns, st, true));
       HIPTRY(launch_update(d, s0, ns, st, true));
     }
@@ -384,7 +489,7 @@ int launch_area_part(mase_ctx* c, hipStream_t st, int s0, int ns) {
   }
   {
     StageMark m(c, st, MASE_STAGE_CONDENSE);
-    HIPTRY(launch_eliminate(d, 0, K, s0, ns, c->lds_el_area, st));
+    HIPTRY(launch_area_eliminate(c, 0, K, s0, ns, st));
   }
   return 0;
 }
@@ -524,9 +629,9 @@ int pipelined_solve(mase_ctx* c, int max_iter) {
       if (done[g]) continue;
       HIPTRY(hipEventSynchronize(c->pev_b[g]));
       ++iters[g];
-      bool bad = false;
-      for (int s = c->pg_s0[g]; s < c->pg_s0[g + 1]; ++s) bad |= snapshot_bad(c, s);
-      if (bad || !group_active(g) || iters[g] >= max_iter) {
+      // a snapshot with a non-positive pivot is frozen (inactive) by the
+      // update kernel, so its group goes on with the others
+      if (!group_active(g) || iters[g] >= max_iter) {
         done[g] = 1;
         --pending;
         continue;
@@ -568,7 +673,7 @@ int launch_plain_iteration(mase_ctx* c, int s) {
   for (int ai = 0; ai < K; ++ai) {
     hipStream_t as = c->astreams[ai % ns];
     HIPTRY(launch_assemble(d, ai, 1, s, 1, MODE_ASSEMBLE, c->lds_asm, c->br_lds, as));
-    HIPTRY(launch_eliminate(d, ai, 1, s, 1, c->lds_el_area, as));
+    HIPTRY(launch_area_eliminate(c, ai, 1, s, 1, as));
   }
   for (int i = 0; i < ns; ++i) {
     HIPTRY(hipEventRecord(c->aevents[i], c->astreams[i]));
@@ -867,10 +972,16 @@ int mase_set_state_dev(mase_ctx* c, const double* vm_dev, const double* va_dev) 
   return 0;
 }
 
-int mase_gn_iter(mase_ctx* c, double* max_abs_dx) {
-  int rc = check_device(c);
-  if (rc) return rc;
-  if (!c->have_z) return fail(MASE_ERR_STATE, "no measurements set");
+}  // extern "C"
+
+namespace {
+
+// One batched (or plain) iteration for every active snapshot, flags read
+// back.  A snapshot that hits a non-positive pivot is frozen by k_update and
+// reported through its status flags only, so callers can keep iterating the
+// others.
+int gn_iter_all(mase_ctx* c) {
+  int rc = 0;
   const int S = c->plan.n_snap;
   int nactive_before = 0;
   for (int s = 0; s < S; ++s) nactive_before += c->h_active[s] != 0;
@@ -905,6 +1016,19 @@ int mase_gn_iter(mase_ctx* c, double* max_abs_dx) {
     }
     if ((rc = read_flags(c))) return rc;
   }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mase_gn_iter(mase_ctx* c, double* max_abs_dx) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  if (!c->have_z) return fail(MASE_ERR_STATE, "no measurements set");
+  if ((rc = gn_iter_all(c))) return rc;
+  const int S = c->plan.n_snap;
   if (max_abs_dx) std::memcpy(max_abs_dx, c->h_maxdx, sizeof(double) * S);
   for (int s = 0; s < S; ++s)
     if (snapshot_bad(c, s))
@@ -1015,8 +1139,10 @@ int solve_batched(mase_ctx* c, int max_iter) {
   if (c->opt.use_graph && !c->prof && c->npipe > 1) return pipelined_solve(c, max_iter);
   int nact = 0;
   for (int s = 0; s < S; ++s) nact += c->h_active[s] != 0;
+  // a snapshot with a non-positive pivot is frozen by the update kernel;
+  // the others keep iterating
   for (int it = 0; it < max_iter && nact > 0; ++it) {
-    if ((rc = mase_gn_iter(c, nullptr))) return rc;
+    if ((rc = gn_iter_all(c))) return rc;
     nact = 0;
     for (int s = 0; s < S; ++s) nact += c->h_active[s] != 0;
   }
@@ -1080,40 +1206,51 @@ int autotune(mase_ctx* c) {
   const bool snode0 = c->gamma_snode;
   double best = 1e300;
   int best_np = c->npipe, best_sn = snode0 ? 1 : 0;
-  std::pair<int, int> best_dense = dense_cands[0];
-  for (int snc = 1; snc >= 0; --snc) {
-    if (snc == 1 && !c->snode_possible) continue;
-    for (int npc : {1, 2, 4, 8}) {
-      if (npc > S) continue;
-      for (const auto& dc : dense_cands) {
-        if ((rc = reset_graphs(c))) return rc;
-        c->npipe = npc;
-        c->gamma_snode = snc == 1;
-        c->dense_mode = dc.first;
-        c->dense_nb = dc.second;
-        double t = 0.0;
-        for (int rep = 0; rep < 2; ++rep) {  // the first run captures the graphs
-          if ((rc = save_restore(false))) return rc;
-          const auto t0 = std::chrono::steady_clock::now();
-          if ((rc = solve_batched(c, 2))) return rc;
-          HIPTRY(hipStreamSynchronize(c->stream));
-          t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        }
-        if (t < best) {
-          best = t;
-          best_np = npc;
-          best_sn = snc;
-          best_dense = dc;
+  std::pair<int, int> best_dense{c->dense_mode, c->dense_nb};
+  // a snapshot with a non-positive pivot only freezes itself, so a failure
+  // here is a runtime error; the state and the schedule are restored on
+  // every exit
+  auto trials = [&]() -> int {
+    for (int snc = 1; snc >= 0; --snc) {
+      if (snc == 1 && !c->snode_possible) continue;
+      for (int npc : {1, 2, 4, 8}) {
+        if (npc > S) continue;
+        for (const auto& dc : dense_cands) {
+          int e = reset_graphs(c);
+          if (e) return e;
+          c->npipe = npc;
+          c->gamma_snode = snc == 1;
+          c->dense_mode = dc.first;
+          c->dense_nb = dc.second;
+          double t = 0.0;
+          for (int rep = 0; rep < 2; ++rep) {  // the first run captures the graphs
+            if ((e = save_restore(false))) return e;
+            const auto t0 = std::chrono::steady_clock::now();
+            if ((e = solve_batched(c, 2))) return e;
+            HIPTRY(hipStreamSynchronize(c->stream));
+            t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+          }
+          if (t < best) {
+            best = t;
+            best_np = npc;
+            best_sn = snc;
+            best_dense = dc;
+          }
         }
       }
     }
-  }
-  if ((rc = reset_graphs(c))) return rc;
+    return 0;
+  };
+  const int rc_trials = trials();
+  const std::string err_trials = rc_trials ? g_err : std::string();
+  rc = reset_graphs(c);
   c->npipe = best_np;
   c->gamma_snode = best_sn == 1;
   c->dense_mode = best_dense.first;
   c->dense_nb = best_dense.second;
-  if ((rc = save_restore(false))) return rc;
+  if (!rc) rc = save_restore(false);
+  if (rc_trials) return fail(rc_trials, err_trials);
+  if (rc) return rc;
   write_tune_cache(c, best_np, best_sn, best_dense.first, best_dense.second);
   return 0;
 }
@@ -1165,19 +1302,83 @@ int mase_solve(mase_ctx* c, double tol, int32_t max_iter, int32_t* iters, int32_
   return all ? MASE_OK : MASE_NOT_CONVERGED;
 }
 
-int mase_solve_stream(mase_ctx* c, const double* z_dev, const double* vm0_dev, const double* va0_dev,
-                      int64_t n_total, double tol, int32_t max_iter, double* vm_dev, double* va_dev,
-                      int32_t* iters, int32_t* converged) {
-  int rc = check_device(c);
-  if (rc) return rc;
-  if (!c->opt.batched) return fail(MASE_ERR_ARG, "the stream solve needs the batched schedule");
-  if (!(tol > 0.0) || max_iter < 1) return fail(MASE_ERR_ARG, "need tol > 0 and max_iter >= 1");
-  if (n_total < 0 || n_total > (int64_t(1) << 30)) return fail(MASE_ERR_ARG, "n_total must be in [0, 2^30]");
-  if ((vm0_dev == nullptr) != (va0_dev == nullptr)) return fail(MASE_ERR_ARG, "give both vm0 and va0 or neither");
-  if (n_total == 0) return MASE_OK;
-  if (!z_dev || !vm_dev || !va_dev) return fail(MASE_ERR_ARG, "null z or output");
+}  // extern "C"
+
+namespace {
+
+// Host-buffer ends of a stream solve: snapshots are uploaded chunk by chunk
+// on a copy stream ahead of the stream position, and downloaded chunk by
+// chunk once every snapshot of the chunk has left its slot.
+struct StreamHost {
+  const double* z_host = nullptr;   // [n_total][n_meas]
+  const double* vm0_host = nullptr; // [n_total][n_bus] or null (flat start)
+  const double* va0_host = nullptr;
+  double* vm_host = nullptr;        // [n_total][n_bus]
+  double* va_host = nullptr;
+  double* z_dev = nullptr;          // device copies (workspace)
+  double* vm0_dev = nullptr;
+  double* va0_dev = nullptr;
+  double* vm_dev = nullptr;
+  double* va_dev = nullptr;
+  hipStream_t cs = nullptr;         // copy stream (default priority)
+  std::vector<hipEvent_t> up_ev;    // per uploaded chunk
+  int64_t chunk = 64;
+  int64_t up_to = 0;                // snapshots whose upload is enqueued
+  int64_t down_to = 0;              // snapshots whose download is enqueued
+  int64_t n_total = 0;
+  int n_meas = 0, n_bus = 0;
+
+  ~StreamHost() {
+    for (auto e : up_ev) if (e) (void)hipEventDestroy(e);
+    if (cs) (void)hipStreamDestroy(cs);
+  }
+  // enqueue uploads of every chunk that starts below `need` (and a little
+  // ahead), then make `st` wait for the chunk that holds position need - 1
+  int ensure(int64_t need, hipStream_t st) {
+    need = std::min(need, n_total);
+    const int64_t ahead = std::min(n_total, need + 2 * chunk);
+    while (up_to < ahead) {
+      const int64_t n = std::min(chunk, n_total - up_to);
+      HIPTRY(hipMemcpyAsync(z_dev + up_to * n_meas, z_host + up_to * n_meas, sizeof(double) * n * n_meas,
+                            hipMemcpyHostToDevice, cs));
+      if (vm0_host) {
+        HIPTRY(hipMemcpyAsync(vm0_dev + up_to * n_bus, vm0_host + up_to * n_bus, sizeof(double) * n * n_bus,
+                              hipMemcpyHostToDevice, cs));
+        HIPTRY(hipMemcpyAsync(va0_dev + up_to * n_bus, va0_host + up_to * n_bus, sizeof(double) * n * n_bus,
+                              hipMemcpyHostToDevice, cs));
+      }
+      hipEvent_t e = nullptr;
+      HIPTRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      up_ev.push_back(e);
+      HIPTRY(hipEventRecord(e, cs));
+      up_to += n;
+    }
+    if (need > 0) HIPTRY(hipStreamWaitEvent(st, up_ev[(size_t)((need - 1) / chunk)], 0));
+    return 0;
+  }
+  // enqueue downloads of the chunks below `done` (whole chunks only unless
+  // done == n_total), after the work recorded in `ev`
+  int drain(int64_t done, hipEvent_t ev) {
+    int64_t upto = done >= n_total ? n_total : done / chunk * chunk;
+    if (upto <= down_to) return 0;
+    HIPTRY(hipStreamWaitEvent(cs, ev, 0));
+    const int64_t n = upto - down_to;
+    HIPTRY(hipMemcpyAsync(vm_host + down_to * n_bus, vm_dev + down_to * n_bus, sizeof(double) * n * n_bus,
+                          hipMemcpyDeviceToHost, cs));
+    HIPTRY(hipMemcpyAsync(va_host + down_to * n_bus, va_dev + down_to * n_bus, sizeof(double) * n * n_bus,
+                          hipMemcpyDeviceToHost, cs));
+    down_to = upto;
+    return 0;
+  }
+};
+
+// Continuous batching core (mase_solve_stream and its host-buffer variant).
+int stream_solve(mase_ctx* c, const double* z_dev, const double* vm0_dev, const double* va0_dev, int64_t n_total,
+                 double tol, int32_t max_iter, double* vm_dev, double* va_dev, int32_t* iters,
+                 int32_t* converged, StreamHost* io) {
   const int S = c->plan.n_snap;
-  if (!c->st_slots && (rc = dalloc(c, (size_t)3 * S + 1, &c->st_slots))) return rc;
+  int rc = 0;
+  if (!c->st_slots && (rc = dalloc(c, (size_t)3 * S + 2, &c->st_slots))) return rc;
   if (c->st_out_cap < n_total) {
     if (c->st_out) HIPTRY(hipFree(c->st_out));
     c->st_out = nullptr;
@@ -1191,7 +1392,7 @@ int mase_solve_stream(mase_ctx* c, const double* z_dev, const double* vm0_dev, c
   int32_t* slot_id = c->st_slots;
   int32_t* retire = slot_id + S;
   int32_t* refill = retire + S;
-  int32_t* next = refill + S;
+  int32_t* next = refill + S;  // [0] stream position, [1] lowest position still in a slot
   int32_t* out_iters = c->st_out;
   int32_t* out_flag = c->st_out + n_total;
   const int32_t nt = (int32_t)n_total;
@@ -1199,11 +1400,13 @@ int mase_solve_stream(mase_ctx* c, const double* z_dev, const double* vm0_dev, c
   HIPTRY(hipMemcpyAsync(c->dtol, c->h_tol, sizeof(double), hipMemcpyHostToDevice, c->stream));
   // every slot idle, then the first refill loads the first n_snap snapshots
   HIPTRY(hipMemsetAsync(slot_id, 0xff, sizeof(int32_t) * S, c->stream));
-  HIPTRY(hipMemsetAsync(next, 0, sizeof(int32_t), c->stream));
+  HIPTRY(hipMemsetAsync(next, 0, sizeof(int32_t) * 2, c->stream));
   // weights: those of the last mase_set_measurements call, else 1/sigma^2
   if (!c->have_z)
     HIPTRY(hipMemcpyAsync((void*)c->d.w, c->w_default, sizeof(double) * c->plan.n_meas, hipMemcpyDeviceToDevice,
                           c->stream));
+  // the first refill hands out positions [0, S), the first pass up to 2 S
+  if (io && (rc = io->ensure(2 * (int64_t)S, c->stream))) return rc;
   HIPTRY(launch_stream_refill(c->d, slot_id, next, retire, refill, out_iters, out_flag, nt, max_iter, c->stream));
   HIPTRY(launch_stream_copy(c->d, retire, refill, z_dev, vm0_dev, va0_dev, vm_dev, va_dev, c->stream));
   if ((rc = read_flags(c))) return rc;
@@ -1214,6 +1417,7 @@ int mase_solve_stream(mase_ctx* c, const double* z_dev, const double* vm0_dev, c
   // n_total * max_iter snapshot-iterations; after the last one has entered,
   // at most max_iter passes remain
   const int64_t limit = (n_total * max_iter + S - 1) / S + max_iter + 1;
+  int32_t* hpos = c->h_st_pos;  // [2][2] pinned: next[0..1] of alternate passes
   auto launch_pass = [&]() -> int {
     if (c->opt.use_graph && !c->prof) {
       if (!c->gexec) {
@@ -1241,22 +1445,21 @@ int mase_solve_stream(mase_ctx* c, const double* z_dev, const double* vm0_dev, c
     for (int s = 0; s < S; ++s) n += a[s] != 0;
     return n;
   };
+  int64_t known_next = S;  // stream position after the last pass whose flags were read
   if (c->opt.use_graph && !c->prof) {
     // one pass always queued ahead: pass j + 1 is enqueued before the host
     // waits for the active flags of pass j (two pinned flag buffers, two
     // events), so the device never idles on the host's turnaround. A pass
     // enqueued after the stream has drained finds every slot idle and
     // changes nothing.
-    if (!c->h_st_active) {
-      void* hp = nullptr;
-      HIPTRY(hipHostMalloc(&hp, sizeof(int32_t) * 2 * (size_t)S, hipHostMallocDefault));
-      c->h_st_active = static_cast<int32_t*>(hp);
-      for (auto& e : c->st_ev) HIPTRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    }
     auto enqueue = [&](int64_t j) -> int {
+      // passes j - 1 and j may hand out up to 2 S positions past the last known one
+      if (io && (rc = io->ensure(known_next + 2 * (int64_t)S, c->stream))) return rc;
       if ((rc = launch_pass())) return rc;
       HIPTRY(hipMemcpyAsync(c->h_st_active + (j & 1) * S, c->d.active, sizeof(int32_t) * S, hipMemcpyDeviceToHost,
                             c->stream));
+      if (io)
+        HIPTRY(hipMemcpyAsync(hpos + 2 * (j & 1), next, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, c->stream));
       HIPTRY(hipEventRecord(c->st_ev[j & 1], c->stream));
       return 0;
     };
@@ -1269,6 +1472,10 @@ int mase_solve_stream(mase_ctx* c, const double* z_dev, const double* vm0_dev, c
         }
         if ((rc = enqueue(j + 1))) return rc;
         HIPTRY(hipEventSynchronize(c->st_ev[j & 1]));
+        if (io) {
+          known_next = hpos[2 * (j & 1)];
+          if ((rc = io->drain(hpos[2 * (j & 1) + 1], c->st_ev[j & 1]))) return rc;
+        }
         if (count_active(c->h_st_active + (j & 1) * S) == 0) break;
       }
     }
@@ -1279,26 +1486,115 @@ int mase_solve_stream(mase_ctx* c, const double* z_dev, const double* vm0_dev, c
       const int nact = count_active(c->h_active);
       if (nact == 0) break;
       if (++pass > limit) return fail(MASE_ERR_STATE, "stream solve did not drain");
+      if (io && (rc = io->ensure(known_next + (int64_t)S, c->stream))) return rc;
       if ((rc = launch_pass())) return rc;
       if ((rc = read_flags(c))) return rc;
       if ((rc = accumulate_profile(c, nact))) return rc;
+      if (io) {
+        HIPTRY(hipMemcpy(hpos, next, sizeof(int32_t) * 2, hipMemcpyDeviceToHost));
+        known_next = hpos[0];
+        HIPTRY(hipEventRecord(c->st_ev[0], c->stream));
+        if ((rc = io->drain(hpos[1], c->st_ev[0]))) return rc;
+      }
     }
   }
-  std::vector<int32_t> h((size_t)2 * n_total);
-  HIPTRY(hipMemcpyAsync(h.data(), out_iters, sizeof(int32_t) * n_total, hipMemcpyDeviceToHost, c->stream));
-  HIPTRY(hipMemcpyAsync(h.data() + n_total, out_flag, sizeof(int32_t) * n_total, hipMemcpyDeviceToHost,
-                        c->stream));
+  if (io) {
+    HIPTRY(hipEventRecord(c->st_ev[0], c->stream));
+    if ((rc = io->drain(n_total, c->st_ev[0]))) return rc;
+  }
+  // per-snapshot results straight into the caller's arrays (converged holds
+  // the outcome codes until they are turned into flags below)
+  std::vector<int32_t> hflag;
+  int32_t* flags = converged;
+  if (!flags) {
+    hflag.resize((size_t)n_total);
+    flags = hflag.data();
+  }
+  if (iters) HIPTRY(hipMemcpyAsync(iters, out_iters, sizeof(int32_t) * n_total, hipMemcpyDeviceToHost, c->stream));
+  HIPTRY(hipMemcpyAsync(flags, out_flag, sizeof(int32_t) * n_total, hipMemcpyDeviceToHost, c->stream));
   HIPTRY(hipStreamSynchronize(c->stream));
+  if (io) HIPTRY(hipStreamSynchronize(io->cs));
   bool all = true, bad = false;
   for (int64_t i = 0; i < n_total; ++i) {
-    const int32_t f = h[(size_t)(n_total + i)];
+    const int32_t f = flags[i];
     bad |= f == 2;
     all &= f == 1;
-    if (iters) iters[i] = h[(size_t)i];
-    if (converged) converged[i] = f == 1 ? 1 : 0;
+    flags[i] = f == 1 ? 1 : 0;
   }
   if (bad) return fail(MASE_ERR_NOT_POSDEF, "a snapshot of the stream hit a non-positive pivot");
   return all ? MASE_OK : MASE_NOT_CONVERGED;
+}
+
+int stream_args(const mase_ctx* c, int64_t n_total, double tol, int32_t max_iter, const void* vm0, const void* va0) {
+  if (!c->opt.batched) return fail(MASE_ERR_ARG, "the stream solve needs the batched schedule");
+  if (!(tol > 0.0) || max_iter < 1) return fail(MASE_ERR_ARG, "need tol > 0 and max_iter >= 1");
+  if (n_total < 0 || n_total > (int64_t(1) << 30)) return fail(MASE_ERR_ARG, "n_total must be in [0, 2^30]");
+  if ((vm0 == nullptr) != (va0 == nullptr)) return fail(MASE_ERR_ARG, "give both vm0 and va0 or neither");
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mase_solve_stream(mase_ctx* c, const double* z_dev, const double* vm0_dev, const double* va0_dev,
+                      int64_t n_total, double tol, int32_t max_iter, double* vm_dev, double* va_dev,
+                      int32_t* iters, int32_t* converged) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  if ((rc = stream_args(c, n_total, tol, max_iter, vm0_dev, va0_dev))) return rc;
+  if (n_total == 0) return MASE_OK;
+  if (!z_dev || !vm_dev || !va_dev) return fail(MASE_ERR_ARG, "null z or output");
+  return stream_solve(c, z_dev, vm0_dev, va0_dev, n_total, tol, max_iter, vm_dev, va_dev, iters, converged,
+                      nullptr);
+}
+
+int64_t mase_stream_host_work(const mase_ctx* c, int64_t n_total, int32_t with_start) {
+  if (!c || n_total < 0) return -1;
+  const int64_t per = (int64_t)c->plan.n_meas + 2 * (int64_t)c->plan.n_bus * (with_start ? 2 : 1);
+  return per * n_total;
+}
+
+int mase_solve_stream_host(mase_ctx* c, const double* z_host, const double* vm0_host, const double* va0_host,
+                           int64_t n_total, double tol, int32_t max_iter, double* vm_host, double* va_host,
+                           int32_t* iters, int32_t* converged, double* work_dev, int64_t work_len) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  if ((rc = stream_args(c, n_total, tol, max_iter, vm0_host, va0_host))) return rc;
+  if (n_total == 0) return MASE_OK;
+  if (!z_host || !vm_host || !va_host || !work_dev) return fail(MASE_ERR_ARG, "null z, output or workspace");
+  if (work_len < mase_stream_host_work(c, n_total, vm0_host ? 1 : 0))
+    return fail(MASE_ERR_ARG, "workspace smaller than mase_stream_host_work()");
+  StreamHost io;
+  io.n_total = n_total;
+  io.n_meas = c->plan.n_meas;
+  io.n_bus = c->plan.n_bus;
+  io.chunk = std::max<int64_t>(1, c->plan.n_snap);
+  io.z_host = z_host;
+  io.vm0_host = vm0_host;
+  io.va0_host = va0_host;
+  io.vm_host = vm_host;
+  io.va_host = va_host;
+  double* w = work_dev;
+  io.z_dev = w;
+  w += n_total * (int64_t)io.n_meas;
+  io.vm_dev = w;
+  w += n_total * (int64_t)io.n_bus;
+  io.va_dev = w;
+  w += n_total * (int64_t)io.n_bus;
+  if (vm0_host) {
+    io.vm0_dev = w;
+    w += n_total * (int64_t)io.n_bus;
+    io.va0_dev = w;
+  }
+  HIPTRY(hipStreamCreateWithFlags(&io.cs, hipStreamNonBlocking));
+  // the copy stream starts after everything queued so far on the context's stream
+  HIPTRY(hipEventRecord(c->ev_main, c->stream));
+  HIPTRY(hipStreamWaitEvent(io.cs, c->ev_main, 0));
+  rc = stream_solve(c, io.z_dev, io.vm0_dev, io.va0_dev, n_total, tol, max_iter, io.vm_dev, io.va_dev, iters,
+                    converged, &io);
+  (void)hipStreamSynchronize(io.cs);
+  return rc;
 }
 
 int mase_state(mase_ctx* c, double* vm, double* va) {
@@ -1392,7 +1688,7 @@ int mase_info(const mase_ctx* c, int32_t what, int64_t* value) {
     case MASE_INFO_BYTES_ASSEMBLY: v = (int64_t)p.bytes_assembly(); break;
     case MASE_INFO_N_SNAP: v = p.n_snap; break;
     case MASE_INFO_N_AREA: v = p.n_area; break;
-    case MASE_INFO_BYTES_CONDENSE: v = (int64_t)p.bytes_condense(); break;
+    case MASE_INFO_BYTES_CONDENSE: v = (int64_t)p.bytes_condense(c->area_lds); break;
     case MASE_INFO_FLOPS_DENSE: v = (int64_t)p.flops_dense(); break;
     case MASE_INFO_BYTES_BACKSOLVE: v = (int64_t)p.bytes_backsolve(); break;
     case MASE_INFO_FLOPS_GAMMA_SPARSE: v = (int64_t)p.sys[p.n_area].elim_flops(); break;
@@ -1403,6 +1699,13 @@ int mase_info(const mase_ctx* c, int32_t what, int64_t* value) {
     case MASE_INFO_GAMMA_SUBTREE_GROUPS: v = c->d.n_sn_grp; break;
     case MASE_INFO_GAMMA_DENSE_PANEL: v = c->dense_mode == DENSE_WIDE ? c->dense_nb
                                         : c->dense_mode == DENSE_PANEL16 ? 16 : 0; break;
+    case MASE_INFO_AREA_LDS: {
+      int n = 0;
+      if (c->area_lds)
+        for (int k = 0; k < p.n_area; ++k) n += p.tpl[k].lds_split > 0;
+      v = n;
+      break;
+    }
     default: return fail(MASE_ERR_ARG, "unknown info key");
   }
   *value = v;
@@ -1456,7 +1759,7 @@ int mase_stage_assemble(mase_ctx* c) {
 int mase_stage_condense(mase_ctx* c) {
   int rc = check_device(c);
   if (rc) return rc;
-  HIPTRY(launch_eliminate(c->d, 0, c->plan.n_area, 0, c->plan.n_snap, c->lds_el_area, c->stream));
+  HIPTRY(launch_area_eliminate(c, 0, c->plan.n_area, 0, c->plan.n_snap, c->stream));
   HIPTRY(hipStreamSynchronize(c->stream));
   return 0;
 }
@@ -1508,6 +1811,18 @@ int mase_read_local_system(mase_ctx* c, int32_t snap, int32_t area, double* G, d
                    sizeof(double) * s.nval, hipMemcpyDeviceToHost));
   HIPTRY(hipMemcpy(rhs.data(), c->d.rhs + (size_t)snap * p.rstride + p.rhs_off[area],
                    sizeof(double) * rhs.size(), hipMemcpyDeviceToHost));
+  if (c->area_lds && p.tpl[area].lds_split > 0) {
+    // the assembly wrote the compact blocks below the LDS split (fill
+    // positions there are zero) and the packed storage above it
+    const AreaTemplates& t = p.tpl[area];
+    std::vector<double> gc(4 * t.cimg.size() + 1);
+    if (!t.cimg.empty())
+      HIPTRY(hipMemcpy(gc.data(), c->d.vals + (size_t)snap * p.vstride + p.gc_off[area],
+                       sizeof(double) * 4 * t.cimg.size(), hipMemcpyDeviceToHost));
+    std::fill(vals.begin(), vals.begin() + t.lds_split, 0.0);
+    for (size_t i = 0; i < t.cimg.size(); ++i)
+      for (int e = 0; e < 4; ++e) vals[(size_t)t.cimg[i] + e] = gc[4 * i + e];
+  }
   const std::vector<int32_t> ci = canon_index(p, area);
   int dim = 0;
   for (int32_t v : ci) dim += v >= 0;

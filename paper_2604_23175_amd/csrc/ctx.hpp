@@ -29,6 +29,12 @@ struct mase_ctx {
   size_t lds_asm = 0;
   bool br_lds = false;
   size_t lds_el_area = 0, lds_el_gamma = 0;  // elimination staging LDS bytes
+  // the areas' elimination held in LDS: launch classes over runs of
+  // area_order positions with the same workgroups per CU (LDS bytes of the
+  // largest area in the run, threads per workgroup, Schur block in HBM)
+  bool area_lds = false;
+  struct ElClass { int a0, na; size_t lds; int nt; bool tail_hbm; };
+  std::vector<ElClass> el_class;
   int dense_mode = 0;                         // DENSE_GLOBAL / DENSE_PANEL16 / DENSE_WIDE
   int dense_nb = 16;                          // panel width of DENSE_WIDE
   bool gamma_snode = false;                   // supernodal boundary elimination
@@ -64,6 +70,7 @@ struct mase_ctx {
   int32_t* st_out = nullptr;
   int64_t st_out_cap = 0;
   int32_t* h_st_active = nullptr;  // [2][n_snap] pinned: active flags of alternate passes
+  int32_t* h_st_pos = nullptr;     // [2][2] pinned: stream position, lowest position in a slot
   hipEvent_t st_ev[2] = {};
   // per-stage timing
   bool prof = false;

@@ -16,7 +16,7 @@ struct SysMeta {
   int32_t val_off, rhs_off;       // offsets inside one snapshot's value / rhs block
   int32_t cd_ptr, up_ptr, rb_ptr, bs_ptr;  // first entry of this system's level pointers
   int32_t gbus;                   // first entry of local->global bus map
-  int32_t pad;
+  int32_t asm_pin;                // offset the assembly writes the pinned slack block to, or -1
 };
 
 // Per area templates (Section 4.1).
@@ -25,6 +25,9 @@ struct AreaMeta {
   int32_t br, inc_ptr, row, slot;  // first entries in the flattened arrays
   int32_t rslot, tail_src, slack_local;
   int32_t stage_off;  // doubles: this area's region in a snapshot's assembly staging (global mode)
+  // elimination in LDS: compact G at val_off + gc_rel (n_cslot blocks, their
+  // packed offsets from cimg), packed storage [0, split) held in LDS
+  int32_t gc_rel, n_cslot, cimg, split;
 };
 
 enum { MODE_ASSEMBLE = 0, MODE_OBJECTIVE = 1, MODE_EVAL_H = 2 };
@@ -57,6 +60,11 @@ struct Dev {
   const int2* rb_con;
   const int4* bs_items;
   const int2* bs_con;
+  // the same update / rhs lists addressed by packed offsets (elimination in LDS)
+  const int4* up_tgt_img;
+  const int2* up_con_img;
+  const int2* rb_con_img;
+  const int32_t* cimg;   // per compact G block: its packed offset
   // supernodes of the boundary system (the plan's sn, sn2, sn_rows, sn_tgt)
   int32_t n_sn;
   const int4* sn;

@@ -428,7 +428,7 @@ __global__ void __launch_bounds__(ASM_NT) k_assemble(Dev d, int a0, int na, int 
     const bool diag = sl.y < 0;
     const int stride = diag ? -sl.y : sl.y;
     if (diag) c01 = c10;
-    if (sl.x == sm.pin_off) { c00 = 1.0; c10 = 0.0; c01 = 0.0; }
+    if (sl.x == sm.asm_pin) { c00 = 1.0; c10 = 0.0; c01 = 0.0; }
     double* o = vals + sl.x;
     o[0] = c00;
     o[1] = c10;
@@ -598,6 +598,131 @@ __global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int
   }
   if (RL)
     for (int i = tid; i < 2 * sm.nn; i += NT) rhs_g[i] = rhs[i];
+  if (bad) d.status[(int64_t)s * (d.n_area + 1) + k] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// Stage 2 with the area held in LDS.  One workgroup per area x snapshot
+// keeps the area's packed storage [0, split) and its rhs in LDS for the whole
+// elimination: it zeroes the image, drops in the compact G blocks the
+// assembly wrote (fill positions stay zero), runs the same level schedule as
+// k_eliminate with every factor block, pivot and update in LDS, and writes the
+// storage back once (the factor for the back substitution, S_b^k for the
+// boundary assembly).  HBM sees G read once and L written once instead of a
+// read-modify-write round trip per level.  With TAIL_HBM the area does not
+// fit whole: its Schur block [split, nval) stays in HBM, already assembled
+// there, and only the updates that land in it go to HBM.  The arithmetic and
+// its order are those of k_eliminate, so results are bitwise the same.
+// ---------------------------------------------------------------------------
+template <int NT, bool TAIL_HBM>
+__global__ void __launch_bounds__(NT) k_elim_lds(Dev d, int a0, int na, int s0, int ns) {
+  int ai, s;
+  area_snap_of_block(blockIdx.x, na, ns, ai, s);
+  s += s0;
+  if (!d.active[s]) return;
+  const int k = d.area_order[a0 + ai];
+  const SysMeta sm = d.sys[k];
+  const AreaMeta am = d.area[k];
+  double* vals = d.vals + (int64_t)s * d.vstride + sm.val_off;
+  double* rhs_g = d.rhs + (int64_t)s * d.rstride + sm.rhs_off;
+  extern __shared__ double2 lds2[];
+  double* img = reinterpret_cast<double*>(lds2);
+  const int split = am.split;  // a multiple of 4
+  double* rhs = img + split;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < split / 2; i += NT) lds2[i] = make_double2(0.0, 0.0);
+  for (int i = tid; i < sm.nn; i += NT)
+    reinterpret_cast<double2*>(rhs)[i] = reinterpret_cast<const double2*>(rhs_g)[i];
+  __syncthreads();
+  {
+    const double2* gc = reinterpret_cast<const double2*>(vals + am.gc_rel);
+    const int32_t* cimg = d.cimg + am.cimg;
+    for (int i = tid; i < am.n_cslot; i += NT) {
+      const double2 lo = gc[2 * i], hi = gc[2 * i + 1];
+      double2* dst = reinterpret_cast<double2*>(img + cimg[i]);
+      dst[0] = lo;
+      dst[1] = hi;
+    }
+  }
+  __syncthreads();
+  bool bad = false;
+  const int32_t* cdp = d.cd_ptr + sm.cd_ptr;
+  const int32_t* upp = d.up_ptr + sm.up_ptr;
+  const int32_t* rbp = d.rb_ptr + sm.rb_ptr;
+  for (int lev = 0; lev < sm.nlev; ++lev) {
+    const int c0 = cdp[lev], c1 = cdp[lev + 1];
+    const int u0 = upp[lev], u1 = upp[lev + 1];
+    const int r0 = rbp[lev], r1 = rbp[lev + 1];
+    for (int it = c0 + tid; it < c1; it += NT) {
+      const int4 c = d.cd_items[it];
+      const double* D = img + c.x;
+      double l00, l10, l11, i00, i11;
+      if (!chol2(D[0], D[1], D[3], l00, l10, l11, i00, i11)) {
+        bad = true;
+        l00 = l11 = i00 = i11 = 1.0;
+        l10 = 0.0;
+      }
+      if (c.y < 0) {
+        const double y0 = rhs[c.z] * i00;
+        const double y1 = (rhs[c.z + 1] - l10 * y0) * i11;
+        rhs[c.z] = y0;
+        rhs[c.z + 1] = y1;
+      } else {
+        double2* M = reinterpret_cast<double2*>(img + c.y);  // X L^T = M
+        const double2 m0 = M[0], m1 = M[1];
+        const double x00 = m0.x * i00, x10 = m0.y * i00;
+        const double x01 = (m1.x - x00 * l10) * i11, x11 = (m1.y - x10 * l10) * i11;
+        M[0] = make_double2(x00, x10);
+        M[1] = make_double2(x01, x11);
+      }
+    }
+    __syncthreads();
+    for (int it = u0 + tid; it < u1; it += NT) {
+      const int4 t = d.up_tgt_img[it];
+      const bool single = (t.y & UP_SINGLE_FLAG) != 0;
+      const int stride = t.y & ~UP_SINGLE_FLAG;
+      const int cb = single ? 0 : t.z, ce = single ? 1 : t.w;
+      double a00 = 0, a10 = 0, a01 = 0, a11 = 0;
+      bool sym = false;
+      for (int c = cb; c < ce; ++c) {
+        const int2 u = single ? make_int2(t.z, t.w) : d.up_con_img[c];
+        const double2 L0 = *reinterpret_cast<const double2*>(img + u.x);
+        const double2 L1 = *reinterpret_cast<const double2*>(img + u.x + 2);
+        const double2 P0 = *reinterpret_cast<const double2*>(img + u.y);
+        const double2 P1 = *reinterpret_cast<const double2*>(img + u.y + 2);
+        a00 += L0.x * P0.x + L1.x * P1.x;
+        a10 += L0.y * P0.x + L1.y * P1.x;
+        a01 += L0.x * P0.y + L1.x * P1.y;
+        a11 += L0.y * P0.y + L1.y * P1.y;
+        sym = (u.x == u.y);
+      }
+      if (sym) a01 = a10;
+      double* C = (!TAIL_HBM || t.x < split) ? img + t.x : vals + t.x;
+      const double c00 = C[0], c10 = C[1], c01 = C[stride], c11 = C[stride + 1];
+      C[0] = c00 - a00;
+      C[1] = c10 - a10;
+      C[stride] = c01 - a01;
+      C[stride + 1] = c11 - a11;
+    }
+    for (int it = r0 + tid; it < r1; it += NT) {
+      const int4 t = d.rb_tgt[it];
+      double b0 = 0, b1 = 0;
+      for (int c = t.y; c < t.z; ++c) {
+        const int2 u = d.rb_con_img[c];
+        const double* L = img + u.x;
+        const double y0 = rhs[u.y], y1 = rhs[u.y + 1];
+        b0 += L[0] * y0 + L[2] * y1;
+        b1 += L[1] * y0 + L[3] * y1;
+      }
+      rhs[t.x] -= b0;
+      rhs[t.x + 1] -= b1;
+    }
+    __syncthreads();
+  }
+  double2* v2 = reinterpret_cast<double2*>(vals);
+  for (int i = tid; i < split / 2; i += NT) v2[i] = lds2[i];
+  for (int i = tid; i < sm.nn; i += NT)
+    reinterpret_cast<double2*>(rhs_g)[i] = reinterpret_cast<const double2*>(rhs)[i];
   if (bad) d.status[(int64_t)s * (d.n_area + 1) + k] = 1;
 }
 
@@ -1576,21 +1701,26 @@ __global__ void k_reset_flags(Dev d) {
 // the stream in slot order (a prefix count, so the assignment is
 // deterministic) and start them with cleared flags, or go idle once the
 // stream is exhausted. retire[s] / refill[s] tell k_stream_copy which
-// snapshot leaves and which enters slot s (-1: none).
+// snapshot leaves and which enters slot s (-1: none). next[0] is the stream
+// position; next[1] receives the lowest stream position still in a slot
+// (next[0] when every slot is idle): every earlier snapshot has left.
 __global__ void __launch_bounds__(256) k_stream_refill(Dev d, int32_t* slot_id, int32_t* next,
                                                        int32_t* retire, int32_t* refill, int32_t* out_iters,
                                                        int32_t* out_flag, int32_t n_total, int32_t max_iter) {
   __shared__ int cnt[4];
   __shared__ int base;
+  __shared__ int lows[4];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int K1 = d.n_area + 1;
+  int low = 0x7fffffff;
   if (tid == 0) base = *next;
   __syncthreads();
   for (int c0 = 0; c0 < d.n_snap; c0 += 256) {
     const int s = c0 + tid;
-    int want = 0, leaving = -1;
+    int want = 0, leaving = -1, keep = -1;
     if (s < d.n_snap) {
       const int id = slot_id[s];
+      keep = id;
       if (id < 0) {
         want = 1;
       } else {
@@ -1616,6 +1746,7 @@ __global__ void __launch_bounds__(256) k_stream_refill(Dev d, int32_t* slot_id, 
       if (want) {
         const bool take = rank < n_total;
         entering = take ? rank : -1;
+        keep = entering;
         slot_id[s] = entering;
         d.active[s] = take ? 1 : 0;
         d.iters[s] = 0;
@@ -1623,12 +1754,21 @@ __global__ void __launch_bounds__(256) k_stream_refill(Dev d, int32_t* slot_id, 
         for (int k = 0; k < K1; ++k) d.status[(int64_t)s * K1 + k] = 0;
       }
       refill[s] = entering;
+      if (keep >= 0 && keep < low) low = keep;
     }
     __syncthreads();
     if (tid == 0) base += cnt[0] + cnt[1] + cnt[2] + cnt[3];
     __syncthreads();
   }
-  if (tid == 0) *next = base < n_total ? base : n_total;
+  for (int off = 32; off > 0; off >>= 1) low = min(low, __shfl_down(low, off, 64));
+  if (lane == 0) lows[wv] = low;
+  __syncthreads();
+  if (tid == 0) {
+    const int nx = base < n_total ? base : n_total;
+    const int lo = min(min(lows[0], lows[1]), min(lows[2], lows[3]));
+    next[0] = nx;
+    next[1] = lo < nx ? lo : nx;
+  }
 }
 
 // Grid (chunks, n_snap). Slot s hands the state of its finished snapshot to
@@ -1709,6 +1849,39 @@ hipError_t launch_eliminate(const Dev& d, int sys0, int nsys, int s0, int ns, si
       hipLaunchKernelGGL((k_eliminate<AREA_NT, false>), grid, dim3(AREA_NT), bytes, st, d, sys0, nsys, s0, ns, lstride);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_elim_lds(const Dev& d, int a0, int na, int s0, int ns, size_t lds, int nt, bool tail_hbm,
+                           hipStream_t st) {
+  if (na <= 0 || ns <= 0) return hipSuccess;
+  const dim3 grid(na * ns);
+#define ELIM_LDS_CASE(N)                                                                              \
+  if (nt == N) {                                                                                      \
+    if (tail_hbm)                                                                                     \
+      hipLaunchKernelGGL((k_elim_lds<N, true>), grid, dim3(N), lds, st, d, a0, na, s0, ns);           \
+    else                                                                                              \
+      hipLaunchKernelGGL((k_elim_lds<N, false>), grid, dim3(N), lds, st, d, a0, na, s0, ns);          \
+    return hipGetLastError();                                                                         \
+  }
+  ELIM_LDS_CASE(256)
+  ELIM_LDS_CASE(512)
+  ELIM_LDS_CASE(1024)
+#undef ELIM_LDS_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t allow_elim_lds(size_t bytes) {
+  const void* f[6] = {reinterpret_cast<const void*>(&k_elim_lds<256, false>),
+                      reinterpret_cast<const void*>(&k_elim_lds<256, true>),
+                      reinterpret_cast<const void*>(&k_elim_lds<512, false>),
+                      reinterpret_cast<const void*>(&k_elim_lds<512, true>),
+                      reinterpret_cast<const void*>(&k_elim_lds<1024, false>),
+                      reinterpret_cast<const void*>(&k_elim_lds<1024, true>)};
+  for (const void* fn : f) {
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t allow_eliminate_lds(size_t bytes) {

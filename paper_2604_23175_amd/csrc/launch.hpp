@@ -15,6 +15,12 @@ hipError_t launch_assemble(const Dev& d, int a0, int na, int s0, int ns, int mod
 // lds: dynamic LDS bytes for the level staging (max over the launched systems)
 hipError_t launch_eliminate(const Dev& d, int sys0, int nsys, int s0, int ns, size_t lds, hipStream_t st);
 hipError_t allow_eliminate_lds(size_t bytes);
+// the elimination with the area held in LDS, for the areas at positions
+// [a0, a0 + na) of area_order: lds bytes (the largest of them), nt threads
+// (256, 512 or 1024), tail_hbm if any of them keeps its Schur block in HBM
+hipError_t launch_elim_lds(const Dev& d, int a0, int na, int s0, int ns, size_t lds, int nt, bool tail_hbm,
+                           hipStream_t st);
+hipError_t allow_elim_lds(size_t bytes);
 // supernodal elimination of the boundary system's leading buses; lds: the
 // plan's sn_lds_bytes
 // supernodal elimination of the boundary system's leading buses (one

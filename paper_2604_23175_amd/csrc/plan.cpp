@@ -130,8 +130,12 @@ void finish_system(SysPlan& s) {
   s.bs_ptr.assign(1, 0);
   s.cd_items.clear(); s.up_tgt.clear(); s.up_con.clear();
   s.rb_tgt.clear(); s.rb_con.clear(); s.bs_items.clear(); s.bs_con.clear();
-  struct UpT { int32_t tgt, stride, lij, lpj, j; };
-  struct RbT { int32_t rhs_i, lij, rhs_j, j; };
+  s.up_tgt_img.clear(); s.up_con_img.clear(); s.rb_con_img.clear();
+  // lij / lpj: LDS staging slots of the level's factor blocks; oij / opj:
+  // the same blocks' offsets in the packed storage (for the variant that
+  // keeps the whole system in LDS and needs no staging)
+  struct UpT { int32_t tgt, stride, lij, lpj, j, oij, opj; };
+  struct RbT { int32_t rhs_i, lij, rhs_j, j, oij; };
   s.lds_doubles = 0;
   for (int lev = 0; lev < s.nlev; ++lev) {
     std::vector<UpT> ups;
@@ -159,11 +163,11 @@ void finish_system(SysPlan& s) {
       const auto& st = s.strct[j];
       for (size_t a = 0; a < st.size(); ++a) {
         const int i = st[a];
-        rbs.push_back({2 * i, slot_of.at(s.blk_off(i, j)), yslot[q], j});
+        rbs.push_back({2 * i, slot_of.at(s.blk_off(i, j)), yslot[q], j, s.blk_off(i, j)});
         for (size_t b = 0; b <= a; ++b) {
           const int p = st[b];  // p <= i
           ups.push_back({s.blk_off(i, p), s.blk_stride(i, p), slot_of.at(s.blk_off(i, j)),
-                         slot_of.at(s.blk_off(p, j)), j});
+                         slot_of.at(s.blk_off(p, j)), j, s.blk_off(i, j), s.blk_off(p, j)});
         }
       }
       // back-solve item for column j
@@ -180,10 +184,15 @@ void finish_system(SysPlan& s) {
       if (b - a == 1) {
         // one contribution: its two LDS slots ride in the target record
         s.up_tgt.push_back({ups[a].tgt, ups[a].stride | UP_SINGLE, ups[a].lij, ups[a].lpj});
+        s.up_tgt_img.push_back({ups[a].tgt, ups[a].stride | UP_SINGLE, ups[a].oij, ups[a].opj});
       } else {
         s.up_tgt.push_back({ups[a].tgt, ups[a].stride, (int32_t)s.up_con.size(),
                             (int32_t)(s.up_con.size() + (b - a))});
-        for (size_t c = a; c < b; ++c) s.up_con.push_back({ups[c].lij, ups[c].lpj});
+        s.up_tgt_img.push_back(s.up_tgt.back());
+        for (size_t c = a; c < b; ++c) {
+          s.up_con.push_back({ups[c].lij, ups[c].lpj});
+          s.up_con_img.push_back({ups[c].oij, ups[c].opj});
+        }
       }
       a = b;
     }
@@ -195,7 +204,10 @@ void finish_system(SysPlan& s) {
       while (b < rbs.size() && rbs[b].rhs_i == rbs[a].rhs_i) ++b;
       s.rb_tgt.push_back({rbs[a].rhs_i, (int32_t)s.rb_con.size(),
                           (int32_t)(s.rb_con.size() + (b - a)), 0});
-      for (size_t c = a; c < b; ++c) s.rb_con.push_back({rbs[c].lij, rbs[c].rhs_j});
+      for (size_t c = a; c < b; ++c) {
+        s.rb_con.push_back({rbs[c].lij, rbs[c].rhs_j});
+        s.rb_con_img.push_back({rbs[c].oij, 2 * rbs[c].j});
+      }
       a = b;
     }
     s.cd_ptr.push_back((int32_t)s.cd_items.size());
@@ -402,9 +414,7 @@ double Plan::flops_local() const {
 }
 
 double Plan::flops_gamma() const {
-  const SysPlan& g = sys[n_area];
-  const double nd = g.ld;
-  return g.elim_flops() + nd * nd * nd / 3.0 + 2.0 * nd * nd;
+  return sys[n_area].elim_flops() + flops_dense();
 }
 
 double Plan::bytes_assembly() const {
@@ -412,7 +422,11 @@ double Plan::bytes_assembly() const {
   double tmpl = 0;
   for (int k = 0; k < n_area; ++k) {
     const auto& t = tpl[k];
-    b += 8.0 * 4 * t.slot.size() + 16.0 * sys[k].nn + 8.0;  // packed G, b, J
+    // packed G: the 2x2 blocks that some measurement row contributes to
+    // (fill positions of the factor are not part of G), b, J
+    int64_t nz = 0;
+    for (const I4& sl : t.slot) nz += sl.w > sl.z;
+    b += 8.0 * 4 * nz + 16.0 * sys[k].nn + 8.0;
     tmpl += 16.0 * t.slot.size() + 8.0 * t.scon.size() + 8.0 * t.rslot.size() + 8.0 * t.rcon.size() +
             12.0 * t.row_type.size() + 40.0 * t.br_lf.size() + 4.0 * (t.inc_ptr.size() + t.inc_end.size());
   }
@@ -420,20 +434,33 @@ double Plan::bytes_assembly() const {
   return b + tmpl / std::max(1, n_snap);
 }
 
-double Plan::bytes_condense() const {
+double Plan::bytes_condense(bool lds) const {
   double b = 0;
-  for (int k = 0; k < n_area; ++k) b += 2.0 * 8 * sys[k].nval + 2.0 * 16 * sys[k].nn;
+  for (int k = 0; k < n_area; ++k) {
+    const SysPlan& s = sys[k];
+    if (lds && tpl[k].lds_split > 0) {
+      // read the compact G (and the Schur block kept in HBM, read and
+      // written), write the packed storage once, rhs in and out
+      const double in_hbm = (double)(s.nval - tpl[k].lds_split);
+      b += 8.0 * 4 * tpl[k].cimg.size() + 8.0 * tpl[k].lds_split + 2.0 * 8 * in_hbm + 2.0 * 16 * s.nn;
+    } else {
+      b += 2.0 * 8 * s.nval + 2.0 * 16 * s.nn;
+    }
+  }
   return b;
 }
 
 double Plan::bytes_backsolve() const {
+  // the areas' back substitution (the boundary system's has its own kernels)
   double b = 0;
-  for (int k = 0; k <= n_area; ++k) b += 8.0 * sys[k].tail_off + 2.0 * 16 * sys[k].nn;
+  for (int k = 0; k < n_area; ++k) b += 8.0 * sys[k].tail_off + 2.0 * 16 * sys[k].nn;
   return b;
 }
 
 double Plan::flops_dense() const {
-  const double nd = sys[n_area].ld;
+  // Cholesky and two triangular solves of the dense block's 2 nt variables
+  // (its storage is padded to ld; the padding is not counted)
+  const double nd = 2.0 * sys[n_area].nt;
   return nd * nd * nd / 3.0 + 2.0 * nd * nd;
 }
 
@@ -636,6 +663,20 @@ std::string build_plan(const Input& in, Plan& p) {
       for (auto& c : by_bus[v]) t.rcon.push_back(c);
       t.rslot.push_back({cb, (int32_t)t.rcon.size()});
     }
+    // compact output for the elimination in LDS: everything in LDS if it
+    // fits beside the rhs, else all but the Schur block (which stays in HBM)
+    if ((int64_t)s.nval + 2 * nn <= AREA_LDS_DOUBLES) t.lds_split = s.nval;
+    else if ((int64_t)s.tail_off + 2 * nn <= AREA_LDS_DOUBLES) t.lds_split = s.tail_off;
+    else t.lds_split = 0;
+    for (const I4& sl : t.slot) {
+      if (sl.x < t.lds_split) {
+        if (sl.w <= sl.z) continue;  // fill: zero in LDS
+        t.cslot.push_back({4 * (int32_t)t.cimg.size(), sl.y < 0 ? -2 : 2, sl.z, sl.w});
+        t.cimg.push_back(sl.x);
+      } else {
+        t.tslot.push_back(sl);
+      }
+    }
   }
 
   // ---------------- boundary system ----------------
@@ -713,6 +754,14 @@ std::string build_plan(const Input& in, Plan& p) {
       p.rhs_off[k] = (int32_t)ro;
       vo = round_up(vo + p.sys[k].nval, 32);
       ro = round_up(ro + 2 * (int64_t)p.sys[k].nn, 32);
+      if (vo > ((int64_t)1 << 31) - 64) return "per-snapshot storage over 2^31 doubles";
+    }
+    p.lds_areas = false;
+    p.gc_off.assign(K, 0);
+    for (int k = 0; k < K; ++k) {
+      p.gc_off[k] = (int32_t)vo;
+      vo = round_up(vo + 4 * (int64_t)p.tpl[k].cimg.size(), 32);
+      p.lds_areas |= p.tpl[k].lds_split > 0;
       if (vo > ((int64_t)1 << 31) - 64) return "per-snapshot storage over 2^31 doubles";
     }
     p.vstride = vo;

@@ -25,6 +25,9 @@ constexpr int32_t UP_SINGLE = 1 << 30;
 constexpr int LDS_STAGE_DOUBLES = 6144;
 // Widest supernode (buses): its panel is at most 64 variables wide.
 constexpr int SN_MAX_W = 32;
+// LDS of one workgroup on gfx950 (doubles): the budget for holding an area's
+// whole packed storage (or all but its Schur block) during its elimination.
+constexpr int AREA_LDS_DOUBLES = 160 * 1024 / 8;
 
 // Panel geometry of a supernode of w buses with r row buses below: the LDS
 // panel has sn_rows_padded() rows (the 2w own variables padded to a multiple
@@ -110,6 +113,13 @@ struct SysPlan {
   std::vector<I4> tail_ent;       // {target, 0 matrix (col * ld + row) / 1 rhs (variable), cbeg, cend}
   std::vector<int32_t> tail_con;  // buffer offsets, per target in supernode order
   int32_t tl_doubles = 0;         // doubles of the compact buffer per snapshot
+  // The same update and rhs lists for a system held whole in LDS: factor
+  // blocks are addressed by their packed-storage offsets instead of staging
+  // slots (a single-contribution target carries the two offsets inline), and
+  // y_j by its rhs offset 2 j.
+  std::vector<I4> up_tgt_img;   // parallel to up_tgt
+  std::vector<I2> up_con_img;   // {off L_ij, off L_pj}
+  std::vector<I2> rb_con_img;   // {off L_ij, rhs offset of y_j}
   std::vector<int32_t> bs_ptr;  // [nlev+1] -> bs_items (same levels, run top-down)
   std::vector<I4> bs_items;     // {diag_off, rhs_j, cbeg, cend}
   std::vector<I2> bs_con;       // {off L_ij, rhs_i}: t -= L_ij^T * x_i
@@ -143,6 +153,17 @@ struct AreaTemplates {
   std::vector<I2> rslot;
   std::vector<I2> rcon;
   int64_t n_contrib() const { return (int64_t)scon.size() + (int64_t)rcon.size(); }
+  // Output of the assembly for the elimination that holds the area in LDS:
+  // the slots with at least one contribution below lds_split go to a compact
+  // array (4 doubles each, in this order; cslot offsets count from its start,
+  // cimg gives each one's offset in the packed storage); fill positions there
+  // are zeroed in LDS instead of being written.  Slots at or above lds_split
+  // (the Schur block, when the area does not fit whole) keep their
+  // packed-storage offsets in tslot and are all written, fill included.
+  std::vector<I4> cslot, tslot;
+  std::vector<int32_t> cimg;
+  int32_t lds_split = 0;   // doubles of the packed storage held in LDS (0: does not fit;
+                           // the area then runs the level engine over HBM)
 };
 
 struct Input {
@@ -175,7 +196,9 @@ struct Plan {
 
   // per-snapshot layout (doubles)
   std::vector<int32_t> val_off, rhs_off;  // per system
+  std::vector<int32_t> gc_off;            // per area: the compact G array (after all systems)
   int64_t vstride = 0, rstride = 0;
+  bool lds_areas = false;                 // some area fits the LDS budget (its elimination in LDS)
 
   // boundary assembly (Eq. 11): Gamma slots {offset, stride, cbeg, cend},
   // contributions {src_off, src_ld, transpose, 0} (offsets relative to the
@@ -195,10 +218,11 @@ struct Plan {
   int max_levels() const;
   double flops_local() const;
   double flops_gamma() const;
-  double bytes_assembly() const;  // algorithmic HBM bytes per snapshot
-  double bytes_condense() const;  // read G once, write L once (areas), rhs
-  double bytes_backsolve() const; // read L once, rhs read / write
-  double flops_dense() const;     // dense boundary block: n^3/3 + 2 n^2
+  double bytes_assembly() const;  // algorithmic HBM bytes per snapshot (nonzero G blocks only)
+  // read G once, write L once (areas), rhs; lds: areas that fit are eliminated in LDS
+  double bytes_condense(bool lds) const;
+  double bytes_backsolve() const; // areas: read L once, rhs read / write
+  double flops_dense() const;     // dense boundary block of n = 2 nt variables: n^3/3 + 2 n^2
   int n_gamma_vars() const;
 };
 

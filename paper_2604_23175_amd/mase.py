@@ -25,7 +25,7 @@ INFO = {"n_gamma": 0, "n_boundary_bus": 1, "gamma_tail": 2, "nnz_factor": 3, "ma
         "flops_local": 5, "flops_gamma": 6, "bytes_assembly": 7, "n_snap": 8, "n_area": 9,
         "bytes_condense": 10, "flops_dense": 11, "bytes_backsolve": 12, "flops_gamma_sparse": 13,
         "gamma_levels": 14, "gamma_supernodes": 15, "gamma_supernodal": 16, "pipeline_groups": 17,
-        "gamma_subtree_groups": 18, "gamma_dense_panel": 19}
+        "gamma_subtree_groups": 18, "gamma_dense_panel": 19, "area_lds": 20}
 STAGES = ("assemble", "condense", "gamma_gather", "gamma_sparse", "gamma_dense", "gamma_back",
           "backsolve", "update", "local")
 MAPS = {"boundary_flag": 0, "meas_area": 1, "gamma_vars": 2, "local_vars": 3,
@@ -35,7 +35,8 @@ MAPS = {"boundary_flag": 0, "meas_area": 1, "gamma_vars": 2, "local_vars": 3,
 SYMBOLS = (
     "mase_default_options", "mase_create", "mase_destroy", "mase_last_error", "mase_strerror",
     "mase_set_measurements", "mase_set_measurements_dev", "mase_set_state", "mase_set_state_dev",
-    "mase_gn_iter", "mase_solve", "mase_solve_stream", "mase_state", "mase_state_dev", "mase_objective",
+    "mase_gn_iter", "mase_solve", "mase_solve_stream", "mase_solve_stream_host", "mase_stream_host_work",
+    "mase_state", "mase_state_dev", "mase_objective",
     "mase_eval_h_dev", "mase_info", "mase_export_map", "mase_export_pattern",
     "mase_stage_assemble", "mase_stage_condense", "mase_stage_gamma_assemble",
     "mase_stage_gamma_solve", "mase_stage_update", "mase_read_local_system", "mase_read_schur",
@@ -92,6 +93,9 @@ def load():
         "mase_solve": (ctypes.c_int, [P, ctypes.c_double, ctypes.c_int32, i32p, i32p]),
         "mase_solve_stream": (ctypes.c_int, [P, P, P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
                                              P, P, i32p, i32p]),
+        "mase_solve_stream_host": (ctypes.c_int, [P, P, P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
+                                                  P, P, i32p, i32p, P, ctypes.c_int64]),
+        "mase_stream_host_work": (ctypes.c_int64, [P, ctypes.c_int64, ctypes.c_int32]),
         "mase_state": (ctypes.c_int, [P, f64p, f64p]),
         "mase_state_dev": (ctypes.c_int, [P, P, P]),
         "mase_objective": (ctypes.c_int, [P, f64p]),
@@ -149,6 +153,30 @@ def _dptr(x):
     if isinstance(x, int):
         return ctypes.c_void_p(x)
     return ctypes.c_void_p(x.data_ptr())
+
+
+def _dev(x, shape, name, dtype="float64", min_rows=None):
+    """Device pointer of a torch tensor after checking what the C call
+    assumes: a contiguous tensor on a GPU with the given dtype and shape (-1
+    matches any length; min_rows: at least that many rows).  A raw int
+    pointer is passed unchecked; None stays None."""
+    if x is None or isinstance(x, int):
+        return _dptr(x)
+    if not getattr(x, "is_cuda", False):
+        raise ValueError(f"{name}: expected a GPU tensor")
+    if str(x.dtype) != "torch." + dtype:
+        raise ValueError(f"{name}: expected dtype {dtype}, got {x.dtype}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous tensor")
+    want = tuple(shape)
+    got = tuple(x.shape)
+    ok = len(got) == len(want) and all(w == -1 or w == g for w, g in zip(want, got))
+    if ok and min_rows is not None:
+        ok = got[0] >= min_rows
+    if not ok:
+        raise ValueError(f"{name}: expected shape {want}" + (f" with >= {min_rows} rows" if min_rows else "")
+                         + f", got {got}")
+    return _dptr(x)
 
 
 def _check(rc, allow=(MASE_OK,)):
@@ -245,7 +273,8 @@ class Mase:
         _check(self.lib.mase_set_measurements(self.ctx, zp, wp))
 
     def mase_set_measurements_dev(self, z_dev, w_dev=None):
-        _check(self.lib.mase_set_measurements_dev(self.ctx, _dptr(z_dev), _dptr(w_dev)))
+        _check(self.lib.mase_set_measurements_dev(self.ctx, _dev(z_dev, (self.n_snap, self.n_meas), "z_dev"),
+                                                  _dev(w_dev, (self.n_meas,), "w_dev")))
 
     def mase_set_state(self, vm=None, va=None):
         if vm is None:
@@ -257,7 +286,8 @@ class Mase:
         _check(self.lib.mase_set_state(self.ctx, vp, ap))
 
     def mase_set_state_dev(self, vm_dev=None, va_dev=None):
-        _check(self.lib.mase_set_state_dev(self.ctx, _dptr(vm_dev), _dptr(va_dev)))
+        shp = (self.n_snap, self.n_bus)
+        _check(self.lib.mase_set_state_dev(self.ctx, _dev(vm_dev, shp, "vm_dev"), _dev(va_dev, shp, "va_dev")))
 
     def mase_gn_iter(self):
         out = np.zeros(self.n_snap)
@@ -280,10 +310,47 @@ class Mase:
         n_total = int(z_dev.shape[0])
         iters = np.zeros(n_total, dtype=np.int32)
         conv = np.zeros(n_total, dtype=np.int32)
-        rc = self.lib.mase_solve_stream(self.ctx, _dptr(z_dev), _dptr(vm0_dev), _dptr(va0_dev), n_total,
-                                        float(tol), int(max_iter), _dptr(vm_out), _dptr(va_out),
+        sb = (n_total, self.n_bus)
+        zp = _dev(z_dev, (n_total, self.n_meas), "z_dev")
+        v0, a0 = _dev(vm0_dev, sb, "vm0_dev"), _dev(va0_dev, sb, "va0_dev")
+        vo, ao = _dev(vm_out, sb, "vm_out"), _dev(va_out, sb, "va_out")
+        rc = self.lib.mase_solve_stream(self.ctx, zp, v0, a0, n_total,
+                                        float(tol), int(max_iter), vo, ao,
                                         iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                         conv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        _check(rc, allow=(MASE_OK, MASE_NOT_CONVERGED))
+        return iters, conv.astype(bool)
+
+    def mase_stream_host_work(self, n_total, with_start=False):
+        return int(self.lib.mase_stream_host_work(self.ctx, int(n_total), int(bool(with_start))))
+
+    def mase_solve_stream_host(self, z_host, vm_out, va_out, work_dev, vm0_host=None, va0_host=None, tol=1e-6,
+                               max_iter=10):
+        """As mase_solve_stream with host buffers (torch CPU tensors, pinned
+        for overlapped copies): z_host [n_total][n_meas] in, vm_out / va_out
+        [n_total][n_bus] out; work_dev a float64 GPU tensor of at least
+        mase_stream_host_work(n_total, ...) elements."""
+        n_total = int(z_host.shape[0])
+        sb = (n_total, self.n_bus)
+
+        def host(x, shape, name):
+            if x is None:
+                return None
+            if getattr(x, "is_cuda", False) or str(x.dtype) != "torch.float64" or not x.is_contiguous() \
+                    or tuple(x.shape) != tuple(shape):
+                raise ValueError(f"{name}: expected a contiguous float64 CPU tensor of shape {shape}")
+            return ctypes.c_void_p(x.data_ptr())
+        zp = host(z_host, (n_total, self.n_meas), "z_host")
+        v0, a0 = host(vm0_host, sb, "vm0_host"), host(va0_host, sb, "va0_host")
+        vo, ao = host(vm_out, sb, "vm_out"), host(va_out, sb, "va_out")
+        need = self.mase_stream_host_work(n_total, vm0_host is not None)
+        wp = _dev(work_dev, (-1,), "work_dev", min_rows=need)
+        iters = np.zeros(n_total, dtype=np.int32)
+        conv = np.zeros(n_total, dtype=np.int32)
+        rc = self.lib.mase_solve_stream_host(self.ctx, zp, v0, a0, n_total, float(tol), int(max_iter), vo, ao,
+                                             iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                             conv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                             wp, int(work_dev.numel()) if work_dev is not None else 0)
         _check(rc, allow=(MASE_OK, MASE_NOT_CONVERGED))
         return iters, conv.astype(bool)
 
@@ -295,7 +362,8 @@ class Mase:
         return vm, va
 
     def mase_state_dev(self, vm_dev, va_dev):
-        _check(self.lib.mase_state_dev(self.ctx, _dptr(vm_dev), _dptr(va_dev)))
+        shp = (self.n_snap, self.n_bus)
+        _check(self.lib.mase_state_dev(self.ctx, _dev(vm_dev, shp, "vm_dev"), _dev(va_dev, shp, "va_dev")))
 
     def mase_objective(self):
         J = np.zeros(self.n_snap)
@@ -303,7 +371,9 @@ class Mase:
         return J
 
     def mase_eval_h_dev(self, vm_dev, va_dev, h_dev):
-        _check(self.lib.mase_eval_h_dev(self.ctx, _dptr(vm_dev), _dptr(va_dev), _dptr(h_dev)))
+        shp = (self.n_snap, self.n_bus)
+        _check(self.lib.mase_eval_h_dev(self.ctx, _dev(vm_dev, shp, "vm_dev"), _dev(va_dev, shp, "va_dev"),
+                                        _dev(h_dev, (self.n_snap, self.n_meas), "h_dev")))
 
     # ---- per-stage timing ----
     def mase_profile(self, enable=True):
@@ -435,6 +505,12 @@ class Mlp:
         except Exception:
             pass
 
+    def _io(self, z_dev, vm_dev, va_dev, batch):
+        o = self.owner
+        return (_dev(z_dev, (-1, o.n_meas), "z_dev", min_rows=int(batch)),
+                _dev(vm_dev, (-1, o.n_bus), "vm_dev", min_rows=int(batch)),
+                _dev(va_dev, (-1, o.n_bus), "va_dev", min_rows=int(batch)))
+
     def mase_mlp_set_params(self, params):
         p = np.ascontiguousarray(params, dtype=np.float32)
         assert p.size == self.n_param
@@ -454,19 +530,22 @@ class Mlp:
     def mase_mlp_loss_grad(self, z_dev, vm_dev, va_dev, batch, want_grad=True):
         loss = ctypes.c_double()
         g = np.zeros(self.n_param, dtype=np.float32) if want_grad else None
-        _check(self.lib.mase_mlp_loss_grad(self.h, _dptr(z_dev), _dptr(vm_dev), _dptr(va_dev), int(batch),
+        zp, vp, ap = self._io(z_dev, vm_dev, va_dev, batch)
+        _check(self.lib.mase_mlp_loss_grad(self.h, zp, vp, ap, int(batch),
                                            ctypes.byref(loss),
                                            g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if want_grad else None))
         return float(loss.value), g
 
     def mase_mlp_train_step(self, z_dev, vm_dev, va_dev, batch, lr, want_loss=False):
         loss = ctypes.c_double()
-        _check(self.lib.mase_mlp_train_step(self.h, _dptr(z_dev), _dptr(vm_dev), _dptr(va_dev), int(batch),
+        zp, vp, ap = self._io(z_dev, vm_dev, va_dev, batch)
+        _check(self.lib.mase_mlp_train_step(self.h, zp, vp, ap, int(batch),
                                             float(lr), ctypes.byref(loss) if want_loss else None))
         return float(loss.value) if want_loss else None
 
     def mase_mlp_predict_dev(self, z_dev, batch, vm_dev, va_dev):
-        _check(self.lib.mase_mlp_predict_dev(self.h, _dptr(z_dev), int(batch), _dptr(vm_dev), _dptr(va_dev)))
+        zp, vp, ap = self._io(z_dev, vm_dev, va_dev, batch)
+        _check(self.lib.mase_mlp_predict_dev(self.h, zp, int(batch), vp, ap))
 
     def mase_mlp_set_accept_cap(self, j_cap):
         _check(self.lib.mase_mlp_set_accept_cap(self.h, float(j_cap)))

@@ -3,14 +3,20 @@
 Stage 1 (G^k, b^k), stage 2 (S_b^k, bhat_b^k), stage 3a (S_Gamma, bhat_Gamma)
 and stage 4 (the full step dx) are read back in canonical order and compared
 with the oracle's dense construction on the same seeded inputs.  Floating-point
-sums run in a different order on the two sides, so the bar is relative:
-|a - b| <= rtol * max|b| per matrix.
+sums run in a different order on the two sides.  G^k, b^k, S_b^k and S_Gamma
+are held entry by entry to rounding bounds built from the magnitudes of the
+terms that make up each entry (tests/bounds.py); bhat and dx, results of
+solves, to a bar relative to their largest entry.
 """
 import numpy as np
 import pytest
 
+import bounds
 from gpu_common import Case, assert_state_close, boundary_slack, say
 from oracle import wls
+
+C_ASM = 64     # per-entry constant of the assembly bound (both sides' rounding)
+C_CHOL = 64    # per-entry constant of the elimination's backward error
 
 pytestmark = pytest.mark.gpu
 
@@ -47,26 +53,41 @@ def test_stage_parity(name, slack, gamma_mode):
     vm, va = _perturbed_state(c)
     m.mase_set_state(vm, va)
     m.mase_stage_assemble()
+    worst = {"G": 0.0, "b": 0.0, "S": 0.0, "SG": 0.0}
+    mags, sbnd = {}, {}
     for s in range(2):
         for k in range(c.g.n_area):
             G, b = m.mase_read_local_system(s, k)
             Go, bo = c.A.local_system(k, c.z[s], vm[s], va[s])
+            MG, Mb = bounds.local_magnitudes(c.A, k, c.z[s], vm[s])
+            mags[s, k] = MG
+            worst["G"] = max(worst["G"], bounds.check_entries(G, Go, C_ASM * bounds.EPS * MG, f"G^{k}"))
+            worst["b"] = max(worst["b"], bounds.check_entries(b, bo, C_ASM * bounds.EPS * Mb, f"b^{k}"))
             _close(G, Go, RTOL_G, f"G^{k}")
-            _close(b, bo, RTOL_G, f"b^{k}")
     m.mase_stage_condense()
     for s in range(2):
         for k in range(c.g.n_area):
             S, bh = m.mase_read_schur(s, k)
             Go, bo = c.A.local_system(k, c.z[s], vm[s], va[s])
             So, bho = c.A.condense(k, Go, bo)
-            _close(S, So, RTOL_S, f"S_b^{k}")
+            ni = c.A.n_internal_vars[k]
+            sbnd[s, k] = bounds.schur_bound(Go, mags[s, k], ni, C_ASM, C_CHOL)
+            worst["S"] = max(worst["S"], bounds.check_entries(S, So, sbnd[s, k], f"S_b^{k}"))
             _close(bh, bho, RTOL_S, f"bhat_b^{k}")
     m.mase_stage_gamma_assemble()
     for s in range(2):
         SG, bG = m.mase_read_gamma_system(s)
         _, det = c.A.condensed_step(c.z[s], vm[s], va[s], detail=True)
-        _close(SG, det["S_gamma"], RTOL_S, "S_Gamma")
+        # the gather adds the areas' blocks: their bounds add the same way
+        # (plus the rounding of the sums themselves)
+        ng = SG.shape[0]
+        BG = np.zeros((ng, ng))
+        for k in range(c.g.n_area):
+            E = c.A.E[k]
+            BG[np.ix_(E, E)] += sbnd[s, k] + 4 * bounds.EPS * np.abs(det["systems"][k][2])
+        worst["SG"] = max(worst["SG"], bounds.check_entries(SG, det["S_gamma"], BG, "S_Gamma"))
         _close(bG, det["b_gamma"], RTOL_S, "bhat_Gamma")
+    say("  largest error / per-entry bound:", {k: f"{v:.3g}" for k, v in worst.items()})
     m.mase_stage_gamma_solve()
     m.mase_stage_update()
     for s in range(2):

@@ -392,3 +392,87 @@ def test_subtree_groups_bitwise_identical(name, monkeypatch):
     np.testing.assert_array_equal(res[0][1][0], res[1][1][0])
     np.testing.assert_array_equal(res[0][1][1], res[1][1][1])
     np.testing.assert_array_equal(res[0][2], res[1][2])
+
+
+def test_high_weight_rows_match_oracle():
+    # the top of the weight range FP64 is kept for (Eq. 2, W = R^-1): every
+    # 10th |V| row and every 10th active from-end flow row measured with
+    # sigma = 1e-4 (w = 1e8) beside the other rows' w = 1.6e4 - 6.3e4, so the
+    # weights span 1e4 - 1e8; states within 1e-8 of the oracle
+    say("weights up to 1e8")
+    c = Case("c1", 3, seed=31)
+    t = c.t
+    hi = np.concatenate([np.nonzero(t == synth.VM)[0][::10], np.nonzero(t == synth.PF)[0][::10]])
+    sig = np.asarray(c.s, dtype=np.float64).copy()
+    sig[hi] = 1e-4
+    for i in range(c.n_snap):
+        h = c.net.h(c.vm_true[i], c.va_true[i])
+        c.z[i, hi] = h[hi] + sig[hi] * c.batch.eps[i, hi]
+    c.w = 1.0 / sig ** 2
+    assert c.w.max() / c.w.min() >= 1e4 - 1
+    m = c.ctx()
+    iters, conv = m.mase_solve(1e-6, 10)
+    vm, va = m.mase_state()
+    J = m.mase_objective()
+    for i in range(c.n_snap):
+        ref = c.oracle_solve(i)
+        assert conv[i] and ref["converged"]
+        assert iters[i] == ref["iters"], (iters[i], ref["iters"])
+        assert_state_close(vm[i], va[i], ref["vm"], ref["va"], 1e-8)
+        assert abs(J[i] - ref["J"]) <= 1e-8 * ref["J"]
+    m.close()
+
+
+@pytest.mark.parametrize("npipe", [1, 2])
+def test_failed_snapshot_leaves_the_others_solved(npipe):
+    # NaN measurements in one snapshot: its state turns NaN and the next
+    # iteration's factorisation meets a non-positive (NaN) pivot; that
+    # snapshot is frozen and reported, every other one is solved as usual
+    say("one failing snapshot, pipeline groups", npipe)
+    c = Case("c1", 6, seed=33)
+    c.z[2, :] = np.nan
+    m = c.ctx(pipeline_groups=npipe)
+    iters = np.zeros(6, dtype=np.int32)
+    conv = np.zeros(6, dtype=np.int32)
+    import ctypes
+    rc = m.lib.mase_solve(m.ctx, 1e-6, 10, iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                          conv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    assert rc == mase.MASE_ERR_NOT_POSDEF
+    assert conv[2] == 0 and conv[[0, 1, 3, 4, 5]].all(), conv
+    vm, va = m.mase_state()
+    for i in (0, 1, 3, 4, 5):
+        ref = c.oracle_solve(i)
+        assert iters[i] == ref["iters"], (i, iters[i], ref["iters"])
+        assert_state_close(vm[i], va[i], ref["vm"], ref["va"], 1e-8)
+    m.close()
+
+
+@pytest.mark.parametrize("name", ["c0", "k5", "c1", "c2", "c3"])
+def test_lds_elimination_bitwise_equal_to_level_engine(name, monkeypatch):
+    # the areas' elimination held in LDS runs the level schedule's arithmetic
+    # in the same order as the level engine over HBM: identical S_b^k after
+    # one condensation and identical states after a solve (c2: five areas keep
+    # their Schur block in HBM; c3: three areas too large for LDS stay on the
+    # level engine beside the others)
+    say("LDS elimination vs level engine", name)
+    c = Case(name, 2, seed=51)
+    out = []
+    for env in ("1", "0"):
+        monkeypatch.setenv("MASE_AREA_LDS", env)
+        m = c.ctx()
+        n_lds = m.mase_info("area_lds")
+        assert (n_lds > 0) == (env == "1"), n_lds
+        m.mase_stage_assemble()
+        m.mase_stage_condense()
+        S = [m.mase_read_schur(1, k) for k in range(c.g.n_area)]
+        m.mase_set_state()
+        it, conv = m.mase_solve(1e-6, 10)
+        out.append((S, m.mase_state(), it, n_lds))
+        m.close()
+    say("  areas in LDS:", out[0][3], "of", c.g.n_area)
+    for k in range(c.g.n_area):
+        np.testing.assert_array_equal(out[0][0][k][0], out[1][0][k][0])
+        np.testing.assert_array_equal(out[0][0][k][1], out[1][0][k][1])
+    np.testing.assert_array_equal(out[0][1][0], out[1][1][0])
+    np.testing.assert_array_equal(out[0][1][1], out[1][1][1])
+    np.testing.assert_array_equal(out[0][2], out[1][2])

@@ -26,7 +26,7 @@ def test_full_batch_sampled_parity(name, sample):
     vm, va = m.mase_state()
     J = m.mase_objective()
     mn = c.net.m - c.net.n
-    assert np.all(np.abs(J - mn) <= 6 * math.sqrt(2 * mn)), (J.min(), J.max(), mn)
+    assert np.all(np.abs(J - mn) <= 4 * math.sqrt(2 * mn)), (J.min(), J.max(), mn)
     for i in sample:
         say("  oracle snapshot", i)
         ref = c.oracle_solve(i)
@@ -99,5 +99,38 @@ def test_stream_full_size_matches_batched_and_oracle():
         say("  oracle snapshot", i)
         ref = c.oracle_solve(i)
         assert ref["converged"] and it[i] == ref["iters"]
+        assert_state_close(vm[i], va[i], ref["vm"], ref["va"], 1e-8)
+    m.close()
+
+
+@pytest.mark.parametrize("schedule", ["autotune", "panel16"])
+def test_stream_headline_schedule_matches_oracle(schedule, tmp_path, monkeypatch):
+    # the benchmark's configuration on the 9241-bus grid: 64 slots, a stream
+    # of 96 snapshots, the schedule the autotuner picks (or the 16-column
+    # dense-block kernel with lookahead forced), checked against the oracle
+    import torch
+    say("stream headline schedule c2", schedule)
+    from paper_2604_23175_amd import mase
+    dev = torch.device("cuda:0")
+    c = Case("c2", 96, seed=9)
+    if schedule == "panel16":
+        monkeypatch.setenv("MASE_DENSE_PANEL", "1")
+        m = mase.Mase.from_grid(c.g, c.t, c.a, c.s, 64, slack=c.slack)
+        assert m.mase_info("gamma_dense_panel") == 16
+    else:
+        m = mase.Mase.from_grid(c.g, c.t, c.a, c.s, 64, slack=c.slack, autotune=True,
+                                tune_cache=str(tmp_path / "tune.txt"))
+    n = c.z.shape[0]
+    vm = torch.empty((n, c.g.n_bus), dtype=torch.float64, device=dev)
+    va = torch.empty_like(vm)
+    it, conv = m.mase_solve_stream(torch.tensor(c.z, device=dev), vm, va, None, None, 1e-6, 10)
+    say("  schedule:", {k: m.mase_info(k) for k in ("pipeline_groups", "gamma_supernodal",
+                                                   "gamma_subtree_groups", "gamma_dense_panel")})
+    assert conv.all(), it
+    vm, va = vm.cpu().numpy(), va.cpu().numpy()
+    for i in (1, 50, 94):
+        say("  oracle snapshot", i)
+        ref = c.oracle_solve(i)
+        assert ref["converged"] and it[i] == ref["iters"], (it[i], ref["iters"])
         assert_state_close(vm[i], va[i], ref["vm"], ref["va"], 1e-8)
     m.close()

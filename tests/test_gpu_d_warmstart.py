@@ -66,12 +66,54 @@ def test_loss_and_gradients_match_oracle(hidden, B):
     lo, go = omlp.loss_and_grads(params, Xs, Ts, recipe=True)
     assert abs(loss - lo) <= 1e-5 * lo, (loss, lo)
     gg = omlp.unflatten(g.astype(np.float64), M.shapes)
+    n_out = sum(T.shape[1] for T in Ts)
+    worst, n_out_tier1, n_el = 0.0, 0, 0
     for k in range(len(M.shapes)):
+        bnd = _grad_bounds(params[k], Xs[k], Ts[k], n_out)
         for key in omlp.PARAM_ORDER:
-            a, b = gg[k][key], go[k][key]
-            rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
-            assert rel <= 2e-3, (k, key, rel)
+            err = np.abs(gg[k][key] - go[k][key])
+            ratio = err / bnd[key]
+            worst = max(worst, float(ratio.max()))
+            over = int((ratio > C_TIER1).sum())
+            n_out_tier1 += over
+            n_el += err.size
+            # every element within the wide tier, all but 0.1 % within the narrow one
+            assert (ratio <= C_TIER2).all(), (k, key, float(ratio.max()))
+            assert over <= max(1, err.size // 1000), (k, key, over, err.size)
+    say("  largest gradient error / (eps_bf16 |A|^T |B|):", f"{worst:.3g};",
+        n_out_tier1, "of", n_el, "elements beyond", C_TIER1)
     ctx.close()
+
+
+EPS_BF16 = 2.0 ** -8   # unit roundoff of bfloat16 (8 significand bits)
+C_TIER1, C_TIER2 = 4.0, 64.0
+
+
+def _grad_bounds(p, X, T, n_out):
+    """Per-element scale eps_bf16 (|A|^T |B|)_ij of each gradient product
+    g = A^T B (and eps_bf16 sum |B| for the biases) for one area.
+
+    The kernels and oracle.mlp round the same operands to bfloat16, but the
+    kernels accumulate in FP32, so a value just before a bf16 rounding can
+    land on the other side of a rounding boundary: that operand element then
+    differs by one bf16 unit, which moves the products it enters by about
+    eps_bf16 |a_bi| |b_bj|.  Most elements stay within a few units of that
+    scale; a rare difference that also flips a ReLU mask further up costs
+    more, so the test allows a wide second tier for a handful of elements.
+    A wrong index or a transposed operand puts most elements of a block far
+    beyond both tiers."""
+    B = X.shape[0]
+    r = omlp.bf16
+    a = np.abs
+    fw = omlp.area_forward(p, X, recipe=True)
+    dY = 2.0 * (fw["Y"] - T) / (B * n_out)
+    dH2 = (r(dY) @ r(p["W3"]).T) * (fw["P2"] > 0)
+    dH1 = (r(dH2) @ r(p["W2"]).T) * (fw["P1"] > 0)
+    tiny = 1e-30
+    e = EPS_BF16
+    return {"W3": e * (a(fw["A2"]).T @ a(r(dY))) + tiny, "b3": e * a(dY).sum(0) + tiny,
+            "W2": e * (a(fw["A1"]).T @ a(r(dH2))) + tiny, "b2": e * a(dH2).sum(0) + tiny,
+            "W1": e * (a(fw["A0"]).T @ a(r(dH1))) + tiny, "b1": e * a(dH1).sum(0) + tiny}
 
 
 def test_adam_step_matches_oracle():
@@ -177,5 +219,65 @@ def test_warm_start_acceptance_rule_and_fallback():
     assert not acc.any()
     it_rej, _ = ctx.mase_solve(1e-6, 10)
     np.testing.assert_array_equal(it_rej, it_flat)
+    M.close()
+    ctx.close()
+
+
+def test_warm_start_gain_under_calibrated_cap():
+    """What the trained network gains, asserted: trained on one set of drift
+    chains, its acceptance cap calibrated on a second, evaluated on a third.
+    Under the cap the warm-started solves take no more Gauss-Newton
+    iterations in total than flat start (rejected snapshots solve exactly as
+    from flat start) and reach the same minimiser; the iterations of forced
+    predictions (every prediction used) are reported beside them."""
+    say("warm start gain")
+    from gridgen import synth
+    g = synth.make_config("c1")
+    t_, a_, s_ = synth.measurement_set(g.n_bus, g.n_branch)
+    S = 32
+    ctx = mase.Mase.from_grid(g, t_, a_, s_, S)
+    z, vm, va, bad = ws.solved_set(ctx, g, s_, 48, 32, ws.TRAIN_SEED, DEV)
+    assert bad == 0
+    M = mase.Mlp(ctx, hidden=256, max_batch=256)
+    norm = ws.set_normalisation(M, z, vm, va)
+    ws.init_params(M, 0, ws.input_rms(M, z, norm[0], s_))
+    ws.train(M, z, vm, va, epochs=25, batch=256, lr=1e-3)
+    cap, cal = ws.calibrate_accept_cap(ctx, M, g, s_, DEV, n_chain=2, seed=ws.HELDOUT_SEED)
+    # evaluation chains: seeds disjoint from training and calibration
+    hv, ha, he = synth.make_chains(g, 2, S, ws.HELDOUT_SEED + 500)
+    ha = ha - ha[:, [g.slack]]
+    it_f, it_w, it_p, acc_n = [], [], [], 0
+    pv = torch.empty((S, g.n_bus), dtype=torch.float64, device=DEV)
+    pa = torch.empty_like(pv)
+    for b0 in range(0, hv.shape[0], S):
+        idx = np.arange(b0, b0 + S)
+        zh = ws.measurements_dev(ctx, hv[idx], ha[idx], he[idx], s_, DEV)
+        ctx.mase_set_measurements_dev(zh)
+        ctx.mase_set_state()
+        itf, cf = ctx.mase_solve(1e-6, 10)
+        ctx.mase_solve(1e-10, 15)
+        xf = ctx.mase_state()
+        acc = mase.mase_warm_start(ctx, M)
+        acc_n += int(acc.sum())
+        itw, cw = ctx.mase_solve(1e-6, 10)
+        assert cf.all() and cw.all()
+        np.testing.assert_array_equal(itw[~acc], itf[~acc])
+        ctx.mase_solve(1e-10, 15)
+        xw = ctx.mase_state()
+        np.testing.assert_allclose(xw[0], xf[0], rtol=0, atol=1e-8)
+        np.testing.assert_allclose(xw[1], xf[1], rtol=0, atol=1e-8)
+        M.mase_mlp_predict_dev(zh, S, pv, pa)
+        torch.cuda.synchronize()
+        ctx.mase_set_state_dev(pv, pa)
+        itp, cp = ctx.mase_solve(1e-6, 10)
+        it_f.append(itf)
+        it_w.append(itw)
+        it_p.append(np.where(cp, itp, 11))
+    it_f, it_w, it_p = map(np.concatenate, (it_f, it_w, it_p))
+    gain = int(it_f.sum() - it_w.sum())
+    say(f"  cap {cap:.4g} (calibration: {cal}) | evaluation: {acc_n} of {it_f.size} accepted, "
+        f"mean iterations flat {it_f.mean():.3f}, warm {it_w.mean():.3f}, forced prediction "
+        f"{it_p.mean():.3f}; iterations saved {gain}")
+    assert gain >= 0, (gain, it_f.sum(), it_w.sum())
     M.close()
     ctx.close()

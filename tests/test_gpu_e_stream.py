@@ -175,3 +175,69 @@ def test_stream_schedules_and_autotune(tmp_path):
         assert it[i] == ref["iters"]
         assert_state_close(vm[i], va[i], ref["vm"], ref["va"], 1e-8)
     m.close()
+
+
+def test_stream_failed_snapshot_among_healthy_ones():
+    # one snapshot of the stream with NaN measurements is retired as failed;
+    # the others pass through the same slots and match their batched solves
+    say("stream: one failing snapshot")
+    c = Case("k5", 9, seed=41)
+    z = c.z.copy()
+    z[4, :] = np.nan
+    m = mase.Mase.from_grid(c.g, c.t, c.a, c.s, 3, slack=c.slack)
+    n = z.shape[0]
+    vm = torch.empty((n, c.g.n_bus), dtype=torch.float64, device=DEV)
+    va = torch.empty_like(vm)
+    with pytest.raises(mase.MaseError) as e:
+        m.mase_solve_stream(torch.tensor(z, device=DEV), vm, va, None, None, 1e-6, 10)
+    assert e.value.code == mase.MASE_ERR_NOT_POSDEF
+    vm, va = vm.cpu().numpy(), va.cpu().numpy()
+    for i in (0, 3, 5, 8):
+        ref = c.oracle_solve(i)
+        assert_state_close(vm[i], va[i], ref["vm"], ref["va"], 1e-8)
+    m.close()
+
+
+@pytest.mark.parametrize("name,slots,n_total,start", [("k5", 3, 11, False), ("c1", 8, 37, True),
+                                                      ("c1", 8, 5, False)])
+def test_stream_host_buffers_equal_device_stream(name, slots, n_total, start):
+    # measurements uploaded chunk by chunk from pinned host memory while the
+    # stream iterates, states downloaded as chunks finish: bitwise the device
+    # stream's results
+    say("stream with host buffers", name, slots, n_total, start)
+    c = Case(name, n_total, seed=17)
+    m = mase.Mase.from_grid(c.g, c.t, c.a, c.s, slots, slack=c.slack)
+    vm0 = va0 = None
+    if start:
+        rng = np.random.default_rng(3)
+        vm0 = torch.tensor(c.vm_true + rng.normal(0, 0.01, c.vm_true.shape)).pin_memory()
+        va0 = torch.tensor(c.va_true + rng.normal(0, 0.01, c.va_true.shape)).pin_memory()
+    zd = torch.tensor(c.z, device=DEV)
+    vd = torch.empty((n_total, c.g.n_bus), dtype=torch.float64, device=DEV)
+    ad = torch.empty_like(vd)
+    it_d, conv_d = m.mase_solve_stream(zd, vd, ad, None if vm0 is None else vm0.to(DEV),
+                                       None if va0 is None else va0.to(DEV), 1e-6, 10)
+    zh = torch.tensor(c.z).pin_memory()
+    vh = torch.empty((n_total, c.g.n_bus), dtype=torch.float64).pin_memory()
+    ah = torch.empty_like(vh).pin_memory()
+    work = torch.empty(m.mase_stream_host_work(n_total, start), dtype=torch.float64, device=DEV)
+    it_h, conv_h = m.mase_solve_stream_host(zh, vh, ah, work, vm0, va0, 1e-6, 10)
+    np.testing.assert_array_equal(it_h, it_d)
+    np.testing.assert_array_equal(conv_h, conv_d)
+    np.testing.assert_array_equal(vh.numpy(), vd.cpu().numpy())
+    np.testing.assert_array_equal(ah.numpy(), ad.cpu().numpy())
+    assert conv_h.all()
+    ref = c.oracle_solve(n_total - 1) if not start else None
+    if ref is not None:
+        assert_state_close(vh.numpy()[-1], ah.numpy()[-1], ref["vm"], ref["va"], 1e-8)
+    # null buffers and a workspace one double short are argument errors
+    import ctypes
+    P = ctypes.c_void_p
+    rc = m.lib.mase_solve_stream_host(m.ctx, None, None, None, n_total, 1e-6, 10, None, None, None, None, None, 0)
+    assert rc == mase.MASE_ERR_ARG
+    need = m.mase_stream_host_work(n_total, start)
+    rc = m.lib.mase_solve_stream_host(m.ctx, P(zh.data_ptr()), None if vm0 is None else P(vm0.data_ptr()),
+                                      None if va0 is None else P(va0.data_ptr()), n_total, 1e-6, 10,
+                                      P(vh.data_ptr()), P(ah.data_ptr()), None, None, P(work.data_ptr()), need - 1)
+    assert rc == mase.MASE_ERR_ARG
+    m.close()
