@@ -108,10 +108,12 @@ typedef struct {
                             MASE_ERR_NO_DEVICE) */
   int32_t autotune;      /* 1: the first mase_solve times the candidate
                             schedules (pipeline groups 1/2/4/8, supernodal or
-                            level-scheduled boundary elimination) for two GN
-                            iterations on the current measurements, keeps the
-                            fastest and restores the state; results are then
-                            the chosen schedule's */
+                            level-scheduled boundary elimination, the dense
+                            block's panel width, then the LDS elimination's
+                            workgroup size) for two GN iterations on the
+                            current measurements, keeps the fastest and
+                            restores the state; results are then the chosen
+                            schedule's (bitwise the same for every choice) */
   const char* tune_cache;/* path of a text file caching that choice per grid
                             structure, batch size and device (read before
                             tuning, appended after), or NULL */
@@ -424,9 +426,13 @@ enum {
                                      (the environment variable MASE_SNODE_GROUPS caps it) */
   MASE_INFO_GAMMA_DENSE_PANEL,    /* columns per LDS panel of the boundary system's dense block
                                      (0: panels read from HBM); the autotuner may change it */
-  MASE_INFO_AREA_LDS              /* areas whose elimination holds their packed storage in LDS (the
+  MASE_INFO_AREA_LDS,             /* areas whose elimination holds their packed storage in LDS (the
                                      others run the level engine over HBM; the environment
                                      variable MASE_AREA_LDS=0 selects it for all) */
+  MASE_INFO_ELIM_THREADS          /* threads per workgroup of the LDS elimination and back
+                                     substitution (0: per launch class, 1024 for areas that take a
+                                     whole CU's LDS, 512 up to four per CU, else 256); the
+                                     autotuner may set 256, 512 or 1024 for all */
 };
 int mase_info(const mase_ctx* ctx, int32_t what, int64_t* value);
 

@@ -326,7 +326,7 @@ int upload_plan(mase_ctx* c) {
     size_t lds_max = 0;
     int q = 0;
     while (q < K && am[ord[q]].split == 0) ++q;
-    if (q > 0) c->el_class.push_back({0, q, 0, 0, false});
+    if (q > 0) c->el_class.push_back({0, q, 0, 0, false, 0});
     while (q < K) {
       const int k0 = ord[q];
       const size_t b0 = need(k0);
@@ -339,7 +339,7 @@ int upload_plan(mase_ctx* c) {
       }
       const int nt = (nt_force == 256 || nt_force == 512 || nt_force == 1024) ? nt_force
                      : wpc == 1 ? 1024 : (wpc <= 4 ? 512 : 256);
-      c->el_class.push_back({q, r - q, b0, nt, tail});
+      c->el_class.push_back({q, r - q, b0, nt, tail, nt});
       lds_max = std::max(lds_max, b0);
       q = r;
     }
@@ -468,6 +468,22 @@ hipError_t launch_area_eliminate(const mase_ctx* c, int a0, int na, int s0, int 
   return hipSuccess;
 }
 
+// The areas' back substitution (stage 4a) for the same positions: the factor
+// read into LDS for the areas eliminated there (the class's LDS size covers
+// the factor and the rhs), else the level engine over HBM.
+hipError_t launch_area_backsolve(const mase_ctx* c, int a0, int na, int s0, int ns, hipStream_t st,
+                                 bool fixed_bnd = false) {
+  if (!c->area_lds) return launch_backsolve(c->d, a0, na, s0, ns, st, fixed_bnd);
+  for (const auto& cl : c->el_class) {
+    const int lo = std::max(a0, cl.a0), hi = std::min(a0 + na, cl.a0 + cl.na);
+    if (lo >= hi) continue;
+    const hipError_t e = cl.nt ? launch_back_lds(c->d, lo, hi - lo, s0, ns, cl.lds, cl.nt, fixed_bnd, st)
+                               : launch_backsolve(c->d, lo, hi - lo, s0, ns, st, fixed_bnd);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // Stages 1-2 (assembly, condensation) for snapshots [s0, s0 + ns), after
 // the iteration's local steps (Eq. 6: each area's internal variables take
 // GN steps with its boundary held; same kernels, dx_b = 0).
@@ -479,7 +495,7 @@ int launch_area_part(mase_ctx* c, hipStream_t st, int s0, int ns) {
     for (int l = 0; l < c->opt.local_steps; ++l) {
       HIPTRY(launch_assemble(d, 0, K, s0, ns, MODE_ASSEMBLE, c->lds_asm, c->br_lds, st));
       HIPTRY(launch_area_eliminate(c, 0, K, s0, ns, st));
-      HIPTRY(launch_backsolve(d, 0, K, s0, ns, st, true));
+      HIPTRY(launch_area_backsolve(c, 0, K, s0, ns, st, true));
       HIPTRY(launch_update(d, s0, ns, st, true));
     }
   }
@@ -520,7 +536,7 @@ int launch_gamma_part(mase_ctx* c, hipStream_t st, int s0, int ns) {
   }
   {
     StageMark m(c, st, MASE_STAGE_BACKSOLVE);
-    HIPTRY(launch_backsolve(d, 0, K, s0, ns, st));
+    HIPTRY(launch_area_backsolve(c, 0, K, s0, ns, st));
   }
   {
     StageMark m(c, st, MASE_STAGE_UPDATE);
@@ -688,7 +704,7 @@ int launch_plain_iteration(mase_ctx* c, int s) {
   }
   HIPTRY(hipEventRecord(c->ev_main, st));
   for (int i = 0; i < ns; ++i) HIPTRY(hipStreamWaitEvent(c->astreams[i], c->ev_main, 0));
-  for (int ai = 0; ai < K; ++ai) HIPTRY(launch_backsolve(d, ai, 1, s, 1, c->astreams[ai % ns]));
+  for (int ai = 0; ai < K; ++ai) HIPTRY(launch_area_backsolve(c, ai, 1, s, 1, c->astreams[ai % ns]));
   for (int i = 0; i < ns; ++i) {
     HIPTRY(hipEventRecord(c->aevents[i], c->astreams[i]));
     HIPTRY(hipStreamWaitEvent(st, c->aevents[i], 0));
@@ -1057,8 +1073,8 @@ uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
 std::string make_tune_key(const mase_ctx* c) {
   const Plan& p = c->plan;
   uint64_t h = 1469598103934665603ull;
-  const int32_t dims[7] = {p.n_bus, p.n_branch, p.n_area, p.n_meas, p.n_snap, c->opt.gamma_mode,
-                           c->opt.local_steps};
+  const int32_t dims[8] = {p.n_bus, p.n_branch, p.n_area, p.n_meas, p.n_snap, c->opt.gamma_mode,
+                           c->opt.local_steps, c->area_lds ? 1 : 0};
   h = fnv1a(h, dims, sizeof(dims));
   h = fnv1a(h, p.br_from.data(), p.br_from.size() * sizeof(int32_t));
   h = fnv1a(h, p.br_to.data(), p.br_to.size() * sizeof(int32_t));
@@ -1075,21 +1091,26 @@ std::string make_tune_key(const mase_ctx* c) {
   return std::string(buf) + "/" + (arch.empty() ? "unknown" : arch);
 }
 
-// One cache line per tuned configuration: "key npipe snode dense_mode dense_nb".
-bool read_tune_cache(const mase_ctx* c, int& npipe, int& snode, int& dmode, int& dnb) {
+// One cache line per tuned configuration:
+// "key npipe snode dense_mode dense_nb [elim_nt]" (elim_nt 0: per-class default).
+bool read_tune_cache(const mase_ctx* c, int& npipe, int& snode, int& dmode, int& dnb, int& ent) {
   if (c->tune_path.empty()) return false;
   FILE* f = std::fopen(c->tune_path.c_str(), "r");
   if (!f) return false;
   char line[512], key[256];
   bool found = false;
   while (std::fgets(line, sizeof(line), f)) {
-    int a = 0, b = 0, m = 0, w = 0;
-    if (std::sscanf(line, "%255s %d %d %d %d", key, &a, &b, &m, &w) != 5) continue;
-    if (c->tune_key == key && a >= 1 && (b == 0 || b == 1) && m >= DENSE_GLOBAL && m <= DENSE_WIDE && w >= 0) {
+    int a = 0, b = 0, m = 0, w = 0, e = 0;
+    const int n = std::sscanf(line, "%255s %d %d %d %d %d", key, &a, &b, &m, &w, &e);
+    if (n < 5) continue;
+    if (n == 5) e = 0;
+    if (c->tune_key == key && a >= 1 && (b == 0 || b == 1) && m >= DENSE_GLOBAL && m <= DENSE_WIDE && w >= 0 &&
+        (e == 0 || e == 256 || e == 512 || e == 1024)) {
       npipe = a;
       snode = b;
       dmode = m;
       dnb = w;
+      ent = e;
       found = true;  // the last matching line wins
     }
   }
@@ -1097,12 +1118,19 @@ bool read_tune_cache(const mase_ctx* c, int& npipe, int& snode, int& dmode, int&
   return found;
 }
 
-void write_tune_cache(const mase_ctx* c, int npipe, int snode, int dmode, int dnb) {
+void write_tune_cache(const mase_ctx* c, int npipe, int snode, int dmode, int dnb, int ent) {
   if (c->tune_path.empty()) return;
   FILE* f = std::fopen(c->tune_path.c_str(), "a");
   if (!f) return;
-  std::fprintf(f, "%s %d %d %d %d\n", c->tune_key.c_str(), npipe, snode, dmode, dnb);
+  std::fprintf(f, "%s %d %d %d %d %d\n", c->tune_key.c_str(), npipe, snode, dmode, dnb, ent);
   std::fclose(f);
+}
+
+// Threads per workgroup of every LDS elimination class (0: each class's default).
+void apply_elim_nt(mase_ctx* c, int nt) {
+  c->elim_nt = nt;
+  for (auto& cl : c->el_class)
+    if (cl.nt) cl.nt = nt ? nt : cl.nt_default;
 }
 
 // Drops every captured graph (they bake in the schedule choices).
@@ -1161,12 +1189,13 @@ int autotune(mase_ctx* c) {
     if (c->dense_nb > 32) dense_cands.push_back({DENSE_WIDE, 32});
     dense_cands.push_back({DENSE_PANEL16, 16});
   }
-  int np = 0, sn = 0, dm = 0, dnb = 0;
-  if (read_tune_cache(c, np, sn, dm, dnb)) {
+  int np = 0, sn = 0, dm = 0, dnb = 0, ent = 0;
+  if (read_tune_cache(c, np, sn, dm, dnb, ent)) {
     int rc = reset_graphs(c);
     if (rc) return rc;
     c->npipe = std::max(1, std::min(np, c->plan.n_snap));
     c->gamma_snode = sn && c->snode_possible;
+    apply_elim_nt(c, ent);
     for (const auto& dc : dense_cands)
       if (dc.first == dm && dc.second == dnb) {
         c->dense_mode = dm;
@@ -1207,6 +1236,7 @@ int autotune(mase_ctx* c) {
   double best = 1e300;
   int best_np = c->npipe, best_sn = snode0 ? 1 : 0;
   std::pair<int, int> best_dense{c->dense_mode, c->dense_nb};
+  int best_ent = c->elim_nt;
   // a snapshot with a non-positive pivot only freezes itself, so a failure
   // here is a runtime error; the state and the schedule are restored on
   // every exit
@@ -1239,6 +1269,30 @@ int autotune(mase_ctx* c) {
         }
       }
     }
+    // then the LDS elimination's workgroup size under the best schedule
+    if (c->area_lds) {
+      for (int ntc : {256, 512, 1024}) {
+        int e = reset_graphs(c);
+        if (e) return e;
+        c->npipe = best_np;
+        c->gamma_snode = best_sn == 1;
+        c->dense_mode = best_dense.first;
+        c->dense_nb = best_dense.second;
+        apply_elim_nt(c, ntc);
+        double t = 0.0;
+        for (int rep = 0; rep < 2; ++rep) {
+          if ((e = save_restore(false))) return e;
+          const auto t0 = std::chrono::steady_clock::now();
+          if ((e = solve_batched(c, 2))) return e;
+          HIPTRY(hipStreamSynchronize(c->stream));
+          t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+        if (t < best) {
+          best = t;
+          best_ent = ntc;
+        }
+      }
+    }
     return 0;
   };
   const int rc_trials = trials();
@@ -1248,10 +1302,11 @@ int autotune(mase_ctx* c) {
   c->gamma_snode = best_sn == 1;
   c->dense_mode = best_dense.first;
   c->dense_nb = best_dense.second;
+  apply_elim_nt(c, best_ent);
   if (!rc) rc = save_restore(false);
   if (rc_trials) return fail(rc_trials, err_trials);
   if (rc) return rc;
-  write_tune_cache(c, best_np, best_sn, best_dense.first, best_dense.second);
+  write_tune_cache(c, best_np, best_sn, best_dense.first, best_dense.second, best_ent);
   return 0;
 }
 
@@ -1373,9 +1428,9 @@ struct StreamHost {
 };
 
 // Continuous batching core (mase_solve_stream and its host-buffer variant).
-int stream_solve(mase_ctx* c, const double* z_dev, const double* vm0_dev, const double* va0_dev, int64_t n_total,
-                 double tol, int32_t max_iter, double* vm_dev, double* va_dev, int32_t* iters,
-                 int32_t* converged, StreamHost* io) {
+// The stream's device bookkeeping, grown on demand: slot tables (3 n_snap +
+// 2 ints) and per-snapshot results (2 n_total ints).
+int stream_buffers(mase_ctx* c, int64_t n_total, int32_t** tables, int32_t** results) {
   const int S = c->plan.n_snap;
   int rc = 0;
   if (!c->st_slots && (rc = dalloc(c, (size_t)3 * S + 2, &c->st_slots))) return rc;
@@ -1389,18 +1444,31 @@ int stream_solve(mase_ctx* c, const double* z_dev, const double* vm0_dev, const 
     c->st_out = static_cast<int32_t*>(p);
     c->st_out_cap = n_total;
   }
-  int32_t* slot_id = c->st_slots;
+  *tables = c->st_slots;
+  *results = c->st_out;
+  return 0;
+}
+
+// Continuous batching core.  tables [3 n_snap + 2] and results [2 n_total]
+// are device ints the call owns for its duration.  no_alloc: allocate
+// nothing (no graph instantiation, no autotuning, no host buffers): a graph
+// already instantiated is replayed, else the kernels are launched directly.
+int stream_solve(mase_ctx* c, const double* z_dev, const double* vm0_dev, const double* va0_dev, int64_t n_total,
+                 double tol, int32_t max_iter, double* vm_dev, double* va_dev, int32_t* iters,
+                 int32_t* converged, StreamHost* io, int32_t* tables, int32_t* results, bool no_alloc = false) {
+  const int S = c->plan.n_snap;
+  int rc = 0;
+  int32_t* slot_id = tables;
   int32_t* retire = slot_id + S;
   int32_t* refill = retire + S;
   int32_t* next = refill + S;  // [0] stream position, [1] lowest position still in a slot
-  int32_t* out_iters = c->st_out;
-  int32_t* out_flag = c->st_out + n_total;
+  int32_t* out_iters = results;
+  int32_t* out_flag = results + n_total;
   const int32_t nt = (int32_t)n_total;
   c->h_tol[0] = tol;
   HIPTRY(hipMemcpyAsync(c->dtol, c->h_tol, sizeof(double), hipMemcpyHostToDevice, c->stream));
   // every slot idle, then the first refill loads the first n_snap snapshots
-  HIPTRY(hipMemsetAsync(slot_id, 0xff, sizeof(int32_t) * S, c->stream));
-  HIPTRY(hipMemsetAsync(next, 0, sizeof(int32_t) * 2, c->stream));
+  HIPTRY(launch_stream_init(slot_id, next, S, c->stream));
   // weights: those of the last mase_set_measurements call, else 1/sigma^2
   if (!c->have_z)
     HIPTRY(hipMemcpyAsync((void*)c->d.w, c->w_default, sizeof(double) * c->plan.n_meas, hipMemcpyDeviceToDevice,
@@ -1411,15 +1479,18 @@ int stream_solve(mase_ctx* c, const double* z_dev, const double* vm0_dev, const 
   HIPTRY(launch_stream_copy(c->d, retire, refill, z_dev, vm0_dev, va0_dev, vm_dev, va_dev, c->stream));
   if ((rc = read_flags(c))) return rc;
   c->have_z = true;
-  if (c->opt.autotune && !c->tuned && c->opt.use_graph && !c->prof)
+  if (c->opt.autotune && !c->tuned && c->opt.use_graph && !c->prof && !no_alloc)
     if ((rc = autotune(c)) || (rc = read_flags(c))) return rc;
+  // graph replay, or direct launches (profiling; or nothing may be allocated
+  // and no graph exists yet)
+  const bool use_graph = c->opt.use_graph && !c->prof && (!no_alloc || c->gexec);
   // while snapshots wait, every pass advances all S slots by one of at most
   // n_total * max_iter snapshot-iterations; after the last one has entered,
   // at most max_iter passes remain
   const int64_t limit = (n_total * max_iter + S - 1) / S + max_iter + 1;
   int32_t* hpos = c->h_st_pos;  // [2][2] pinned: next[0..1] of alternate passes
   auto launch_pass = [&]() -> int {
-    if (c->opt.use_graph && !c->prof) {
+    if (use_graph) {
       if (!c->gexec) {
         HIPTRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
         int e0 = launch_batched_iteration(c, c->stream);
@@ -1446,7 +1517,7 @@ int stream_solve(mase_ctx* c, const double* z_dev, const double* vm0_dev, const 
     return n;
   };
   int64_t known_next = S;  // stream position after the last pass whose flags were read
-  if (c->opt.use_graph && !c->prof) {
+  if (use_graph || no_alloc) {
     // one pass always queued ahead: pass j + 1 is enqueued before the host
     // waits for the active flags of pass j (two pinned flag buffers, two
     // events), so the device never idles on the host's turnaround. A pass
@@ -1503,24 +1574,25 @@ int stream_solve(mase_ctx* c, const double* z_dev, const double* vm0_dev, const 
     if ((rc = io->drain(n_total, c->st_ev[0]))) return rc;
   }
   // per-snapshot results straight into the caller's arrays (converged holds
-  // the outcome codes until they are turned into flags below)
-  std::vector<int32_t> hflag;
-  int32_t* flags = converged;
-  if (!flags) {
-    hflag.resize((size_t)n_total);
-    flags = hflag.data();
-  }
+  // the outcome codes until they are turned into flags below; without it the
+  // codes pass through a fixed buffer on the stack)
   if (iters) HIPTRY(hipMemcpyAsync(iters, out_iters, sizeof(int32_t) * n_total, hipMemcpyDeviceToHost, c->stream));
-  HIPTRY(hipMemcpyAsync(flags, out_flag, sizeof(int32_t) * n_total, hipMemcpyDeviceToHost, c->stream));
-  HIPTRY(hipStreamSynchronize(c->stream));
-  if (io) HIPTRY(hipStreamSynchronize(io->cs));
   bool all = true, bad = false;
-  for (int64_t i = 0; i < n_total; ++i) {
-    const int32_t f = flags[i];
-    bad |= f == 2;
-    all &= f == 1;
-    flags[i] = f == 1 ? 1 : 0;
+  constexpr int64_t CH = 1024;
+  int32_t buf[CH];
+  for (int64_t i0 = 0; i0 < n_total; i0 += converged ? n_total : CH) {
+    const int64_t n = converged ? n_total : std::min(CH, n_total - i0);
+    int32_t* flags = converged ? converged : buf;
+    HIPTRY(hipMemcpyAsync(flags, out_flag + i0, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPTRY(hipStreamSynchronize(c->stream));
+    for (int64_t i = 0; i < n; ++i) {
+      const int32_t f = flags[i];
+      bad |= f == 2;
+      all &= f == 1;
+      flags[i] = f == 1 ? 1 : 0;
+    }
   }
+  if (io) HIPTRY(hipStreamSynchronize(io->cs));
   if (bad) return fail(MASE_ERR_NOT_POSDEF, "a snapshot of the stream hit a non-positive pivot");
   return all ? MASE_OK : MASE_NOT_CONVERGED;
 }
@@ -1545,8 +1617,10 @@ int mase_solve_stream(mase_ctx* c, const double* z_dev, const double* vm0_dev, c
   if ((rc = stream_args(c, n_total, tol, max_iter, vm0_dev, va0_dev))) return rc;
   if (n_total == 0) return MASE_OK;
   if (!z_dev || !vm_dev || !va_dev) return fail(MASE_ERR_ARG, "null z or output");
+  int32_t *tables = nullptr, *results = nullptr;
+  if ((rc = stream_buffers(c, n_total, &tables, &results))) return rc;
   return stream_solve(c, z_dev, vm0_dev, va0_dev, n_total, tol, max_iter, vm_dev, va_dev, iters, converged,
-                      nullptr);
+                      nullptr, tables, results);
 }
 
 int64_t mase_stream_host_work(const mase_ctx* c, int64_t n_total, int32_t with_start) {
@@ -1591,8 +1665,10 @@ int mase_solve_stream_host(mase_ctx* c, const double* z_host, const double* vm0_
   // the copy stream starts after everything queued so far on the context's stream
   HIPTRY(hipEventRecord(c->ev_main, c->stream));
   HIPTRY(hipStreamWaitEvent(io.cs, c->ev_main, 0));
+  int32_t *tables = nullptr, *results = nullptr;
+  if ((rc = stream_buffers(c, n_total, &tables, &results))) return rc;
   rc = stream_solve(c, io.z_dev, io.vm0_dev, io.va0_dev, n_total, tol, max_iter, io.vm_dev, io.va_dev, iters,
-                    converged, &io);
+                    converged, &io, tables, results);
   (void)hipStreamSynchronize(io.cs);
   return rc;
 }
@@ -1699,6 +1775,7 @@ int mase_info(const mase_ctx* c, int32_t what, int64_t* value) {
     case MASE_INFO_GAMMA_SUBTREE_GROUPS: v = c->d.n_sn_grp; break;
     case MASE_INFO_GAMMA_DENSE_PANEL: v = c->dense_mode == DENSE_WIDE ? c->dense_nb
                                         : c->dense_mode == DENSE_PANEL16 ? 16 : 0; break;
+    case MASE_INFO_ELIM_THREADS: v = c->elim_nt; break;
     case MASE_INFO_AREA_LDS: {
       int n = 0;
       if (c->area_lds)
@@ -1790,7 +1867,7 @@ int mase_stage_gamma_solve(mase_ctx* c) {
 int mase_stage_update(mase_ctx* c, double* max_abs_dx) {
   int rc = check_device(c);
   if (rc) return rc;
-  HIPTRY(launch_backsolve(c->d, 0, c->plan.n_area, 0, c->plan.n_snap, c->stream));
+  HIPTRY(launch_area_backsolve(c, 0, c->plan.n_area, 0, c->plan.n_snap, c->stream));
   HIPTRY(launch_update(c->d, 0, c->plan.n_snap, c->stream));
   if ((rc = read_flags(c))) return rc;
   if (max_abs_dx) std::memcpy(max_abs_dx, c->h_maxdx, sizeof(double) * c->plan.n_snap);

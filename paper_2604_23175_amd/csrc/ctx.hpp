@@ -33,8 +33,9 @@ struct mase_ctx {
   // area_order positions with the same workgroups per CU (LDS bytes of the
   // largest area in the run, threads per workgroup, Schur block in HBM)
   bool area_lds = false;
-  struct ElClass { int a0, na; size_t lds; int nt; bool tail_hbm; };
+  struct ElClass { int a0, na; size_t lds; int nt; bool tail_hbm; int nt_default; };
   std::vector<ElClass> el_class;
+  int elim_nt = 0;  // threads per LDS elimination workgroup for every class (0: class defaults)
   int dense_mode = 0;                         // DENSE_GLOBAL / DENSE_PANEL16 / DENSE_WIDE
   int dense_nb = 16;                          // panel width of DENSE_WIDE
   bool gamma_snode = false;                   // supernodal boundary elimination

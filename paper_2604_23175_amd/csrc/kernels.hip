@@ -1612,6 +1612,77 @@ __global__ void __launch_bounds__(NT) k_backsolve(Dev d, int sys0, int nsys, int
 }
 
 // ---------------------------------------------------------------------------
+// Stage 4a for an area held in LDS: its factor [0, tail_off) is read once,
+// coalesced, into LDS next to the rhs; the level-by-level substitution of
+// k_backsolve then runs on LDS only (same arithmetic, same order, so the
+// same results).
+// ---------------------------------------------------------------------------
+template <int NT>
+__global__ void __launch_bounds__(NT) k_back_lds(Dev d, int a0, int na, int s0, int ns, int fixed_bnd) {
+  constexpr int G = 8;  // lanes per column
+  int ai, s;
+  area_snap_of_block(blockIdx.x, na, ns, ai, s);
+  s += s0;
+  if (!d.active[s]) return;
+  const int k = d.area_order[a0 + ai];
+  const SysMeta sm = d.sys[k];
+  const AreaMeta am = d.area[k];
+  const double* vals = d.vals + (int64_t)s * d.vstride + sm.val_off;
+  double* rb = d.rhs + (int64_t)s * d.rstride;
+  double* rhs = rb + sm.rhs_off;
+  extern __shared__ double2 lds2[];
+  double* L = reinterpret_cast<double*>(lds2);
+  const int nl = sm.tail_off;  // a multiple of 16
+  double* xl = L + nl;
+  const int tid = threadIdx.x;
+  const double2* v2 = reinterpret_cast<const double2*>(vals);
+  for (int i = tid; i < nl / 2; i += NT) lds2[i] = v2[i];
+  for (int i = tid; i < 2 * sm.ne; i += NT) xl[i] = rhs[i];
+  for (int t = tid; t < sm.nt; t += NT) {
+    // dx_b = E_k dx_Gamma, or 0 for a local step with the boundary fixed
+    const int src = d.tail_src[am.tail_src + t];
+    xl[2 * (sm.ne + t)] = fixed_bnd ? 0.0 : rb[src];
+    xl[2 * (sm.ne + t) + 1] = fixed_bnd ? 0.0 : rb[src + 1];
+  }
+  __syncthreads();
+  const int grp = tid / G, gl = tid % G;
+  for (int lev = sm.nlev - 1; lev >= 0; --lev) {
+    const int b0 = d.bs_ptr[sm.bs_ptr + lev], b1 = d.bs_ptr[sm.bs_ptr + lev + 1];
+    for (int it = b0 + grp; it < b1; it += NT / G) {
+      const int4 b = d.bs_items[it];
+      double t0 = 0.0, t1 = 0.0;
+      for (int c = b.z + gl; c < b.w; c += G) {
+        const int2 u = d.bs_con[c];
+        const double* Lb = L + u.x;
+        const double x0 = xl[u.y], x1 = xl[u.y + 1];
+        t0 += Lb[0] * x0 + Lb[1] * x1;
+        t1 += Lb[2] * x0 + Lb[3] * x1;
+      }
+#pragma unroll
+      for (int off = G / 2; off > 0; off >>= 1) {
+        t0 += __shfl_xor(t0, off, G);
+        t1 += __shfl_xor(t1, off, G);
+      }
+      if (gl == 0) {
+        t0 = xl[b.y] - t0;
+        t1 = xl[b.y + 1] - t1;
+        const double* D = L + b.x;
+        double l00, l10, l11, i00, i11;
+        if (!chol2(D[0], D[1], D[3], l00, l10, l11, i00, i11)) {
+          l00 = l11 = i00 = i11 = 1.0;
+          l10 = 0.0;
+        }
+        const double x1 = t1 * i11;
+        xl[b.y + 1] = x1;
+        xl[b.y] = (t0 - l10 * x1) * i00;
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < 2 * sm.nn; i += NT) rhs[i] = xl[i];
+}
+
+// ---------------------------------------------------------------------------
 // Stage 4b: x += dx for every bus, max |dx| per snapshot, convergence.
 // One workgroup per snapshot.  A snapshot whose factorisation hit a
 // non-positive pivot is frozen without an update.
@@ -1771,6 +1842,14 @@ __global__ void __launch_bounds__(256) k_stream_refill(Dev d, int32_t* slot_id, 
   }
 }
 
+// Every slot idle and the stream position at 0 (a kernel rather than a
+// memset, so that the clearing also behaves inside captured work).
+__global__ void k_stream_init(int32_t* slot_id, int32_t* next, int n_snap) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_snap) slot_id[i] = -1;
+  if (i < 2) next[i] = 0;
+}
+
 // Grid (chunks, n_snap). Slot s hands the state of its finished snapshot to
 // vm_out / va_out [n_total][n_bus] and loads the entering snapshot's
 // measurements (zs [n_total][n_meas]) and starting state (vm0 / va0
@@ -1870,7 +1949,26 @@ hipError_t launch_elim_lds(const Dev& d, int a0, int na, int s0, int ns, size_t 
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_back_lds(const Dev& d, int a0, int na, int s0, int ns, size_t lds, int nt, bool fixed_bnd,
+                           hipStream_t st) {
+  if (na <= 0 || ns <= 0) return hipSuccess;
+  const dim3 grid(na * ns);
+  const int fb = fixed_bnd ? 1 : 0;
+  if (nt == 256) hipLaunchKernelGGL((k_back_lds<256>), grid, dim3(256), lds, st, d, a0, na, s0, ns, fb);
+  else if (nt == 512) hipLaunchKernelGGL((k_back_lds<512>), grid, dim3(512), lds, st, d, a0, na, s0, ns, fb);
+  else if (nt == 1024) hipLaunchKernelGGL((k_back_lds<1024>), grid, dim3(1024), lds, st, d, a0, na, s0, ns, fb);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 hipError_t allow_elim_lds(size_t bytes) {
+  const void* g[3] = {reinterpret_cast<const void*>(&k_back_lds<256>),
+                      reinterpret_cast<const void*>(&k_back_lds<512>),
+                      reinterpret_cast<const void*>(&k_back_lds<1024>)};
+  for (const void* fn : g) {
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
   const void* f[6] = {reinterpret_cast<const void*>(&k_elim_lds<256, false>),
                       reinterpret_cast<const void*>(&k_elim_lds<256, true>),
                       reinterpret_cast<const void*>(&k_elim_lds<512, false>),
@@ -1994,6 +2092,12 @@ hipError_t launch_stream_refill(const Dev& d, int32_t* slot_id, int32_t* next, i
                                 int32_t max_iter, hipStream_t st) {
   hipLaunchKernelGGL(k_stream_refill, dim3(1), dim3(256), 0, st, d, slot_id, next, retire, refill, out_iters,
                      out_flag, n_total, max_iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_init(int32_t* slot_id, int32_t* next, int n_snap, hipStream_t st) {
+  const int n = n_snap > 2 ? n_snap : 2;
+  hipLaunchKernelGGL(k_stream_init, dim3((n + 255) / 256), dim3(256), 0, st, slot_id, next, n_snap);
   return hipGetLastError();
 }
 

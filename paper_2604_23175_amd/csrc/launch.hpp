@@ -20,7 +20,10 @@ hipError_t allow_eliminate_lds(size_t bytes);
 // (256, 512 or 1024), tail_hbm if any of them keeps its Schur block in HBM
 hipError_t launch_elim_lds(const Dev& d, int a0, int na, int s0, int ns, size_t lds, int nt, bool tail_hbm,
                            hipStream_t st);
-hipError_t allow_elim_lds(size_t bytes);
+// the back substitution of the same areas with their factor read into LDS
+hipError_t launch_back_lds(const Dev& d, int a0, int na, int s0, int ns, size_t lds, int nt, bool fixed_bnd,
+                           hipStream_t st);
+hipError_t allow_elim_lds(size_t bytes);  // both kernels
 // supernodal elimination of the boundary system's leading buses; lds: the
 // plan's sn_lds_bytes
 // supernodal elimination of the boundary system's leading buses (one
@@ -51,6 +54,7 @@ hipError_t launch_reset_flags(const Dev& d, hipStream_t st);
 hipError_t launch_stream_refill(const Dev& d, int32_t* slot_id, int32_t* next, int32_t* retire,
                                 int32_t* refill, int32_t* out_iters, int32_t* out_flag, int32_t n_total,
                                 int32_t max_iter, hipStream_t st);
+hipError_t launch_stream_init(int32_t* slot_id, int32_t* next, int n_snap, hipStream_t st);
 hipError_t launch_stream_copy(const Dev& d, const int32_t* retire, const int32_t* refill, const double* zs,
                               const double* vm0, const double* va0, double* vm_out, double* va_out,
                               hipStream_t st);

@@ -25,7 +25,8 @@ INFO = {"n_gamma": 0, "n_boundary_bus": 1, "gamma_tail": 2, "nnz_factor": 3, "ma
         "flops_local": 5, "flops_gamma": 6, "bytes_assembly": 7, "n_snap": 8, "n_area": 9,
         "bytes_condense": 10, "flops_dense": 11, "bytes_backsolve": 12, "flops_gamma_sparse": 13,
         "gamma_levels": 14, "gamma_supernodes": 15, "gamma_supernodal": 16, "pipeline_groups": 17,
-        "gamma_subtree_groups": 18, "gamma_dense_panel": 19, "area_lds": 20}
+        "gamma_subtree_groups": 18, "gamma_dense_panel": 19, "area_lds": 20,
+        "elim_threads": 21}
 STAGES = ("assemble", "condense", "gamma_gather", "gamma_sparse", "gamma_dense", "gamma_back",
           "backsolve", "update", "local")
 MAPS = {"boundary_flag": 0, "meas_area": 1, "gamma_vars": 2, "local_vars": 3,

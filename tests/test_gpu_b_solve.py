@@ -106,13 +106,13 @@ def test_autotune_choice_cached_and_results_match(tmp_path):
     assert conv.all()
     x = m.mase_state()
     assert_state_close(x[0], x[1], xr[0], xr[1], 1e-10)
-    keys = ("pipeline_groups", "gamma_supernodal", "gamma_dense_panel")
+    keys = ("pipeline_groups", "gamma_supernodal", "gamma_dense_panel", "elim_threads")
     choice = tuple(m.mase_info(k) for k in keys)
     m.close()
     lines = [ln.split() for ln in cache.read_text().splitlines() if ln.strip()]
-    assert len(lines) == 1 and len(lines[0]) == 5
+    assert len(lines) == 1 and len(lines[0]) == 6
     panel = {0: 0, 1: 16}.get(int(lines[0][3]), int(lines[0][4]))
-    assert (int(lines[0][1]), int(lines[0][2]), panel) == choice
+    assert (int(lines[0][1]), int(lines[0][2]), panel, int(lines[0][5])) == choice
     # a second context takes the cached choice without tuning again
     m2 = c.ctx(autotune=True, tune_cache=str(cache))
     m2.mase_solve(1e-10, 12)
