@@ -427,8 +427,8 @@ enum {
   MASE_INFO_GAMMA_DENSE_PANEL,    /* columns per LDS panel of the boundary system's dense block
                                      (0: panels read from HBM); the autotuner may change it */
   MASE_INFO_AREA_LDS,             /* areas whose elimination holds their packed storage in LDS (the
-                                     others run the level engine over HBM; the environment
-                                     variable MASE_AREA_LDS=0 selects it for all) */
+                                     others run the level engine over HBM); 0 unless the
+                                     environment variable MASE_AREA_LDS=1 was set at creation */
   MASE_INFO_ELIM_THREADS          /* threads per workgroup of the LDS elimination and back
                                      substitution (0: per launch class, 1024 for areas that take a
                                      whole CU's LDS, 512 up to four per CU, else 256); the

@@ -91,11 +91,13 @@ int upload_plan(mase_ctx* c) {
   std::vector<int32_t> gbus, cd_ptr, up_ptr, rb_ptr, bs_ptr;
   std::vector<I4> cd_items, up_tgt, rb_tgt, bs_items, up_tgt_img;
   std::vector<I2> up_con, rb_con, bs_con, up_con_img, rb_con_img;
-  // the areas' elimination runs in LDS when every area fits (MASE_AREA_LDS=0
-  // selects the level engine over HBM)
+  // the areas' elimination runs the level engine over HBM; MASE_AREA_LDS=1
+  // holds each area that fits in LDS instead (measured slower at the
+  // 9241-bus / 32-area workload: an area image of up to 160 KB leaves one
+  // workgroup per CU)
   {
     const char* env = getenv("MASE_AREA_LDS");
-    c->area_lds = p.lds_areas && !(env && env[0] == '0');
+    c->area_lds = p.lds_areas && env && env[0] == '1';
   }
   for (int i = 0; i <= K; ++i) {
     const SysPlan& s = p.sys[i];
