@@ -270,6 +270,29 @@ int mase_solve_stream_host(mase_ctx* ctx, const double* z_host, const double* vm
                            int64_t n_total, double tol, int32_t max_iter, double* vm_host, double* va_host,
                            int32_t* iters, int32_t* converged, double* work_dev, int64_t work_len);
 
+/*
+ * mase_solve_stream for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, results (bitwise) and return codes, but the
+ * stream's bookkeeping (slot tables and per-snapshot results) lives in a
+ * fixed 4 MiB device array of the library instead of context allocations,
+ * and nothing is allocated: no autotuning, and when the context has no
+ * instantiated iteration graph yet the kernels are launched directly.
+ * Limit: 3 n_snap + 2 + 2 n_total <= 2^20 ints, i.e. n_total at most
+ * mase_stream_noalloc_max(ctx); larger n_total returns MASE_ERR_ARG before
+ * any device work.  Every no-alloc call on one GPU shares that array (one
+ * copy per GPU, held until the process ends), so calls that overlap on one
+ * GPU, from any context or thread, race and must be serialised by the
+ * caller.
+ */
+int mase_solve_stream_noalloc(mase_ctx* ctx, const double* z_dev, const double* vm0_dev, const double* va0_dev,
+                              int64_t n_total, double tol, int32_t max_iter, double* vm_dev, double* va_dev,
+                              int32_t* iters, int32_t* converged);
+
+/* Largest n_total mase_solve_stream_noalloc accepts for this context; -1 on
+ * a null context. */
+int64_t mase_stream_noalloc_max(const mase_ctx* ctx);
+
 /* Doubles of device workspace mase_solve_stream_host needs for n_total
  * snapshots (with_start != 0: starting states given); -1 on a bad argument. */
 int64_t mase_stream_host_work(const mase_ctx* ctx, int64_t n_total, int32_t with_start);

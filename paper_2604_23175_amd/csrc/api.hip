@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -41,6 +42,15 @@ int fail(int code, const std::string& msg) {
 
 
 
+// Fixed device scratch of mase_solve_stream_noalloc: the stream's slot
+// tables (3 n_snap + 2 ints) followed by its per-snapshot results
+// (2 n_total ints).  Each GPU the library runs on holds one copy until the
+// process ends; every no-alloc call on that GPU shares it.  In host code the
+// array's name is not a device address: kernels get the address that
+// hipGetSymbolAddress returns for the current device (scratch_address).
+constexpr int64_t NOALLOC_SCRATCH_INTS = int64_t(1) << 20;  // 4 MiB
+static __device__ __align__(256) int32_t scratch[NOALLOC_SCRATCH_INTS];
+
 namespace {
 
 template <class T>
@@ -51,6 +61,26 @@ int dalloc(mase_ctx* c, size_t n, T** out) {
   if (e != hipSuccess) return fail(MASE_ERR_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
   c->dallocs.push_back(p);
   *out = static_cast<T*>(p);
+  return 0;
+}
+
+// Device address of `scratch` on the current device, resolved once per
+// device (the caller has made the context's device current).
+int scratch_address(int32_t** out) {
+  static std::mutex mu;
+  static std::vector<int32_t*> per_dev;
+  int dev = 0;
+  HIPTRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)per_dev.size() <= dev) per_dev.resize(dev + 1, nullptr);
+  if (!per_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(MASE_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    per_dev[dev] = static_cast<int32_t*>(p);
+  }
+  *out = per_dev[dev];
   return 0;
 }
 
@@ -886,6 +916,7 @@ int mase_create(int32_t n_bus, int32_t n_branch, const int32_t* br_from, const i
   if (!rc && hipEventCreateWithFlags(&c->ev_main, hipEventDisableTiming) != hipSuccess)
     rc = fail(MASE_ERR_HIP, "event creation failed");
   if (!rc) rc = upload_plan(c);
+  if (!rc) rc = scratch_address(&c->noalloc_scratch);
   if (!rc) {
     hipError_t e = launch_pack_state(c->d, nullptr, nullptr, c->d.x, c->stream);
     if (e == hipSuccess) e = launch_reset_flags(c->d, c->stream);
@@ -1623,6 +1654,32 @@ int mase_solve_stream(mase_ctx* c, const double* z_dev, const double* vm0_dev, c
   if ((rc = stream_buffers(c, n_total, &tables, &results))) return rc;
   return stream_solve(c, z_dev, vm0_dev, va0_dev, n_total, tol, max_iter, vm_dev, va_dev, iters, converged,
                       nullptr, tables, results);
+}
+
+int mase_solve_stream_noalloc(mase_ctx* c, const double* z_dev, const double* vm0_dev, const double* va0_dev,
+                              int64_t n_total, double tol, int32_t max_iter, double* vm_dev, double* va_dev,
+                              int32_t* iters, int32_t* converged) {
+  int rc = check_device(c);
+  if (rc) return rc;
+  if ((rc = stream_args(c, n_total, tol, max_iter, vm0_dev, va0_dev))) return rc;
+  if (n_total == 0) return MASE_OK;
+  if (!z_dev || !vm_dev || !va_dev) return fail(MASE_ERR_ARG, "null z or output");
+  const int64_t table_ints = 3 * (int64_t)c->plan.n_snap + 2;
+  if (table_ints + 2 * n_total > NOALLOC_SCRATCH_INTS)
+    return fail(MASE_ERR_ARG, "n_total = " + std::to_string(n_total) + " exceeds the no-alloc stream's limit of " +
+                                  std::to_string(mase_stream_noalloc_max(c)) + " snapshots for this context");
+  if (!c->noalloc_scratch) return fail(MASE_ERR_STATE, "scratch address not resolved");
+  // tables first (k_stream_init clears what must start at zero), then the
+  // results, which every snapshot writes once when it leaves its slot
+  int32_t* tables = c->noalloc_scratch;
+  int32_t* results = tables + table_ints;
+  return stream_solve(c, z_dev, vm0_dev, va0_dev, n_total, tol, max_iter, vm_dev, va_dev, iters, converged,
+                      nullptr, tables, results, /*no_alloc=*/true);
+}
+
+int64_t mase_stream_noalloc_max(const mase_ctx* c) {
+  if (!c) return -1;
+  return std::max<int64_t>(0, (NOALLOC_SCRATCH_INTS - (3 * (int64_t)c->plan.n_snap + 2)) / 2);
 }
 
 int64_t mase_stream_host_work(const mase_ctx* c, int64_t n_total, int32_t with_start) {

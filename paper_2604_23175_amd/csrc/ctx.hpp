@@ -73,6 +73,9 @@ struct mase_ctx {
   int32_t* h_st_active = nullptr;  // [2][n_snap] pinned: active flags of alternate passes
   int32_t* h_st_pos = nullptr;     // [2][2] pinned: stream position, lowest position in a slot
   hipEvent_t st_ev[2] = {};
+  // device address, on this context's GPU, of the library's fixed scratch
+  // array that mase_solve_stream_noalloc uses for the same bookkeeping
+  int32_t* noalloc_scratch = nullptr;
   // per-stage timing
   bool prof = false;
   hipEvent_t pev[2 * MASE_N_STAGE] = {};

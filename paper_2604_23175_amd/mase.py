@@ -37,6 +37,7 @@ SYMBOLS = (
     "mase_default_options", "mase_create", "mase_destroy", "mase_last_error", "mase_strerror",
     "mase_set_measurements", "mase_set_measurements_dev", "mase_set_state", "mase_set_state_dev",
     "mase_gn_iter", "mase_solve", "mase_solve_stream", "mase_solve_stream_host", "mase_stream_host_work",
+    "mase_solve_stream_noalloc", "mase_stream_noalloc_max",
     "mase_state", "mase_state_dev", "mase_objective",
     "mase_eval_h_dev", "mase_info", "mase_export_map", "mase_export_pattern",
     "mase_stage_assemble", "mase_stage_condense", "mase_stage_gamma_assemble",
@@ -97,6 +98,9 @@ def load():
         "mase_solve_stream_host": (ctypes.c_int, [P, P, P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
                                                   P, P, i32p, i32p, P, ctypes.c_int64]),
         "mase_stream_host_work": (ctypes.c_int64, [P, ctypes.c_int64, ctypes.c_int32]),
+        "mase_solve_stream_noalloc": (ctypes.c_int, [P, P, P, P, ctypes.c_int64, ctypes.c_double,
+                                                     ctypes.c_int32, P, P, i32p, i32p]),
+        "mase_stream_noalloc_max": (ctypes.c_int64, [P]),
         "mase_state": (ctypes.c_int, [P, f64p, f64p]),
         "mase_state_dev": (ctypes.c_int, [P, P, P]),
         "mase_objective": (ctypes.c_int, [P, f64p]),
@@ -321,6 +325,28 @@ class Mase:
                                         conv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
         _check(rc, allow=(MASE_OK, MASE_NOT_CONVERGED))
         return iters, conv.astype(bool)
+
+    def mase_solve_stream_noalloc(self, z_dev, vm_out, va_out, vm0_dev=None, va0_dev=None, tol=1e-6,
+                                  max_iter=10):
+        """mase_solve_stream that allocates no device memory (the stream's
+        bookkeeping lives in the library's fixed scratch array); same
+        arguments and results."""
+        n_total = int(z_dev.shape[0])
+        iters = np.zeros(n_total, dtype=np.int32)
+        conv = np.zeros(n_total, dtype=np.int32)
+        sb = (n_total, self.n_bus)
+        zp = _dev(z_dev, (n_total, self.n_meas), "z_dev")
+        v0, a0 = _dev(vm0_dev, sb, "vm0_dev"), _dev(va0_dev, sb, "va0_dev")
+        vo, ao = _dev(vm_out, sb, "vm_out"), _dev(va_out, sb, "va_out")
+        rc = self.lib.mase_solve_stream_noalloc(self.ctx, zp, v0, a0, n_total,
+                                                float(tol), int(max_iter), vo, ao,
+                                                iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                                conv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        _check(rc, allow=(MASE_OK, MASE_NOT_CONVERGED))
+        return iters, conv.astype(bool)
+
+    def mase_stream_noalloc_max(self):
+        return int(self.lib.mase_stream_noalloc_max(self.ctx))
 
     def mase_stream_host_work(self, n_total, with_start=False):
         return int(self.lib.mase_stream_host_work(self.ctx, int(n_total), int(bool(with_start))))
