@@ -496,8 +496,8 @@ def main():
         t_tr = time.perf_counter()
         zt, vmt_, vat_, bad = ws.solved_set(ctx, g, s, args.warm_chains, 64, ws.TRAIN_SEED, dev)
         mlp = mase.Mlp(ctx, hidden=256, max_batch=256)
-        norm = ws.set_normalisation(mlp, zt, vmt_, vat_)
-        ws.init_params(mlp, 0, ws.input_rms(mlp, zt, norm[0], s))
+        norm, in_rms = ws.set_normalisation(mlp, zt, vmt_, vat_)
+        ws.init_params(mlp, 0, in_rms)
         hist = ws.train(mlp, zt, vmt_, vat_, epochs=args.warm_epochs, batch=256, lr=1e-3)
         train_info = {"snapshots": int(zt.shape[0]), "unconverged": bad, "epochs": args.warm_epochs,
                       "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1], "hidden": 256,

@@ -351,6 +351,24 @@ int mase_mlp_get_params(mase_mlp* mlp, float* params);
 /* Normalisation: z_mean [n_meas]; y_mean, y_std [2 n_bus] by variable id. */
 int mase_mlp_set_norm(mase_mlp* mlp, const double* z_mean, const double* y_mean, const double* y_std);
 
+/*
+ * Normalisation from a training set of n snapshots (device, row-major):
+ * z_dev [n][n_meas] measurements, vm_dev, va_dev [n][n_bus] their solved
+ * states.  Sets z_mean to the per-measurement mean of z, y_mean / y_std to
+ * the per-variable mean and sample standard deviation (denominator n - 1,
+ * replaced by 1 where it is at most 1e-6) of the outputs, interleaved per bus
+ * as (theta, |V|), all computed on the device in fixed order.  in_rms
+ * [n_area] (host, may be NULL) receives, per area, the RMS over the area's
+ * inputs and the n snapshots of the normalised input (z - z_mean) / sigma
+ * (used to scale the first layer's initial weights).  n >= 1.
+ */
+int mase_mlp_fit_norm(mase_mlp* mlp, const double* z_dev, const double* vm_dev, const double* va_dev, int32_t n,
+                      double* in_rms);
+
+/* The normalisation in use: z_mean [n_meas], y_mean, y_std [2 n_bus] (host);
+ * MASE_ERR_STATE if none was set. */
+int mase_mlp_get_norm(const mase_mlp* mlp, double* z_mean, double* y_mean, double* y_std);
+
 /* Mean squared error of the standardised outputs over a batch of
  * measurements z_dev [batch][n_meas] against states vm_dev, va_dev
  * [batch][n_bus] (device), and its gradient (host FP32 [n_param], may be

@@ -195,6 +195,62 @@ __global__ void k_adam(float* theta, const float* g, float* m, float* v, uint16_
   tb[i] = to_bf16(th);
 }
 
+// Normalisation statistics of a training set.  Per column of X [n][ncol]
+// (one thread per column, rows in order, so the sums are deterministic): the
+// mean, and with sd the sample standard deviation (denominator n - 1)
+// replaced by 1 where it is at most 1e-6 (a variable that does not vary).
+// Results go to mean[col * ostride + ooff] (and sd likewise).
+__global__ void k_col_stats(const double* X, long long n, int ncol, double* mean, double* sd, int ostride,
+                            int ooff) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= ncol) return;
+  double acc = 0.0;
+  for (long long r = 0; r < n; ++r) acc += X[r * ncol + col];
+  const double mu = acc / (double)n;
+  mean[(long long)col * ostride + ooff] = mu;
+  if (sd) {
+    double q = 0.0;
+    for (long long r = 0; r < n; ++r) {
+      const double e = X[r * ncol + col] - mu;
+      q += e * e;
+    }
+    const double v = n > 1 ? sqrt(q / (double)(n - 1)) : 0.0;
+    sd[(long long)col * ostride + ooff] = v > 1e-6 ? v : 1.0;
+  }
+}
+
+// Mean over the n rows of ((z - mu) / sigma)^2 per measurement.
+__global__ void k_norm_ms(const double* z, long long n, int n_meas, const double* mu, const double* sigma,
+                          double* ms) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_meas) return;
+  double acc = 0.0;
+  for (long long r = 0; r < n; ++r) {
+    const double e = (z[r * n_meas + i] - mu[i]) / sigma[i];
+    acc += e * e;
+  }
+  ms[i] = acc / (double)n;
+}
+
+// Per area (one workgroup each): RMS of the normalised inputs, sqrt of the
+// mean of ms over the area's input measurements (fixed-order reduction).
+__global__ void __launch_bounds__(256) k_area_rms(const double* ms, const int* in_meas, const int* mk, double* rms) {
+  __shared__ double red[256];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  int off = 0;
+  for (int j = 0; j < k; ++j) off += mk[j];
+  const int m = mk[k];
+  double acc = 0.0;
+  for (int i = tid; i < m; i += 256) acc += ms[in_meas[off + i]];
+  red[tid] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) rms[k] = m > 0 ? sqrt(red[0] / (double)m) : 0.0;
+}
+
 __global__ void k_to_bf16(const float* a, uint16_t* b, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = to_bf16(a[i]);
@@ -270,6 +326,7 @@ struct mase_mlp {
   uint16_t *X = nullptr, *H1b = nullptr, *H2b = nullptr, *G3b = nullptr, *G2b = nullptr, *G1b = nullptr;
   float *P1 = nullptr, *P2 = nullptr, *Y = nullptr, *T = nullptr, *G3 = nullptr, *G2 = nullptr, *G1 = nullptr;
   double *zmean = nullptr, *ymean = nullptr, *ystd = nullptr, *sigma = nullptr, *lossp = nullptr;
+  double *zms = nullptr, *area_rms = nullptr;  // input statistics (mase_mlp_fit_norm)
   int *d_in_area = nullptr, *d_in_idx = nullptr, *d_in_meas = nullptr;
   int *d_out_area = nullptr, *d_out_idx = nullptr, *d_out_var = nullptr, *d_mk = nullptr, *d_ok = nullptr;
   long long *d_xoff = nullptr, *d_hoff = nullptr, *d_yoff = nullptr, *d_poff_b1 = nullptr,
@@ -511,6 +568,8 @@ int mase_mlp_create(mase_ctx* c, int32_t hidden, int32_t max_batch, mase_mlp** o
   if (!rc) rc = mdalloc(m, 2 * (size_t)p.n_bus, &m->ymean);
   if (!rc) rc = mdalloc(m, 2 * (size_t)p.n_bus, &m->ystd);
   if (!rc) rc = mupload(m, p.sigma, &m->sigma);
+  if (!rc) rc = mdalloc(m, p.n_meas, &m->zms);
+  if (!rc) rc = mdalloc(m, K, &m->area_rms);
   if (!rc) rc = mdalloc(m, nblk((long long)m->Bmax * m->n_out), &m->lossp);
   if (!rc) rc = mupload(m, in_area, &m->d_in_area);
   if (!rc) rc = mupload(m, in_idx, &m->d_in_idx);
@@ -607,6 +666,39 @@ int mase_mlp_set_norm(mase_mlp* m, const double* z_mean, const double* y_mean, c
   HIPTRY(hipMemcpy(m->ymean, y_mean, sizeof(double) * 2 * m->n_bus, hipMemcpyHostToDevice));
   HIPTRY(hipMemcpy(m->ystd, y_std, sizeof(double) * 2 * m->n_bus, hipMemcpyHostToDevice));
   m->have_norm = true;
+  return 0;
+}
+
+int mase_mlp_fit_norm(mase_mlp* m, const double* z_dev, const double* vm_dev, const double* va_dev, int32_t n,
+                      double* in_rms) {
+  if (!m || !z_dev || !vm_dev || !va_dev) return fail(MASE_ERR_ARG, "null argument");
+  if (n < 1) return fail(MASE_ERR_ARG, "need at least one training snapshot");
+  hipStream_t st = m->ctx->stream;
+  const long long nn = n;
+  const int nb = m->n_bus;
+  hipLaunchKernelGGL(k_col_stats, dim3((m->n_meas + 255) / 256), dim3(256), 0, st, z_dev, nn, m->n_meas,
+                     m->zmean, (double*)nullptr, 1, 0);
+  // outputs interleaved per bus: (theta, |V|)
+  hipLaunchKernelGGL(k_col_stats, dim3((nb + 255) / 256), dim3(256), 0, st, va_dev, nn, nb, m->ymean, m->ystd,
+                     2, 0);
+  hipLaunchKernelGGL(k_col_stats, dim3((nb + 255) / 256), dim3(256), 0, st, vm_dev, nn, nb, m->ymean, m->ystd,
+                     2, 1);
+  hipLaunchKernelGGL(k_norm_ms, dim3((m->n_meas + 255) / 256), dim3(256), 0, st, z_dev, nn, m->n_meas, m->zmean,
+                     m->sigma, m->zms);
+  hipLaunchKernelGGL(k_area_rms, dim3(m->K), dim3(256), 0, st, m->zms, m->d_in_meas, m->d_mk, m->area_rms);
+  HIPTRY(hipGetLastError());
+  if (in_rms) HIPTRY(hipMemcpyAsync(in_rms, m->area_rms, sizeof(double) * m->K, hipMemcpyDeviceToHost, st));
+  HIPTRY(hipStreamSynchronize(st));
+  m->have_norm = true;
+  return 0;
+}
+
+int mase_mlp_get_norm(const mase_mlp* m, double* z_mean, double* y_mean, double* y_std) {
+  if (!m || !z_mean || !y_mean || !y_std) return fail(MASE_ERR_ARG, "null argument");
+  if (!m->have_norm) return fail(MASE_ERR_STATE, "normalisation not set");
+  HIPTRY(hipMemcpy(z_mean, m->zmean, sizeof(double) * m->n_meas, hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(y_mean, m->ymean, sizeof(double) * 2 * m->n_bus, hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(y_std, m->ystd, sizeof(double) * 2 * m->n_bus, hipMemcpyDeviceToHost));
   return 0;
 }
 

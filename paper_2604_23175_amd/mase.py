@@ -44,7 +44,7 @@ SYMBOLS = (
     "mase_stage_gamma_solve", "mase_stage_update", "mase_read_local_system", "mase_read_schur",
     "mase_read_gamma_system", "mase_read_step", "mase_profile", "mase_profile_read",
     "mase_mlp_create", "mase_mlp_destroy", "mase_mlp_info", "mase_mlp_io_map", "mase_mlp_set_params",
-    "mase_mlp_get_params", "mase_mlp_set_norm", "mase_mlp_loss_grad", "mase_mlp_train_step",
+    "mase_mlp_get_params", "mase_mlp_set_norm", "mase_mlp_fit_norm", "mase_mlp_get_norm", "mase_mlp_loss_grad", "mase_mlp_train_step",
     "mase_mlp_predict_dev", "mase_warm_start", "mase_mlp_set_accept_cap", "mase_warm_start_objectives",
 )
 
@@ -126,6 +126,8 @@ def load():
         "mase_mlp_set_params": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_float)]),
         "mase_mlp_get_params": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_float)]),
         "mase_mlp_set_norm": (ctypes.c_int, [P, f64p, f64p, f64p]),
+        "mase_mlp_fit_norm": (ctypes.c_int, [P, P, P, P, ctypes.c_int32, f64p]),
+        "mase_mlp_get_norm": (ctypes.c_int, [P, f64p, f64p, f64p]),
         "mase_mlp_loss_grad": (ctypes.c_int, [P, P, P, P, ctypes.c_int32, f64p, ctypes.POINTER(ctypes.c_float)]),
         "mase_mlp_train_step": (ctypes.c_int, [P, P, P, P, ctypes.c_int32, ctypes.c_float, f64p]),
         "mase_mlp_predict_dev": (ctypes.c_int, [P, P, ctypes.c_int32, P, P]),
@@ -553,6 +555,26 @@ class Mlp:
         ym, yp = _f64(y_mean)
         ys, sp = _f64(y_std)
         _check(self.lib.mase_mlp_set_norm(self.h, zp, yp, sp))
+
+    def mase_mlp_fit_norm(self, z_dev, vm_dev, va_dev):
+        """Normalisation statistics of the training set (device tensors z
+        [n][n_meas], vm / va [n][n_bus]) computed and set by the library;
+        returns the per-area RMS of the normalised inputs."""
+        n = int(z_dev.shape[0])
+        zp = _dev(z_dev, (n, self.owner.n_meas), "z_dev")
+        vp = _dev(vm_dev, (n, self.owner.n_bus), "vm_dev")
+        ap = _dev(va_dev, (n, self.owner.n_bus), "va_dev")
+        rms = np.zeros(self.owner.n_area)
+        _check(self.lib.mase_mlp_fit_norm(self.h, zp, vp, ap, n, rms.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return rms
+
+    def mase_mlp_get_norm(self):
+        z_mean = np.zeros(self.owner.n_meas)
+        y_mean = np.zeros(2 * self.owner.n_bus)
+        y_std = np.zeros(2 * self.owner.n_bus)
+        f = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))  # noqa: E731
+        _check(self.lib.mase_mlp_get_norm(self.h, f(z_mean), f(y_mean), f(y_std)))
+        return z_mean, y_mean, y_std
 
     def mase_mlp_loss_grad(self, z_dev, vm_dev, va_dev, batch, want_grad=True):
         loss = ctypes.c_double()

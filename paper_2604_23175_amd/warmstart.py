@@ -67,13 +67,6 @@ def solved_set(ctx: mase.Mase, grid, sigma, n_chain, chain_len, seed, device, to
     return z_all, vm_all, va_all, n_bad
 
 
-def input_rms(mlp: mase.Mlp, z, z_mean, sigma):
-    """Per-area RMS of the normalised inputs (z - z_mean) / sigma over z."""
-    zn = (z - torch.as_tensor(z_mean, device=z.device)) / torch.as_tensor(sigma, device=z.device)
-    ms = (zn * zn).mean(0).cpu().numpy()
-    return [float(np.sqrt(ms[im].mean())) for im in mlp.in_meas]
-
-
 def init_params(mlp: mase.Mlp, seed=0, in_rms=None):
     """He-normal weights (first layer divided by the area's input RMS, since
     measurements normalised by sigma spread far beyond unit scale), zero
@@ -91,19 +84,13 @@ def init_params(mlp: mase.Mlp, seed=0, in_rms=None):
 
 
 def set_normalisation(mlp: mase.Mlp, z, vm, va):
-    """z mean per measurement; per-variable mean / std of the targets."""
-    z_mean = z.mean(0).cpu().numpy()
-    n_bus = vm.shape[1]
-    y_mean = np.zeros(2 * n_bus)
-    y_std = np.ones(2 * n_bus)
-    y_mean[0::2] = va.mean(0).cpu().numpy()
-    y_mean[1::2] = vm.mean(0).cpu().numpy()
-    sa = va.std(0).cpu().numpy()
-    sv = vm.std(0).cpu().numpy()
-    y_std[0::2] = np.where(sa > 1e-6, sa, 1.0)
-    y_std[1::2] = np.where(sv > 1e-6, sv, 1.0)
-    mlp.mase_mlp_set_norm(z_mean, y_mean, y_std)
-    return z_mean, y_mean, y_std
+    """Normalisation from the training set, computed by the library on the
+    device: z mean per measurement, per-variable mean / std of the targets.
+    Returns ((z_mean, y_mean, y_std), in_rms): the statistics (host copies,
+    for checkpoints) and the per-area RMS of the normalised inputs."""
+    torch.cuda.synchronize()
+    in_rms = mlp.mase_mlp_fit_norm(z, vm, va)
+    return mlp.mase_mlp_get_norm(), [float(r) for r in in_rms]
 
 
 def train(mlp: mase.Mlp, z, vm, va, epochs=30, batch=256, lr=1e-3, lr_final=1e-5, seed=0, log=None):

@@ -55,6 +55,42 @@ def _setup(hidden, B, seed=0):
     return c, ctx, M, flat, (z, vm, va), (z_mean, y_mean, y_std)
 
 
+def test_fit_norm_matches_definitions():
+    # mase_mlp_fit_norm against the plain definitions on the same data: the
+    # column means of z, the mean and sample standard deviation (n - 1) of each
+    # output variable (a constant variable gets 1), and the per-area RMS of
+    # (z - mean) / sigma over the area's inputs
+    say("fit_norm")
+    c = Case("c0", 3, seed=5)
+    ctx = c.ctx()
+    M = mase.Mlp(ctx, hidden=32, max_batch=8)
+    rng = np.random.default_rng(5)
+    n, n_bus = 37, c.g.n_bus
+    z = c.z[rng.integers(0, 3, n)] + rng.normal(0, 0.02, (n, c.net.m))
+    vm = rng.uniform(0.95, 1.05, (n, n_bus))
+    va = rng.normal(-0.2, 0.1, (n, n_bus))
+    va[:, c.slack] = 0.0  # constant: its std is replaced by 1
+    t = lambda a: torch.tensor(a, device=DEV)  # noqa: E731
+    rms = M.mase_mlp_fit_norm(t(z), t(vm), t(va))
+    z_mean, y_mean, y_std = M.mase_mlp_get_norm()
+    np.testing.assert_allclose(z_mean, z.mean(0), rtol=1e-13, atol=1e-13)
+    ym = np.empty(2 * n_bus)
+    ys = np.empty(2 * n_bus)
+    ym[0::2], ym[1::2] = va.mean(0), vm.mean(0)
+    sa, sv = va.std(0, ddof=1), vm.std(0, ddof=1)
+    ys[0::2] = np.where(sa > 1e-6, sa, 1.0)
+    ys[1::2] = np.where(sv > 1e-6, sv, 1.0)
+    np.testing.assert_allclose(y_mean, ym, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(y_std, ys, rtol=1e-10)
+    assert y_std[2 * c.slack] == 1.0
+    zn = (z - z.mean(0)) / c.s
+    ms = (zn * zn).mean(0)
+    want = [np.sqrt(ms[M.in_meas[k]].mean()) for k in range(c.g.n_area)]
+    np.testing.assert_allclose(rms, want, rtol=1e-10)
+    M.close()
+    ctx.close()
+
+
 @pytest.mark.parametrize("hidden,B", [(32, 5), (256, 8)])
 def test_loss_and_gradients_match_oracle(hidden, B):
     say("mlp gradients", hidden, B)
@@ -155,8 +191,8 @@ def test_warm_start_acceptance_rule_and_fallback():
     z, vm, va, bad = ws.solved_set(ctx, g, s_, 48, 32, ws.TRAIN_SEED, DEV)
     assert bad == 0
     M = mase.Mlp(ctx, hidden=256, max_batch=256)
-    norm = ws.set_normalisation(M, z, vm, va)
-    ws.init_params(M, 0, ws.input_rms(M, z, norm[0], s_))
+    norm, in_rms = ws.set_normalisation(M, z, vm, va)
+    ws.init_params(M, 0, in_rms)
     hist = ws.train(M, z, vm, va, epochs=25, batch=256, lr=1e-3)
     assert np.isfinite(hist).all() and hist[-1] < hist[0], hist
     # held-out snapshots
@@ -239,8 +275,8 @@ def test_warm_start_gain_under_calibrated_cap():
     z, vm, va, bad = ws.solved_set(ctx, g, s_, 48, 32, ws.TRAIN_SEED, DEV)
     assert bad == 0
     M = mase.Mlp(ctx, hidden=256, max_batch=256)
-    norm = ws.set_normalisation(M, z, vm, va)
-    ws.init_params(M, 0, ws.input_rms(M, z, norm[0], s_))
+    norm, in_rms = ws.set_normalisation(M, z, vm, va)
+    ws.init_params(M, 0, in_rms)
     ws.train(M, z, vm, va, epochs=25, batch=256, lr=1e-3)
     cap, cal = ws.calibrate_accept_cap(ctx, M, g, s_, DEV, n_chain=2, seed=ws.HELDOUT_SEED)
     # evaluation chains: seeds disjoint from training and calibration
