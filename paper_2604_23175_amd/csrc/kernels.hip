@@ -165,6 +165,23 @@ __device__ __attribute__((always_inline)) inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Plan records as plain structs (kept in registers across loops and
+// barriers; the vector types' copy semantics can leave them on the stack).
+struct alignas(16) Rec4 { int32_t x, y, z, w; };
+struct alignas(8) Rec2 { int32_t x, y; };
+__device__ inline Rec4 ld_rec(const int4* p) { return *reinterpret_cast<const Rec4*>(p); }
+__device__ inline Rec2 ld_rec(const int2* p) { return *reinterpret_cast<const Rec2*>(p); }
+
+// Workgroup barrier for threads that share data through LDS only: it waits
+// for the wave's LDS operations but not for its global loads, so loads of
+// read-only records issued before it stay in flight across it.  Global
+// memory written by one thread and read by another is not ordered by it.
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Value of v held by lane src (uniform across the wave) via the scalar unit.
 __device__ inline double bcast_lane(double v, int src) {
   const long long b = __double_as_longlong(v);
@@ -649,12 +666,37 @@ __global__ void __launch_bounds__(NT) k_elim_lds(Dev d, int a0, int na, int s0, 
   const int32_t* cdp = d.cd_ptr + sm.cd_ptr;
   const int32_t* upp = d.up_ptr + sm.up_ptr;
   const int32_t* rbp = d.rb_ptr + sm.rb_ptr;
+  // Each level's first records per thread (its first column item, its first
+  // two update targets, its first rhs target) are loaded one level ahead.
+  // Threads share values through LDS only, so the barriers between phases
+  // wait for LDS traffic alone and those loads stay in flight across them;
+  // with the Schur block in HBM (TAIL_HBM) its read-modify-writes need the
+  // full workgroup barrier.
+  const Rec4 none{-1, 0, 0, 0};
+  int c0 = 0, c1 = 0, u0 = 0, u1 = 0, r0 = 0, r1 = 0;
+  Rec4 cpre = none, tpre0 = none, tpre1 = none, rpre = none;  // two update targets per pass
+  if (sm.nlev > 0) {
+    c0 = cdp[0]; c1 = cdp[1]; u0 = upp[0]; u1 = upp[1]; r0 = rbp[0]; r1 = rbp[1];
+    if (c0 + tid < c1) cpre = ld_rec(d.cd_items + c0 + tid);
+    if (u0 + tid < u1) tpre0 = ld_rec(d.up_tgt_img + u0 + tid);
+    if (u0 + tid + NT < u1) tpre1 = ld_rec(d.up_tgt_img + u0 + tid + NT);
+    if (r0 + tid < r1) rpre = ld_rec(d.rb_tgt + r0 + tid);
+  }
   for (int lev = 0; lev < sm.nlev; ++lev) {
-    const int c0 = cdp[lev], c1 = cdp[lev + 1];
-    const int u0 = upp[lev], u1 = upp[lev + 1];
-    const int r0 = rbp[lev], r1 = rbp[lev + 1];
+    const bool more = lev + 1 < sm.nlev;
+    const int nc1 = more ? cdp[lev + 2] : c1, nu1 = more ? upp[lev + 2] : u1, nr1 = more ? rbp[lev + 2] : r1;
+    // first contribution of this thread's first rhs target
+    Rec2 rc{0, 0};
+    if (r0 + tid < r1 && rpre.y < rpre.z) rc = ld_rec(d.rb_con_img + rpre.y);
+    // the next level's records, in flight while this level runs
+    Rec4 cnext = none, tnext0 = none, tnext1 = none, rnext = none;
+    if (more && c1 + tid < nc1) cnext = ld_rec(d.cd_items + c1 + tid);
+    if (more && u1 + tid < nu1) tnext0 = ld_rec(d.up_tgt_img + u1 + tid);
+    if (more && u1 + tid + NT < nu1) tnext1 = ld_rec(d.up_tgt_img + u1 + tid + NT);
+    if (more && r1 + tid < nr1) rnext = ld_rec(d.rb_tgt + r1 + tid);
+
     for (int it = c0 + tid; it < c1; it += NT) {
-      const int4 c = d.cd_items[it];
+      const Rec4 c = (it == c0 + tid) ? cpre : ld_rec(d.cd_items + it);
       const double* D = img + c.x;
       double l00, l10, l11, i00, i11;
       if (!chol2(D[0], D[1], D[3], l00, l10, l11, i00, i11)) {
@@ -676,16 +718,16 @@ __global__ void __launch_bounds__(NT) k_elim_lds(Dev d, int a0, int na, int s0, 
         M[1] = make_double2(x01, x11);
       }
     }
-    __syncthreads();
-    for (int it = u0 + tid; it < u1; it += NT) {
-      const int4 t = d.up_tgt_img[it];
+    if constexpr (TAIL_HBM) __syncthreads();
+    else lds_barrier();
+    auto update = [&](const Rec4 t) {
       const bool single = (t.y & UP_SINGLE_FLAG) != 0;
       const int stride = t.y & ~UP_SINGLE_FLAG;
       const int cb = single ? 0 : t.z, ce = single ? 1 : t.w;
       double a00 = 0, a10 = 0, a01 = 0, a11 = 0;
       bool sym = false;
       for (int c = cb; c < ce; ++c) {
-        const int2 u = single ? make_int2(t.z, t.w) : d.up_con_img[c];
+        const Rec2 u = single ? Rec2{t.z, t.w} : ld_rec(d.up_con_img + c);
         const double2 L0 = *reinterpret_cast<const double2*>(img + u.x);
         const double2 L1 = *reinterpret_cast<const double2*>(img + u.x + 2);
         const double2 P0 = *reinterpret_cast<const double2*>(img + u.y);
@@ -703,12 +745,20 @@ __global__ void __launch_bounds__(NT) k_elim_lds(Dev d, int a0, int na, int s0, 
       C[1] = c10 - a10;
       C[stride] = c01 - a01;
       C[stride + 1] = c11 - a11;
+    };
+    for (int it0 = u0 + tid; it0 < u1; it0 += 2 * NT) {
+      const bool first = it0 == u0 + tid;
+      const Rec4 ta = first ? tpre0 : ld_rec(d.up_tgt_img + it0);
+      const Rec4 tb = first ? tpre1 : (it0 + NT < u1 ? ld_rec(d.up_tgt_img + it0 + NT) : none);
+      update(ta);
+      if (tb.x >= 0) update(tb);
     }
     for (int it = r0 + tid; it < r1; it += NT) {
-      const int4 t = d.rb_tgt[it];
+      const bool first = it == r0 + tid;
+      const Rec4 t = first ? rpre : ld_rec(d.rb_tgt + it);
       double b0 = 0, b1 = 0;
       for (int c = t.y; c < t.z; ++c) {
-        const int2 u = d.rb_con_img[c];
+        const Rec2 u = (first && c == t.y) ? rc : ld_rec(d.rb_con_img + c);
         const double* L = img + u.x;
         const double y0 = rhs[u.y], y1 = rhs[u.y + 1];
         b0 += L[0] * y0 + L[2] * y1;
@@ -717,7 +767,13 @@ __global__ void __launch_bounds__(NT) k_elim_lds(Dev d, int a0, int na, int s0, 
       rhs[t.x] -= b0;
       rhs[t.x + 1] -= b1;
     }
-    __syncthreads();
+    if constexpr (TAIL_HBM) __syncthreads();
+    else lds_barrier();
+    c0 = c1; c1 = nc1; u0 = u1; u1 = nu1; r0 = r1; r1 = nr1;
+    cpre = cnext;
+    tpre0 = tnext0;
+    tpre1 = tnext1;
+    rpre = rnext;
   }
   double2* v2 = reinterpret_cast<double2*>(vals);
   for (int i = tid; i < split / 2; i += NT) v2[i] = lds2[i];
@@ -1574,17 +1630,35 @@ __global__ void __launch_bounds__(NT) k_backsolve(Dev d, int sys0, int nsys, int
   }
   __syncthreads();
   const int grp = tid / G, gl = tid % G;
+  // Each level's first item per lane group and that item's first factor
+  // block record per lane are loaded one level ahead.  With x in LDS the
+  // threads share nothing else (the factor is only read), so the barriers
+  // wait for LDS traffic alone and those loads stay in flight across them.
+  const int32_t* bsp = d.bs_ptr + sm.bs_ptr;
+  const int4 none = make_int4(0, 0, 0, 0);
+  int b0 = 0, b1 = 0;
+  int4 bpre = none;
+  int2 upre = make_int2(0, 0);
+  if (sm.nlev > 0) {
+    b0 = bsp[sm.nlev - 1];
+    b1 = bsp[sm.nlev];
+    if (b0 + grp < b1) bpre = d.bs_items[b0 + grp];
+    if (bpre.z + gl < bpre.w) upre = d.bs_con[bpre.z + gl];
+  }
   for (int lev = sm.nlev - 1; lev >= 0; --lev) {
-    const int b0 = d.bs_ptr[sm.bs_ptr + lev], b1 = d.bs_ptr[sm.bs_ptr + lev + 1];
+    const int nb0 = lev > 0 ? bsp[lev - 1] : b0;
+    int4 bnext = none;
+    if (lev > 0 && nb0 + grp < b0) bnext = d.bs_items[nb0 + grp];
     for (int it = b0 + grp; it < b1; it += NT / G) {
-      const int4 b = d.bs_items[it];
+      const bool first = it == b0 + grp;
+      const int4 b = first ? bpre : d.bs_items[it];
       double t0 = 0.0, t1 = 0.0;
       for (int c = b.z + gl; c < b.w; c += G) {
-        const int2 u = d.bs_con[c];
-        const double* L = vals + u.x;
+        const int2 u = (first && c == b.z + gl) ? upre : d.bs_con[c];
+        const double* Lb = vals + u.x;
         const double x0 = xl[u.y], x1 = xl[u.y + 1];
-        t0 += L[0] * x0 + L[1] * x1;
-        t1 += L[2] * x0 + L[3] * x1;
+        t0 += Lb[0] * x0 + Lb[1] * x1;
+        t1 += Lb[2] * x0 + Lb[3] * x1;
       }
 #pragma unroll
       for (int off = G / 2; off > 0; off >>= 1) {
@@ -1605,7 +1679,15 @@ __global__ void __launch_bounds__(NT) k_backsolve(Dev d, int sys0, int nsys, int
         xl[b.y] = (t0 - l10 * x1) * i00;
       }
     }
-    __syncthreads();
+    // the next level's first block record, once its item record is in
+    int2 unext = make_int2(0, 0);
+    if (bnext.z + gl < bnext.w) unext = d.bs_con[bnext.z + gl];
+    if constexpr (XL) lds_barrier();
+    else __syncthreads();
+    b1 = b0;
+    b0 = nb0;
+    bpre = bnext;
+    upre = unext;
   }
   if (XL)
     for (int i = tid; i < 2 * sm.nn; i += NT) rhs[i] = xl[i];
@@ -1646,13 +1728,28 @@ __global__ void __launch_bounds__(NT) k_back_lds(Dev d, int a0, int na, int s0, 
   }
   __syncthreads();
   const int grp = tid / G, gl = tid % G;
+  // records one level ahead, as in k_backsolve; factor and x are in LDS
+  const int32_t* bsp = d.bs_ptr + sm.bs_ptr;
+  const int4 none = make_int4(0, 0, 0, 0);
+  int b0 = 0, b1 = 0;
+  int4 bpre = none;
+  int2 upre = make_int2(0, 0);
+  if (sm.nlev > 0) {
+    b0 = bsp[sm.nlev - 1];
+    b1 = bsp[sm.nlev];
+    if (b0 + grp < b1) bpre = d.bs_items[b0 + grp];
+    if (bpre.z + gl < bpre.w) upre = d.bs_con[bpre.z + gl];
+  }
   for (int lev = sm.nlev - 1; lev >= 0; --lev) {
-    const int b0 = d.bs_ptr[sm.bs_ptr + lev], b1 = d.bs_ptr[sm.bs_ptr + lev + 1];
+    const int nb0 = lev > 0 ? bsp[lev - 1] : b0;
+    int4 bnext = none;
+    if (lev > 0 && nb0 + grp < b0) bnext = d.bs_items[nb0 + grp];
     for (int it = b0 + grp; it < b1; it += NT / G) {
-      const int4 b = d.bs_items[it];
+      const bool first = it == b0 + grp;
+      const int4 b = first ? bpre : d.bs_items[it];
       double t0 = 0.0, t1 = 0.0;
       for (int c = b.z + gl; c < b.w; c += G) {
-        const int2 u = d.bs_con[c];
+        const int2 u = (first && c == b.z + gl) ? upre : d.bs_con[c];
         const double* Lb = L + u.x;
         const double x0 = xl[u.y], x1 = xl[u.y + 1];
         t0 += Lb[0] * x0 + Lb[1] * x1;
@@ -1677,7 +1774,13 @@ __global__ void __launch_bounds__(NT) k_back_lds(Dev d, int a0, int na, int s0, 
         xl[b.y] = (t0 - l10 * x1) * i00;
       }
     }
-    __syncthreads();
+    int2 unext = make_int2(0, 0);
+    if (bnext.z + gl < bnext.w) unext = d.bs_con[bnext.z + gl];
+    lds_barrier();
+    b1 = b0;
+    b0 = nb0;
+    bpre = bnext;
+    upre = unext;
   }
   for (int i = tid; i < 2 * sm.nn; i += NT) rhs[i] = xl[i];
 }
