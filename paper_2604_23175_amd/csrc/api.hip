@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -240,14 +241,59 @@ int upload_plan(mase_ctx* c) {
       // roles are exactly bus v's rhs contributions, in the same order
       std::unordered_map<int32_t, int32_t> diag_bus;
       for (int v = 0; v < p.sys[k].nn; ++v) diag_bus[p.sys[k].blk_off(v, v)] = v;
-      for (int i : ord) {
-        const I4& q = src[i];
-        slot.push_back({q.x, q.y, q.z + (int32_t)scon.size(), q.w + (int32_t)scon.size()});
-        slot_rhs.push_back(q.y < 0 ? 2 * diag_bus.at(img[i]) : -1);
+      // Contributions go to the device in P/Q pairs: the active and reactive
+      // rows of one bus (injections) or one branch end (flows) have the same
+      // support and roles, so one record evaluates both from one set of
+      // branch terms.  Record {family | loc << 3, measurement of the P row or
+      // -1, measurement of the Q row or -1, roles}; family VM, PINJ (for both
+      // injections), PF or PT.
+      std::map<std::pair<int, int>, int> row_of;  // (type, loc) -> row
+      for (size_t r = 0; r < t.row_type.size(); ++r) row_of[{t.row_type[r], t.row_loc[r]}] = (int)r;
+      auto partner = [&](int r) {
+        const int ty = t.row_type[r];
+        if (ty == MASE_VM) return -1;
+        const bool isp = ty == MASE_PINJ || ty == MASE_PF || ty == MASE_PT;
+        auto it = row_of.find({isp ? ty + 1 : ty - 1, t.row_loc[r]});
+        return it == row_of.end() ? -1 : it->second;
+      };
+      // Pair records of every slot, then laid out for the kernel: slot i of
+      // the area is handled by lane i % 64 of a wave, so the slots of each
+      // run of 64 (one wave's, in this order) store their c-th records side
+      // by side, at chunk base + c * 64 + lane; the chunk is as long as its
+      // longest list (the slots are sorted by list length, so little is
+      // padding).  Rows are the area's local rows.
+      std::vector<std::vector<I4>> recs(ord.size());
+      for (size_t n = 0; n < ord.size(); ++n) {
+        const I4& q = src[ord[n]];
+        std::map<std::pair<int, int>, bool> here;  // (row, roles) in this slot
+        for (int c = q.z; c < q.w; ++c) here[{t.scon[c].x, t.scon[c].y}] = true;
+        for (int c = q.z; c < q.w; ++c) {
+          const int r = t.scon[c].x, roles = t.scon[c].y, ty = t.row_type[r];
+          const int o = partner(r);
+          const bool paired = o >= 0 && here.count({o, roles});
+          const bool isq = ty == MASE_QINJ || ty == MASE_QF || ty == MASE_QT;
+          if (paired && isq) continue;  // taken with its P row
+          const int fam = ty == MASE_VM ? MASE_VM : (ty <= MASE_QINJ ? MASE_PINJ : (ty <= MASE_QF ? MASE_PF : MASE_PT));
+          int32_t rp = -1, rq = -1;
+          if (isq) rq = r;
+          else { rp = r; if (paired) rq = o; }
+          recs[n].push_back({fam | (t.row_loc[r] << 3), rp, rq, roles});
+        }
+      }
+      for (size_t c0 = 0; c0 < ord.size(); c0 += 64) {
+        const size_t c1 = std::min(ord.size(), c0 + 64);
+        size_t len = 0;
+        for (size_t n = c0; n < c1; ++n) len = std::max(len, recs[n].size());
+        const int32_t base = (int32_t)scon.size();
+        scon.resize(scon.size() + 64 * len, I4{0, -1, -1, 0});
+        for (size_t n = c0; n < c1; ++n) {
+          for (size_t c = 0; c < recs[n].size(); ++c) scon[base + c * 64 + (n - c0)] = recs[n][c];
+          const I4& q = src[ord[n]];
+          slot.push_back({q.x, q.y, base, (int32_t)recs[n].size()});
+          slot_rhs.push_back(q.y < 0 ? 2 * diag_bus.at(img[ord[n]]) : -1);
+        }
       }
     }
-    for (const I2& cc : t.scon)
-      scon.push_back({t.row_type[cc.x], t.row_loc[cc.x], t.row_meas[cc.x], cc.y});
     // rhs items {cbeg, cend, bus}, by decreasing contribution count
     a.rslot = (int32_t)rslot.size();
     {
@@ -270,13 +316,27 @@ int upload_plan(mase_ctx* c) {
   HIPTRY(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   HIPTRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
   // stage branch records in LDS when every area fits
-  size_t lds_br = 0, lds_nobr = 0;
+  // (and the rows' weights and measurements, when they fit as well)
+  size_t lds_br = 0, lds_nobr = 0, lds_br_wz = 0, lds_nobr_wz = 0;
   for (int k = 0; k < K; ++k) {
-    lds_br = std::max(lds_br, assemble_lds_bytes(am[k].nn, am[k].nbr, true));
-    lds_nobr = std::max(lds_nobr, assemble_lds_bytes(am[k].nn, am[k].nbr, false));
+    lds_br = std::max(lds_br, assemble_lds_bytes(am[k].nn, am[k].nbr, true, 0));
+    lds_nobr = std::max(lds_nobr, assemble_lds_bytes(am[k].nn, am[k].nbr, false, 0));
+    lds_br_wz = std::max(lds_br_wz, assemble_lds_bytes(am[k].nn, am[k].nbr, true, am[k].nrow));
+    lds_nobr_wz = std::max(lds_nobr_wz, assemble_lds_bytes(am[k].nn, am[k].nbr, false, am[k].nrow));
   }
-  c->br_lds = lds_br <= (size_t)maxlds;
-  lds = c->br_lds ? lds_br : lds_nobr;
+  c->d.asm_wz = 0;
+  if (lds_br_wz <= (size_t)maxlds) {
+    c->br_lds = true;
+    c->d.asm_wz = 1;
+    lds = lds_br_wz;
+  } else if (lds_nobr_wz <= (size_t)maxlds) {
+    c->br_lds = false;
+    c->d.asm_wz = 1;
+    lds = lds_nobr_wz;
+  } else {
+    c->br_lds = lds_br <= (size_t)maxlds;
+    lds = c->br_lds ? lds_br : lds_nobr;
+  }
   // an area too large to stage in LDS: every area stages in its own region
   // of HBM instead (same arithmetic)
   int64_t asm_stride = 0;
@@ -286,6 +346,7 @@ int upload_plan(mase_ctx* c) {
       asm_stride += ((8 * (int64_t)am[k].nn + 2 * (int64_t)am[k].nbr) + 31) / 32 * 32;
     }
     c->br_lds = false;
+    c->d.asm_wz = 0;
     lds = 0;
   }
   c->lds_asm = lds;

@@ -106,6 +106,8 @@ struct Dev {
   // AreaMeta::stage_off (nullptr: staging in LDS)
   double* asm_stage;
   int64_t asm_stride;
+  // 1: the assembly stages its rows' weights and measurements in LDS
+  int32_t asm_wz;
 };
 
 }  // namespace mase

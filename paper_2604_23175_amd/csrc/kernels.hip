@@ -141,6 +141,72 @@ struct Asm {
     if (bp == slack_local) pt = 0.0;
     if (bq == slack_local) qt = 0.0;
   }
+
+  // Partials, with respect to the bus across branch e from bus u, of the
+  // active (dPt, dPv) and reactive (dQt, dQv) injections at u: those of
+  // the two flows at u's end of e.  Returns that bus.
+  __device__ int inj_nbr_pq(int u, int e, double& dPt, double& dPv, double& dQt, double& dQv) const {
+    const BrL B = branch(e);
+    const bool from = (B.lf == u);
+    const int o = from ? B.lt : B.lf;
+    const double2 c = cs[e];
+    const double sn = from ? c.y : -c.y;
+    const double va = xs[u].y, vo = xs[o].y;
+    const double A = B.g * c.x + B.bs * sn;
+    const double Bq = B.g * sn - B.bs * c.x;
+    dPt = -(va * vo * Bq);
+    dPv = -va * A;
+    dQt = va * vo * A;
+    dQv = -va * Bq;
+    return o;
+  }
+
+  // One contribution record of a P/Q pair {family | loc << 3, meas P, meas Q,
+  // roles}: values hP, hQ and the partials of both rows with respect to the
+  // buses picked by roles rp (P: pt, pv; Q: qt... as Pp*, Qp*) and rq
+  // (Pq*, Qq*).  Family VM: the P slot carries |V| (partials 0 and 1).
+  __device__ void eval_pq(int fam, int loc, int rp, int rq, double& hP, double& hQ, double& Ppt,
+                          double& Ppv, double& Pqt, double& Pqv, double& Qpt, double& Qpv, double& Qqt,
+                          double& Qqv) const {
+    int bp, bq;
+    if (fam == VM) {
+      hP = xs[loc].y;
+      hQ = 0.0;
+      Ppt = Pqt = Qpt = Qqt = 0.0;
+      Ppv = Pqv = 1.0;
+      Qpv = Qqv = 0.0;
+      bp = bq = loc;
+    } else if (fam < QINJ) {
+      const double* a = agg + 6 * loc;
+      hP = a[0];
+      hQ = a[1];
+      if (rp == ROLE_SELF) { Ppt = a[2]; Ppv = a[3]; Qpt = a[4]; Qpv = a[5]; bp = loc; }
+      else bp = inj_nbr_pq(loc, rp, Ppt, Ppv, Qpt, Qpv);
+      if (rq == ROLE_SELF) { Pqt = a[2]; Pqv = a[3]; Qqt = a[4]; Qqv = a[5]; bq = loc; }
+      else if (rq == rp) { Pqt = Ppt; Pqv = Ppv; Qqt = Qpt; Qqv = Qpv; bq = bp; }
+      else bq = inj_nbr_pq(loc, rq, Pqt, Pqv, Qqt, Qqv);
+    } else {
+      const BrL B = branch(loc);
+      const bool to = (fam == PT);
+      const int a = to ? B.lt : B.lf, o = to ? B.lf : B.lt;
+      const double2 c = cs[loc];
+      const double sn = to ? -c.y : c.y;
+      const double va = xs[a].y, vo = xs[o].y;
+      const double A = B.g * c.x + B.bs * sn;
+      const double Bq = B.g * sn - B.bs * c.x;
+      const double bsh = B.bs + B.hb;
+      hP = B.g * va * va - va * vo * A;
+      hQ = -bsh * va * va - va * vo * Bq;
+      const double Pta = va * vo * Bq, Ptv = 2.0 * B.g * va - vo * A, Pov = -va * A;
+      const double Qta = -va * vo * A, Qtv = -2.0 * bsh * va - vo * Bq, Qov = -va * Bq;
+      if (rp == ROLE_SELF) { Ppt = Pta; Ppv = Ptv; Qpt = Qta; Qpv = Qtv; bp = a; }
+      else { Ppt = -Pta; Ppv = Pov; Qpt = -Qta; Qpv = Qov; bp = o; }
+      if (rq == ROLE_SELF) { Pqt = Pta; Pqv = Ptv; Qqt = Qta; Qqv = Qtv; bq = a; }
+      else { Pqt = -Pta; Pqv = Pov; Qqt = -Qta; Qqv = Qov; bq = o; }
+    }
+    if (bp == slack_local) Ppt = Qpt = 0.0;
+    if (bq == slack_local) Pqt = Qqt = 0.0;
+  }
 };
 
 __device__ inline double block_sum(double v, double* red) {
@@ -335,10 +401,19 @@ __global__ void __launch_bounds__(ASM_NT) k_assemble(Dev d, int a0, int na, int 
   double2* cs = xs + am.nn;
   double* agg = reinterpret_cast<double*>(cs + am.nbr);
   BrL* brl = reinterpret_cast<BrL*>(agg + 6 * am.nn);
+  // weight and measurement of every row of the area (assembly with staging in LDS)
+  double2* wzs = reinterpret_cast<double2*>(brl + (BR_LDS ? am.nbr : 0));
   const double2* xsnap = d.x + (int64_t)s * d.n_bus;
   const int tid = threadIdx.x, nt = blockDim.x;
 
   for (int v = tid; v < am.nn; v += nt) xs[v] = xsnap[d.gbus[sm.gbus + v]];
+  if (mode == MODE_ASSEMBLE && d.asm_wz && !STAGE_HBM) {
+    const double* zsn = d.z + (int64_t)s * d.n_meas;
+    for (int r = tid; r < am.nrow; r += nt) {
+      const int m = d.rowrec[am.row + r].z;
+      wzs[r] = make_double2(d.w[m], zsn[m]);
+    }
+  }
   if (BR_LDS)
     for (int e = tid; e < am.nbr; e += nt) {
       const int b = am.br + e;
@@ -404,44 +479,67 @@ __global__ void __launch_bounds__(ASM_NT) k_assemble(Dev d, int a0, int na, int 
   // contributions with equal roles, which are exactly bus v's rows.
   double* vals = d.vals + (int64_t)s * d.vstride + sm.val_off;
   double* rhs = d.rhs + (int64_t)s * d.rstride + sm.rhs_off;
-  for (int i = tid; i < am.nslot; i += nt) {
-    const int4 sl = d.slot[am.slot + i];
-    const int rb2 = d.slot_rhs[am.slot + i];
+  // Each record is a P/Q pair of rows (or a single row): its two rows share
+  // the branch terms, so both are evaluated at once.  A wave's 64 lanes
+  // handle 64 consecutive slots, whose c-th records lie side by side (one
+  // coalesced load per step); the weights and measurements of the area's
+  // rows are staged in LDS (wz) when they fit.  The next record is in flight
+  // while one is evaluated, and the next slot's header and first record are
+  // requested before this slot's results are stored.
+  const double2* wz = d.asm_wz ? reinterpret_cast<const double2*>(wzs) : nullptr;
+  auto wz_of = [&](int r) -> double2 {
+    if (wz) return wz[r];
+    const int m = d.rowrec[am.row + r].z;
+    return make_double2(d.w[m], zs[m]);
+  };
+  const int lane = tid & 63;
+  const int4 zero4 = make_int4(0, -1, -1, 0);
+  int i = tid;
+  int4 sl = i < am.nslot ? d.slot[am.slot + i] : zero4;
+  int rb2 = i < am.nslot ? d.slot_rhs[am.slot + i] : -1;
+  int4 r0 = (i < am.nslot && sl.w > 0) ? d.scon[sl.z + lane] : zero4;
+  for (; i < am.nslot; i += nt) {
     double c00 = 0, c10 = 0, c01 = 0, c11 = 0, b0 = 0, b1 = 0;
-    // two-stage prefetch: the record of contribution c+2 and the weight (and
-    // measurement) of c+1 are in flight while c is evaluated
-    int4 r0 = make_int4(0, 0, 0, 0), r1 = r0;
-    double w0 = 0.0, z0 = 0.0;
-    if (sl.z < sl.w) {
-      r0 = d.scon[sl.z];
-      w0 = d.w[r0.z];
-      if (rb2 >= 0) z0 = zs[r0.z];
-    }
-    if (sl.z + 1 < sl.w) r1 = d.scon[sl.z + 1];
-    for (int c = sl.z; c < sl.w; ++c) {
+    for (int c = 0; c < sl.w; ++c) {
       const int4 cr = r0;
-      const double wr = w0, zr = z0;
-      r0 = r1;
-      if (c + 1 < sl.w) {
-        w0 = d.w[r1.z];
-        if (rb2 >= 0) z0 = zs[r1.z];
-      }
-      if (c + 2 < sl.w) r1 = d.scon[c + 2];
+      if (c + 1 < sl.w) r0 = d.scon[sl.z + (c + 1) * 64 + lane];
       const int rp = cr.w & 0xFFFF, rq = (cr.w >> 16) & 0xFFFF;
-      double h, pt, pv, qt, qv;
-      X.eval2(cr, rp, rq, h, pt, pv, qt, qv);
-      if (rb2 >= 0 && rp == rq) {
-        const double wres = wr * (zr - h);
-        b0 += pt * wres;
-        b1 += pv * wres;
+      double hP, hQ, Ppt, Ppv, Pqt, Pqv, Qpt, Qpv, Qqt, Qqv;
+      X.eval_pq(cr.x & 7, cr.x >> 3, rp, rq, hP, hQ, Ppt, Ppv, Pqt, Pqv, Qpt, Qpv, Qqt, Qqv);
+      if (cr.y >= 0) {
+        const double2 wzp = wz_of(cr.y);
+        if (rb2 >= 0 && rp == rq) {
+          const double wres = wzp.x * (wzp.y - hP);
+          b0 += Ppt * wres;
+          b1 += Ppv * wres;
+        }
+        Ppt *= wzp.x;
+        Ppv *= wzp.x;
+        c00 += Ppt * Pqt;
+        c10 += Ppv * Pqt;
+        c01 += Ppt * Pqv;
+        c11 += Ppv * Pqv;
       }
-      pt *= wr;
-      pv *= wr;
-      c00 += pt * qt;
-      c10 += pv * qt;
-      c01 += pt * qv;
-      c11 += pv * qv;
+      if (cr.z >= 0) {
+        const double2 wzq = wz_of(cr.z);
+        if (rb2 >= 0 && rp == rq) {
+          const double wres = wzq.x * (wzq.y - hQ);
+          b0 += Qpt * wres;
+          b1 += Qpv * wres;
+        }
+        Qpt *= wzq.x;
+        Qpv *= wzq.x;
+        c00 += Qpt * Qqt;
+        c10 += Qpv * Qqt;
+        c01 += Qpt * Qqv;
+        c11 += Qpv * Qqv;
+      }
     }
+    // the next slot, requested before the stores below
+    const int in = i + nt;
+    const int4 sln = in < am.nslot ? d.slot[am.slot + in] : zero4;
+    const int rbn = in < am.nslot ? d.slot_rhs[am.slot + in] : -1;
+    r0 = (in < am.nslot && sln.w > 0) ? d.scon[sln.z + lane] : zero4;
     const bool diag = sl.y < 0;
     const int stride = diag ? -sl.y : sl.y;
     if (diag) c01 = c10;
@@ -455,6 +553,8 @@ __global__ void __launch_bounds__(ASM_NT) k_assemble(Dev d, int a0, int na, int 
       rhs[rb2] = b0;
       rhs[rb2 + 1] = b1;
     }
+    sl = sln;
+    rb2 = rbn;
   }
 }
 
@@ -500,25 +600,27 @@ __global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int
   const int32_t* upp = d.up_ptr + sm.up_ptr;
   const int32_t* rbp = d.rb_ptr + sm.rb_ptr;
   int nc0 = 0, nc1 = 0;
-  int4 cpre = make_int4(0, 0, 0, 0);
+  Rec4 cpre{0, 0, 0, 0};
   if (sm.nlev > 0) {
     nc0 = cdp[0];
     nc1 = cdp[1];
-    if (nc0 + tid < nc1) cpre = d.cd_items[nc0 + tid];
+    if (nc0 + tid < nc1) cpre = ld_rec(d.cd_items + nc0 + tid);
   }
   for (int lev = 0; lev < sm.nlev; ++lev) {
     const int c0 = nc0, c1 = nc1;
     const int u0 = upp[lev], u1 = upp[lev + 1];
     const int r0 = rbp[lev], r1 = rbp[lev + 1];
-    int4 tpre[UB];
+    Rec4 tpre[UB];
 #pragma unroll
     for (int q = 0; q < UB; ++q) {
       const int it = u0 + tid + q * NT;
-      tpre[q] = (it < u1) ? d.up_tgt[it] : make_int4(-1, 0, 0, 0);
+      tpre[q] = Rec4{-1, 0, 0, 0};
+      if (it < u1) tpre[q] = ld_rec(d.up_tgt + it);
     }
-    const int4 rpre = (r0 + tid < r1) ? d.rb_tgt[r0 + tid] : make_int4(0, 0, 0, 0);
+    Rec4 rpre{0, 0, 0, 0};
+    if (r0 + tid < r1) rpre = ld_rec(d.rb_tgt + r0 + tid);
     for (int it = c0 + tid; it < c1; it += NT) {
-      const int4 c = (it == c0 + tid) ? cpre : d.cd_items[it];
+      const Rec4 c = (it == c0 + tid) ? cpre : ld_rec(d.cd_items + it);
       const double* D = vals + c.x;
       double l00, l10, l11, i00, i11;
       if (!chol2(D[0], D[1], D[3], l00, l10, l11, i00, i11)) {
@@ -549,16 +651,20 @@ __global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int
     if (lev + 1 < sm.nlev) {
       nc0 = c1;
       nc1 = cdp[lev + 2];
-      if (nc0 + tid < nc1) cpre = d.cd_items[nc0 + tid];
+      if (nc0 + tid < nc1) cpre = ld_rec(d.cd_items + nc0 + tid);
     }
     for (int it0 = u0 + tid; it0 < u1; it0 += NT * UB) {
-      int4 t[UB];
+      Rec4 t[UB];
       double c00[UB], c10[UB], c01[UB], c11[UB];
 #pragma unroll
       for (int q = 0; q < UB; ++q) {
         const int it = it0 + q * NT;
-        if (it0 == u0 + tid) t[q] = tpre[q];
-        else t[q] = (it < u1) ? d.up_tgt[it] : make_int4(-1, 0, 0, 0);
+        if (it0 == u0 + tid) {
+          t[q] = tpre[q];
+        } else {
+          t[q] = Rec4{-1, 0, 0, 0};
+          if (it < u1) t[q] = ld_rec(d.up_tgt + it);
+        }
       }
 #pragma unroll
       for (int q = 0; q < UB; ++q) {
@@ -579,7 +685,7 @@ __global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int
         const int cb = single ? 0 : t[q].z, ce = single ? 1 : t[q].w;
         bool sym = false;
         for (int c = cb; c < ce; ++c) {
-          const int2 u = single ? make_int2(t[q].z, t[q].w) : d.up_con[c];
+          const Rec2 u = single ? Rec2{t[q].z, t[q].w} : ld_rec(d.up_con + c);
           const double2 L0 = *reinterpret_cast<const double2*>(lst + u.x);
           const double2 L1 = *reinterpret_cast<const double2*>(lst + u.x + 2);
           const double2 P0 = *reinterpret_cast<const double2*>(lst + u.y);
@@ -599,10 +705,10 @@ __global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int
       }
     }
     for (int it = r0 + tid; it < r1; it += NT) {
-      const int4 t = (it == r0 + tid) ? rpre : d.rb_tgt[it];
+      const Rec4 t = (it == r0 + tid) ? rpre : ld_rec(d.rb_tgt + it);
       double b0 = 0, b1 = 0;
       for (int c = t.y; c < t.z; ++c) {
-        const int2 u = d.rb_con[c];
+        const Rec2 u = ld_rec(d.rb_con + c);
         const double* L = lst + u.x;
         const double y0 = lst[u.y], y1 = lst[u.y + 1];
         b0 += L[0] * y0 + L[2] * y1;
@@ -1993,8 +2099,9 @@ constexpr size_t BACKSOLVE_LDS_MAX = 65536;  // rhs staged in LDS up to 4096 bus
 constexpr size_t ELIM_LDS_MAX = 65536;       // elimination staging + rhs in LDS up to this size
 constexpr int GAMMA_NT = 1024; // level kernels over the one boundary system
 
-size_t assemble_lds_bytes(int nn, int nbr, bool br_lds) {
-  return 16 * (size_t)nn + 16 * (size_t)nbr + 48 * (size_t)nn + (br_lds ? sizeof(BrL) * (size_t)nbr : 0);
+size_t assemble_lds_bytes(int nn, int nbr, bool br_lds, int nrow) {
+  return 16 * (size_t)nn + 16 * (size_t)nbr + 48 * (size_t)nn + (br_lds ? sizeof(BrL) * (size_t)nbr : 0) +
+         16 * (size_t)nrow;
 }
 
 hipError_t launch_assemble(const Dev& d, int a0, int na, int s0, int ns, int mode, size_t lds,

@@ -8,8 +8,9 @@
 namespace mase {
 
 // LDS bytes of k_assemble for an area with nn local buses and nbr branches;
-// br_lds: branch records staged in LDS too.
-size_t assemble_lds_bytes(int nn, int nbr, bool br_lds);
+// br_lds: branch records staged in LDS too; nrow > 0: also the weights and
+// measurements of the area's nrow rows.
+size_t assemble_lds_bytes(int nn, int nbr, bool br_lds, int nrow);
 hipError_t launch_assemble(const Dev& d, int a0, int na, int s0, int ns, int mode, size_t lds,
                            bool br_lds, hipStream_t st);
 // lds: dynamic LDS bytes for the level staging (max over the launched systems)
