@@ -371,6 +371,43 @@ def warm_rank_bound(n_chain=313, chain_len=64, hidden=256):
                       "per_area": per_area}))
 
 
+def batch_sweep(sizes, reps=3):
+    """Per-launch time of every stage kernel for batches of the given sizes
+    on the benchmark grid: assembly and condensation at the base state, then
+    one full Gauss-Newton iteration, each timed by HIP events around the
+    kernels (mase_profile); one JSON line per size.  Shows which stages grow
+    with the batch (throughput-bound) and which do not (latency chains)."""
+    import torch
+    from gridgen import synth
+    from paper_2604_23175_amd import mase
+    dev = torch.device("cuda:0")
+    g = synth.make_config(WORKLOAD)
+    t, a, s = synth.measurement_set(g.n_bus, g.n_branch)
+    for ns in sizes:
+        b = synth.make_batch(g, ns, 0)
+        va = b.va_true - b.va_true[:, [g.slack]]
+        ctx = mase.Mase.from_grid(g, t, a, s, ns)
+        h = torch.empty((ns, t.size), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        ctx.mase_eval_h_dev(torch.tensor(b.vm_true, device=dev), torch.tensor(va, device=dev), h)
+        torch.cuda.synchronize()
+        z = h + torch.tensor(s, device=dev) * torch.tensor(b.eps, device=dev)
+        torch.cuda.synchronize()
+        ctx.mase_set_measurements_dev(z)
+        ctx.mase_set_state_dev(None, None)
+        ctx.mase_gn_iter()
+        ctx.mase_profile(True)
+        for _ in range(reps):
+            ctx.mase_set_state_dev(None, None)
+            ctx.mase_gn_iter()
+        prof = ctx.mase_profile_read()
+        ctx.mase_profile(False)
+        print(json.dumps({"workload": WORKLOAD_NAMES[WORKLOAD], "snapshots": ns,
+                          "ms_per_launch": {k: v["ms"] / v["launches"] for k, v in prof.items() if v["launches"]}}),
+              flush=True)
+        ctx.close()
+
+
 def single_snapshot_gpu(dev):
     """The paper's protocol on the GPU: one 2869-bus snapshot (8 areas), host
     measurements in, host states out, mean of runs 2-11 (Section 5.1)."""
@@ -427,6 +464,9 @@ def main():
     ap.add_argument("--local-sweep", default=None,
                     help="comma-separated local-step counts (boundary held, Eq. 6) before each condensed "
                          "step; the first should be 0 (one JSON line each)")
+    ap.add_argument("--batch-sweep", default=None,
+                    help="comma-separated batch sizes: per-launch time of every stage kernel for each "
+                         "(one JSON line each)")
     ap.add_argument("--warm-rank-bound", action="store_true",
                     help="lower bound of the standardised training MSE of any network whose output layer is "
                          "affine in 256 hidden units, from the training targets (CPU only)")
@@ -445,6 +485,9 @@ def main():
         return
     if args.local_sweep:
         local_sweep([int(k) for k in args.local_sweep.split(",")], args.steps, args.warmup)
+        return
+    if args.batch_sweep:
+        batch_sweep([int(k) for k in args.batch_sweep.split(",")])
         return
     if args.k_sweep:
         k_sweep([int(k) for k in args.k_sweep.split(",")], args.steps, args.warmup)
