@@ -265,73 +265,80 @@ __device__ inline double rsq_nr(double x) {
 
 // Cholesky of the 16x16 diagonal block at (cb, cb) of the column-major LDS
 // matrix P (pitch ldp) by one wave, with the forward solve of y[cb .. cb+15]
-// and the inverse X = L^-1 built alongside.  Lane (r, g) = (lane & 15,
-// lane >> 4) holds row r of L and of X at the columns m = g, g + 4, g + 8,
-// g + 12.  At step c, column c of L and row c of X are final; they go through
-// LDS (cxb: two buffers of 16 + 16 doubles, alternating, so one wave barrier
-// per column suffices) and every lower row subtracts its multiple of them
-// from its four entries.  The pivot comes to all lanes through the scalar
-// unit; 1/sqrt of it is the hardware estimate refined by two Newton steps.
-// Entries above the diagonal of a lane's row of L pick up values that are
-// never read or stored.  L goes back to P; Linv (row-major, pitch 17, zero
-// above the diagonal) receives X, which turns the solves against L below the
-// block into products on MFMA.  A non-positive pivot is replaced by 1 and
-// reported by returning false.
+// and the inverse X = L^-1 built alongside.  The wave's lanes take three
+// roles and run one instruction stream: lanes 0-15 hold row r = lane of the
+// block (becoming row r of L), lanes 16-31 column j = lane - 16 of the
+// identity (becoming column j of X), lane 32 the 16 entries of y.  At step c
+// the pivot comes to all lanes through the scalar unit and 1/sqrt of it is the
+// hardware estimate refined by two Newton steps; every lane scales its entry
+// c by it (row lanes: L[r][c]; column lanes: X[c][j]; rhs lane: y_c) and then
+// subtracts (its entry c) x L[m][c] from each entry m > c.  L[c+1][c], which
+// the next pivot needs, comes through the scalar unit; the rest of column c
+// through LDS: each lane writes its entry c to its own slot of a 64-double
+// buffer (cxb: two of them, alternating, 128 doubles), so no store is
+// divergent and no wave barrier splits the step -- one wave's LDS operations
+// complete in order, and the compiler cannot move the read of slot m above
+// the store to slot `lane`.  Every entry sees the same operations in the same
+// order as a column-by-column right-looking factorisation.  Entries above the
+// diagonal of a row lane pick up values that are never read or stored.  L
+// goes back to P; Linv (row-major, pitch 17, zero above the diagonal)
+// receives X, which turns the solves against L below the block into products
+// on MFMA.  A non-positive pivot is replaced by 1 and reported by returning
+// false.
 __device__ __attribute__((always_inline)) inline bool wave_chol16_inv4(double* P, int ldp, int cb, double* y,
                                                                        double* Linv, double* cxb) {
   const int lane = threadIdx.x & 63;
   int rr = lane & 15;
   asm volatile("" : "+v"(rr));  // per-lane predicates stay here, not hoisted into the caller
-  const int g = lane >> 4;
-  double a[4], x[4];
+  const bool row = lane < 16, col = (lane >= 16 && lane < 32), rhs = lane == 32;
+  double v[16];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int m = g + 4 * t;
-    a[t] = (m <= rr) ? P[(cb + m) * ldp + cb + rr] : 0.0;
-    x[t] = (m == rr) ? 1.0 : 0.0;
+  for (int m = 0; m < 16; ++m) {
+    double t = 0.0;
+    if (row && m <= rr) t = P[(cb + m) * ldp + cb + rr];
+    if (col && m == rr) t = 1.0;
+    if (rhs) t = y[cb + m];
+    v[m] = t;
   }
-  double yr = y[cb + rr];
+  // the start vector is formed here (else its loads sink into the loop and
+  // stay live across it)
+#pragma unroll
+  for (int m = 0; m < 16; ++m) asm volatile("" : "+v"(v[m]));
   bool ok = true;
+  double piv = bcast_lane(v[0], 0);
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
-    const int tc = c >> 2, gc = c & 3;  // column c sits in slot tc of lanes with g == gc
-    double piv = bcast_lane(a[tc], c + 16 * gc);
-    if (!(piv > 0.0)) {
-      ok = false;
-      piv = 1.0;
-    }
-    const double inv = rsq_nr(piv);
-    const bool own = (rr == c), below = (rr > c);
-    if (g == gc) a[tc] = own ? piv * inv : (below ? a[tc] * inv : a[tc]);
-    if (own) {
-      yr *= inv;
+    const bool good = piv > 0.0;
+    ok = ok && good;
+    const double pv = good ? piv : 1.0;
+    const double inv = rsq_nr(pv);
+    v[c] = (row && rr == c) ? pv * inv : v[c] * inv;
+    if (c == 15) break;
+    const double f = (row && rr < c) ? 0.0 : v[c];
+    double* cbuf = cxb + 64 * (c & 1);
+    cbuf[lane] = v[c];
+    v[c + 1] -= f * bcast_lane(v[c], c + 1);
+    piv = bcast_lane(v[c + 1], c + 1);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) x[t] *= inv;
-    }
-    const double yc = bcast_lane(yr, c);
-    double* cb_ = cxb + 32 * (c & 1);  // [0, 16): column c of L; [16, 32): row c of X
-    if (g == gc) cb_[rr] = a[tc];
-    if (own) {
+    for (int m = c + 2; m < 16; ++m) v[m] -= f * cbuf[m];
+    // this step's updates are applied now, not deferred to their next use
+    // (which would keep every step's multipliers and LDS values live)
 #pragma unroll
-      for (int t = 0; t < 4; ++t) cb_[16 + g + 4 * t] = x[t];
-    }
-    wave_lds_sync();
-    const double f = below ? cb_[rr] : 0.0;  // L[r][c] for the rows that update
-    yr -= f * yc;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int m = g + 4 * t;
-      if (m > c) a[t] -= f * cb_[m];
-      else x[t] -= f * cb_[16 + m];
-    }
+    for (int m = c + 2; m < 16; ++m) asm volatile("" : "+v"(v[m]));
   }
+  if (row) {
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int m = g + 4 * t;
-    if (m <= rr) P[(cb + m) * ldp + cb + rr] = a[t];
-    Linv[rr * 17 + m] = x[t];
+    for (int m = 0; m < 16; ++m)
+      if (m <= rr) P[(cb + m) * ldp + cb + rr] = v[m];
   }
-  if (g == 0) y[cb + rr] = yr;
+  if (col) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) Linv[r * 17 + rr] = v[r];
+  }
+  if (rhs) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) y[cb + r] = v[r];
+  }
   return ok;
 }
 
@@ -969,7 +976,7 @@ __global__ void __launch_bounds__(DENSE_NT) k_dense_chol(Dev d, int s0) {
   double* Lp = bl + n;            // [n - 16][PANEL_PITCH]: rows below the diagonal block
   __shared__ double Dk[16 * 17];    // diagonal block, column-major, pitch 17
   __shared__ double Linv[16 * 17];  // its inverse factor, row-major
-  __shared__ double cxb[64];
+  __shared__ double cxb[128];
   __shared__ double part[16 * 16];
   __shared__ int bad;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -1160,7 +1167,7 @@ __global__ void __launch_bounds__(DW_NT) k_dense_wide(Dev d, int s0, int nb) {
   double* yv = dw;      // [n] rhs, then the solution
   double* P = dw + n;   // [nb columns][M rows] of the current panel, M = n - c0, pitch M + 1
   __shared__ double Linv[16 * 17];
-  __shared__ double cxb[64];
+  __shared__ double cxb[128];
   __shared__ double part[16 * 16];
   __shared__ int bad;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1379,7 +1386,7 @@ __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
   double* tl = d.sn_tl + (int64_t)s * d.tl_stride;
   extern __shared__ double sl[];
   __shared__ double Linv[16 * 17];
-  __shared__ double cxb[64];
+  __shared__ double cxb[128];
   __shared__ int bad;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   constexpr int NW = SN_NT / 64, UL = 8, TB = 4;
