@@ -283,8 +283,9 @@ __device__ inline double rsq_nr(double x) {
 // diagonal of a row lane pick up values that are never read or stored.  L
 // goes back to P; Linv (row-major, pitch 17, zero above the diagonal)
 // receives X, which turns the solves against L below the block into products
-// on MFMA.  A non-positive pivot is replaced by 1 and reported by returning
-// false.
+// on MFMA.  A non-positive pivot is reported by returning false; its column
+// is then left unscaled (1/sqrt taken of 1 instead), and what follows is
+// garbage for the caller to discard.
 __device__ __attribute__((always_inline)) inline bool wave_chol16_inv4(double* P, int ldp, int cb, double* y,
                                                                        double* Linv, double* cxb) {
   const int lane = threadIdx.x & 63;
@@ -310,11 +311,12 @@ __device__ __attribute__((always_inline)) inline bool wave_chol16_inv4(double* P
   for (int c = 0; c < 16; ++c) {
     const bool good = piv > 0.0;
     ok = ok && good;
-    const double pv = good ? piv : 1.0;
-    const double inv = rsq_nr(pv);
-    v[c] = (row && rr == c) ? pv * inv : v[c] * inv;
+    const double inv = rsq_nr(good ? piv : 1.0);
+    // row lane c holds the pivot itself, so this is pivot * 1/sqrt(pivot) there
+    v[c] *= inv;
     if (c == 15) break;
-    const double f = (row && rr < c) ? 0.0 : v[c];
+    // a row lane above c multiplies garbage above its diagonal only
+    const double f = v[c];
     double* cbuf = cxb + 64 * (c & 1);
     cbuf[lane] = v[c];
     v[c + 1] -= f * bcast_lane(v[c], c + 1);
@@ -962,6 +964,107 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int DENSE_NT = 1024;
 constexpr int PANEL_PITCH = 17;  // doubles per staged panel row (odd: no LDS bank conflicts)
 
+// Back substitution L^T x = y of the dense block after its factorisation
+// (column-major, leading dimension n, a multiple of 16; y in LDS yv, replaced
+// by x), 16-row blocks from the bottom.  With n <= NT - 64 it runs
+// right-looking: thread 64 + r owns row r and its running sum acc_r = sum over
+// the solved blocks J of L[J][r] . x_J; the 16 entries L[c0 .. c0+15][r] it
+// needs for block c0 are contiguous in column r and are loaded one block
+// ahead.  Per block, the owners of its rows hand y_r - acc_r to wave 0
+// through LDS, wave 0 solves the block's 16 x 16 triangle (loaded one block
+// ahead as well), and every owner of a row above adds its 16 products.  Only
+// LDS traffic and barriers remain on the chain.  Larger blocks take the
+// left-looking form (partial dot products of the columns below each block).
+template <int NT>
+__device__ __attribute__((always_inline)) inline void dense_back_subst(const double* A, int n, double* yv,
+                                                                        double* part, double* xb) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nb = n / 16;
+  if (n > NT - 64) {
+    for (int k = nb - 1; k >= 0; --k) {
+      const int c0 = 16 * k;
+      if (tid < 256) {
+        const int c = tid >> 4, pp = tid & 15;  // 16 lanes read 16 consecutive rows of column c
+        double acc = 0.0;
+        for (int r = c0 + 16 + pp; r < n; r += 16) acc += A[(int64_t)(c0 + c) * n + r] * yv[r];
+        part[pp * 16 + c] = acc;
+      }
+      __syncthreads();
+      if (wv == 0) {
+        // lane r (mod 16) holds t_r and column r of L_kk
+        const int r = lane & 15;
+        double col[16];
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm) col[mm] = (mm >= r) ? A[(int64_t)(c0 + r) * n + c0 + mm] : 0.0;
+        double t = yv[c0 + r];
+        for (int pp = 0; pp < 16; ++pp) t -= part[pp * 16 + r];
+#pragma unroll
+        for (int c = 15; c >= 0; --c) {
+          if (r == c) t /= col[c];
+          const double xc = bcast_lane(t, c);
+          if (r < c) t -= col[c] * xc;
+        }
+        if (lane < 16) yv[c0 + r] = t;
+      }
+      __syncthreads();
+    }
+    return;
+  }
+  if (wv == 0) {
+    // lane q (mod 16) holds t_q and column q of the block's L
+    const int q = lane & 15;
+    double col[16];
+    int c0 = n - 16;
+#pragma unroll
+    for (int mm = 0; mm < 16; ++mm) col[mm] = (mm >= q) ? A[(int64_t)(c0 + q) * n + c0 + mm] : 0.0;
+    for (int k = nb - 1; k >= 0; --k, c0 -= 16) {
+      lds_barrier();  // the owners' t of this block are in xb
+      double t = xb[q];
+      double cur[16];
+#pragma unroll
+      for (int mm = 0; mm < 16; ++mm) cur[mm] = col[mm];
+      if (k > 0) {
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm) col[mm] = (mm >= q) ? A[(int64_t)(c0 - 16 + q) * n + c0 - 16 + mm] : 0.0;
+      }
+#pragma unroll
+      for (int c = 15; c >= 0; --c) {
+        if (q == c) t /= cur[c];
+        const double xc = bcast_lane(t, c);
+        if (q < c) t -= cur[c] * xc;
+      }
+      if (lane < 16) {
+        yv[c0 + q] = t;
+        xb[16 + q] = t;
+      }
+      lds_barrier();  // x of this block is in xb
+    }
+  } else {
+    const int r = tid - 64;
+    const bool own = r < n;
+    const double* Ar = A + (int64_t)(own ? r : 0) * n;  // column r
+    double pf[16];
+    double acc = 0.0;
+    int c0 = n - 16;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) pf[i] = (own && r < c0) ? Ar[c0 + i] : 0.0;
+    for (int k = nb - 1; k >= 0; --k, c0 -= 16) {
+      if (own && r >= c0 && r < c0 + 16) xb[r - c0] = yv[r] - acc;
+      lds_barrier();
+      lds_barrier();
+      if (own && r < c0) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc += pf[i] * xb[16 + i];
+        if (r < c0 - 16) {
+#pragma unroll
+          for (int i = 0; i < 16; ++i) pf[i] = Ar[c0 - 16 + i];
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
 template <bool LDS_PANEL>
 __global__ void __launch_bounds__(DENSE_NT) k_dense_chol(Dev d, int s0) {
   const int s = s0 + blockIdx.x;
@@ -1078,10 +1181,14 @@ __global__ void __launch_bounds__(DENSE_NT) k_dense_chol(Dev d, int s0) {
     // k + 1 < J <= I; each wave loads TB tiles together so the global round
     // trips overlap. Every tile still takes the steps' updates in step order.
     if (wv == 0) {
+      // the next diagonal block is this phase's critical path: its wave gets
+      // the issue slots of its SIMD first
+      __builtin_amdgcn_s_setprio(3);
       load_diag(k + 1, lane, 64);
       wave_lds_sync();
       const bool ok = wave_chol16_inv4(Dk, 17, 0, bl + c0 + 16, Linv, cxb);
       if (!ok && lane == 0) bad = 1;
+      __builtin_amdgcn_s_setprio(0);
     } else {
       const int m = nb - k - 2;
       const int ntile = m * (m + 1) / 2;
@@ -1111,34 +1218,8 @@ __global__ void __launch_bounds__(DENSE_NT) k_dense_chol(Dev d, int s0) {
     }
     __syncthreads();
   }
-  // back substitution L^T x = y, block by block from the bottom
-  for (int k = nb - 1; k >= 0; --k) {
-    const int c0 = 16 * k;
-    if (tid < 256) {
-      const int c = tid >> 4, pp = tid & 15;  // 16 lanes read 16 consecutive rows of column c
-      double acc = 0.0;
-      for (int r = c0 + 16 + pp; r < n; r += 16) acc += A[(int64_t)(c0 + c) * n + r] * bl[r];
-      part[pp * 16 + c] = acc;
-    }
-    __syncthreads();
-    if (wv == 0) {
-      // lane r (mod 16) holds t_r and column r of L_kk
-      const int r = lane & 15;
-      double col[16];
-#pragma unroll
-      for (int mm = 0; mm < 16; ++mm) col[mm] = (mm >= r) ? A[(int64_t)(c0 + r) * n + c0 + mm] : 0.0;
-      double t = bl[c0 + r];
-      for (int pp = 0; pp < 16; ++pp) t -= part[pp * 16 + r];
-#pragma unroll
-      for (int c = 15; c >= 0; --c) {
-        if (r == c) t /= col[c];
-        const double xc = bcast_lane(t, c);
-        if (r < c) t -= col[c] * xc;
-      }
-      if (lane < 16) bl[c0 + r] = t;
-    }
-    __syncthreads();
-  }
+  __syncthreads();
+  dense_back_subst<DENSE_NT>(A, n, bl, part, cxb);
   for (int i = tid; i < nlive; i += nt) b[i] = bl[i];
   if (tid == 0 && bad) d.status[(int64_t)s * (d.n_area + 1) + d.n_area] = 1;
 }
@@ -1295,33 +1376,8 @@ __global__ void __launch_bounds__(DW_NT) k_dense_wide(Dev d, int s0, int nb) {
     }
     __syncthreads();
   }
-  // back substitution L^T x = y, 16-column blocks from the bottom
-  for (int k = n / 16 - 1; k >= 0; --k) {
-    const int c0 = 16 * k;
-    if (tid < 256) {
-      const int c = tid >> 4, pp = tid & 15;  // 16 lanes read 16 consecutive rows of column c
-      double acc = 0.0;
-      for (int r = c0 + 16 + pp; r < n; r += 16) acc += A[(int64_t)(c0 + c) * n + r] * yv[r];
-      part[pp * 16 + c] = acc;
-    }
-    __syncthreads();
-    if (wv == 0) {
-      const int r = lane & 15;
-      double col[16];
-#pragma unroll
-      for (int mm = 0; mm < 16; ++mm) col[mm] = (mm >= r) ? A[(int64_t)(c0 + r) * n + c0 + mm] : 0.0;
-      double t = yv[c0 + r];
-      for (int pp = 0; pp < 16; ++pp) t -= part[pp * 16 + r];
-#pragma unroll
-      for (int c = 15; c >= 0; --c) {
-        if (r == c) t /= col[c];
-        const double xc = bcast_lane(t, c);
-        if (r < c) t -= col[c] * xc;
-      }
-      if (lane < 16) yv[c0 + r] = t;
-    }
-    __syncthreads();
-  }
+  __syncthreads();
+  dense_back_subst<DW_NT>(A, n, yv, part, cxb);
   for (int i = tid; i < nlive; i += DW_NT) b[i] = yv[i];
   if (tid == 0 && bad) d.status[(int64_t)s * (d.n_area + 1) + d.n_area] = 1;
 }
