@@ -1011,12 +1011,13 @@ __device__ __attribute__((always_inline)) inline void dense_back_subst(const dou
     return;
   }
   if (wv == 0) {
-    // lane q (mod 16) holds t_q and column q of the block's L
+    // lane q (mod 16) holds t_q, column q of the block's L and 1 / L_qq
     const int q = lane & 15;
     double col[16];
     int c0 = n - 16;
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) col[mm] = (mm >= q) ? A[(int64_t)(c0 + q) * n + c0 + mm] : 0.0;
+    double rd = 1.0 / col[q];
     for (int k = nb - 1; k >= 0; --k, c0 -= 16) {
       lds_barrier();  // the owners' t of this block are in xb
       double t = xb[q];
@@ -1029,7 +1030,7 @@ __device__ __attribute__((always_inline)) inline void dense_back_subst(const dou
       }
 #pragma unroll
       for (int c = 15; c >= 0; --c) {
-        if (q == c) t /= cur[c];
+        if (q == c) t *= rd;
         const double xc = bcast_lane(t, c);
         if (q < c) t -= cur[c] * xc;
       }
@@ -1038,6 +1039,8 @@ __device__ __attribute__((always_inline)) inline void dense_back_subst(const dou
         xb[16 + q] = t;
       }
       lds_barrier();  // x of this block is in xb
+      // the next block's reciprocal while the owners add their products
+      if (k > 0) rd = 1.0 / col[q];
     }
   } else {
     const int r = tid - 64;
