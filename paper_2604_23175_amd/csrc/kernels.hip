@@ -2071,7 +2071,14 @@ __global__ void __launch_bounds__(256) k_stream_refill(Dev d, int32_t* slot_id, 
         want = 1;
       } else {
         int bad = 0;
-        for (int k = 0; k < K1; ++k) bad |= d.status[(int64_t)s * K1 + k];
+        // the pivot flags, 8 loads in flight
+        for (int k0 = 0; k0 < K1; k0 += 8) {
+          int f[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) f[u] = (k0 + u < K1) ? d.status[(int64_t)s * K1 + k0 + u] : 0;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) bad |= f[u];
+        }
         const int act = d.active[s];
         if (!act || bad || d.iters[s] >= max_iter) {
           want = 1;
@@ -2125,6 +2132,8 @@ __global__ void k_stream_init(int32_t* slot_id, int32_t* next, int n_snap) {
   if (i < 2) next[i] = 0;
 }
 
+constexpr int STREAM_COPY_CHUNKS = 32;  // workgroups per slot
+
 // Grid (chunks, n_snap). Slot s hands the state of its finished snapshot to
 // vm_out / va_out [n_total][n_bus] and loads the entering snapshot's
 // measurements (zs [n_total][n_meas]) and starting state (vm0 / va0
@@ -2151,9 +2160,18 @@ __global__ void k_stream_copy(Dev d, const int32_t* retire, const int32_t* refil
     }
   }
   if (entering >= 0) {
+    // U measurements per thread and pass, loaded together
+    constexpr int U = 4;
     const double* src = zs + (int64_t)entering * d.n_meas;
     double* dst = const_cast<double*>(d.z) + (int64_t)s * d.n_meas;
-    for (int j = i0; j < d.n_meas; j += stride) dst[j] = src[j];
+    for (int j0 = i0; j0 < d.n_meas; j0 += U * stride) {
+      double t[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) t[u] = (j0 + u * stride < d.n_meas) ? src[j0 + u * stride] : 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (j0 + u * stride < d.n_meas) dst[j0 + u * stride] = t[u];
+    }
   }
 }
 
@@ -2380,9 +2398,10 @@ hipError_t launch_stream_init(int32_t* slot_id, int32_t* next, int n_snap, hipSt
 hipError_t launch_stream_copy(const Dev& d, const int32_t* retire, const int32_t* refill, const double* zs,
                               const double* vm0, const double* va0, double* vm_out, double* va_out,
                               hipStream_t st) {
-  // 8 chunks of 256 threads per slot cover the measurement copy (the larger part)
-  hipLaunchKernelGGL(k_stream_copy, dim3(8, (unsigned)d.n_snap), dim3(256), 0, st, d, retire, refill, zs, vm0,
-                     va0, vm_out, va_out);
+  // STREAM_COPY_CHUNKS workgroups of 256 threads per slot cover the measurement
+  // copy (the larger part) with few passes each
+  hipLaunchKernelGGL(k_stream_copy, dim3(STREAM_COPY_CHUNKS, (unsigned)d.n_snap), dim3(256), 0, st, d, retire,
+                     refill, zs, vm0, va0, vm_out, va_out);
   return hipGetLastError();
 }
 
