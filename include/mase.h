@@ -318,7 +318,7 @@ int mase_eval_h_dev(mase_ctx* ctx, const double* vm_dev, const double* va_dev, d
  * a starting (|V|, theta) for each of the area's own buses (outputs
  * standardised by y_mean / y_std).  Weights are bfloat16 copies of FP32
  * master weights; products run on bf16 MFMA with FP32 accumulation; Adam
- * updates the masters.  Gauss-Newton in FP64 remains the judge: a prediction
+ * updates the masters.  Gauss-Newton in FP64 has the last word: a prediction
  * is used for a snapshot only if its objective J (Eq. 2) is not worse than
  * that of the flat start.
  *
