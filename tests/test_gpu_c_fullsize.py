@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 from gpu_common import Case, assert_state_close, say
+from paper_2604_23175_amd import mase
 
 pytestmark = pytest.mark.gpu
 
@@ -134,3 +135,24 @@ def test_stream_headline_schedule_matches_oracle(schedule, tmp_path, monkeypatch
         assert ref["converged"] and it[i] == ref["iters"], (it[i], ref["iters"])
         assert_state_close(vm[i], va[i], ref["vm"], ref["va"], 1e-8)
     m.close()
+
+
+def test_dense_boundary_block_beyond_960_rows_c2():
+    # The whole boundary system as one dense block (9241 buses: 481 boundary
+    # buses, 962 variables, more than the 960 rows up to which the dense
+    # kernels' back substitution runs right-looking) takes the left-looking
+    # back substitution; its states agree with the supernodal boundary solve.
+    say("dense boundary mode c2")
+    c = Case("c2", 2, seed=5)
+    res = []
+    for gm in (mase.MASE_GAMMA_SPARSE, mase.MASE_GAMMA_DENSE):
+        m = c.ctx(gamma_mode=gm)
+        if gm == mase.MASE_GAMMA_DENSE:
+            assert 2 * m.mase_info("gamma_tail") > 960, m.mase_info("gamma_tail")
+        iters, conv = m.mase_solve(1e-8, 12)
+        assert conv.all(), iters
+        res.append((m.mase_state(), iters))
+        m.close()
+    np.testing.assert_array_equal(res[0][1], res[1][1])
+    for i in range(2):
+        assert_state_close(res[1][0][0][i], res[1][0][1][i], res[0][0][0][i], res[0][0][1][i], 1e-10)
