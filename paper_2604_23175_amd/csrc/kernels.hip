@@ -600,39 +600,114 @@ __global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int
     __syncthreads();
   }
   bool bad = false;
-  // UB targets per thread and pass: their records, then their current
-  // values, are loaded together so the global round trips overlap.  The
-  // records of a level's first pass and of the next level's first column
-  // item are plan data: they are fetched a phase early, off the critical path.
-  constexpr int UB = (NT >= 1024) ? 4 : 2;
+  // Latency structure.  A wave's loads complete in issue order (one counter
+  // for loads and stores), so a record fetched early but consumed after a
+  // later load costs nothing only if nothing waits in between.  Each level
+  // therefore issues, in one burst, every load of its first pass (the pivot
+  // and column blocks of its first column item, the current values of its
+  // first UB update targets with their first contribution records, the
+  // first contribution of its first rhs target) together with the next
+  // level's first records and the level bounds two levels ahead; one wait
+  // covers them all.  Update targets of a level lie in later columns, which
+  // the level's column phase does not write, so their values can be read
+  // before it, and the barrier between the phases only orders LDS.  The
+  // barrier that closes a level waits for its stores, which the next level
+  // reads.  Items beyond the first pass load their records and values on
+  // demand.  Every value sees the same operations in the same order as a
+  // plain level-by-level schedule.
+  constexpr int UB = 2;
   const int32_t* cdp = d.cd_ptr + sm.cd_ptr;
   const int32_t* upp = d.up_ptr + sm.up_ptr;
   const int32_t* rbp = d.rb_ptr + sm.rb_ptr;
-  int nc0 = 0, nc1 = 0;
-  Rec4 cpre{0, 0, 0, 0};
-  if (sm.nlev > 0) {
-    nc0 = cdp[0];
-    nc1 = cdp[1];
-    if (nc0 + tid < nc1) cpre = ld_rec(d.cd_items + nc0 + tid);
+  const int nlev = sm.nlev;
+  const Rec4 none{-1, 0, 0, 0};
+  // bounds of this level [c0, c1) ... and the next level's ends nc1, nu1, nr1
+  int c0 = 0, c1 = 0, u0 = 0, u1 = 0, r0 = 0, r1 = 0, nc1 = 0, nu1 = 0, nr1 = 0;
+  Rec4 crec = none, rrec = none;
+  Rec4 trec[UB];
+#pragma unroll
+  for (int q = 0; q < UB; ++q) trec[q] = none;
+  if (nlev > 0) {
+    c0 = __builtin_amdgcn_readfirstlane(cdp[0]);
+    c1 = __builtin_amdgcn_readfirstlane(cdp[1]);
+    u0 = __builtin_amdgcn_readfirstlane(upp[0]);
+    u1 = __builtin_amdgcn_readfirstlane(upp[1]);
+    r0 = __builtin_amdgcn_readfirstlane(rbp[0]);
+    r1 = __builtin_amdgcn_readfirstlane(rbp[1]);
+    nc1 = __builtin_amdgcn_readfirstlane(nlev > 1 ? cdp[2] : c1);
+    nu1 = __builtin_amdgcn_readfirstlane(nlev > 1 ? upp[2] : u1);
+    nr1 = __builtin_amdgcn_readfirstlane(nlev > 1 ? rbp[2] : r1);
+    if (c0 + tid < c1) crec = ld_rec(d.cd_items + c0 + tid);
+#pragma unroll
+    for (int q = 0; q < UB; ++q)
+      if (u0 + tid + q * NT < u1) trec[q] = ld_rec(d.up_tgt + u0 + tid + q * NT);
+    if (r0 + tid < r1) rrec = ld_rec(d.rb_tgt + r0 + tid);
   }
-  for (int lev = 0; lev < sm.nlev; ++lev) {
-    const int c0 = nc0, c1 = nc1;
-    const int u0 = upp[lev], u1 = upp[lev + 1];
-    const int r0 = rbp[lev], r1 = rbp[lev + 1];
-    Rec4 tpre[UB];
+  for (int lev = 0; lev < nlev; ++lev) {
+    // ---- the burst: this level's first-pass values and contribution records
+    double dv0 = 0, dv1 = 0, dv3 = 0;
+    double2 mv0 = make_double2(0, 0), mv1 = make_double2(0, 0);
+    if (crec.x >= 0) {
+      const double* D = vals + crec.x;
+      dv0 = D[0];
+      dv1 = D[1];
+      dv3 = D[3];
+      if (crec.y >= 0) {
+        const double* M = vals + crec.y;
+        mv0 = *reinterpret_cast<const double2*>(M);
+        mv1 = *reinterpret_cast<const double2*>(M + 2);
+      }
+    }
+    double cv[UB][4];
+    Rec2 uc[UB];
 #pragma unroll
     for (int q = 0; q < UB; ++q) {
-      const int it = u0 + tid + q * NT;
-      tpre[q] = Rec4{-1, 0, 0, 0};
-      if (it < u1) tpre[q] = ld_rec(d.up_tgt + it);
+      uc[q] = Rec2{0, 0};
+      cv[q][0] = cv[q][1] = cv[q][2] = cv[q][3] = 0.0;
+      if (trec[q].x >= 0) {
+        const int stride = trec[q].y & ~UP_SINGLE_FLAG;
+        const double* C = vals + trec[q].x;
+        cv[q][0] = C[0];
+        cv[q][1] = C[1];
+        cv[q][2] = C[stride];
+        cv[q][3] = C[stride + 1];
+        if (!(trec[q].y & UP_SINGLE_FLAG)) uc[q] = ld_rec(d.up_con + trec[q].z);
+      }
     }
-    Rec4 rpre{0, 0, 0, 0};
-    if (r0 + tid < r1) rpre = ld_rec(d.rb_tgt + r0 + tid);
+    Rec2 rc{0, 0};
+    if (rrec.x >= 0 && rrec.y < rrec.z) rc = ld_rec(d.rb_con + rrec.y);
+    // ---- the next level's first records and the bounds after it
+    const bool more = lev + 1 < nlev;
+    Rec4 cn = none, rn = none;
+    Rec4 tn[UB];
+#pragma unroll
+    for (int q = 0; q < UB; ++q) tn[q] = none;
+    int nnc1 = nc1, nnu1 = nu1, nnr1 = nr1;
+    if (more) {
+      if (c1 + tid < nc1) cn = ld_rec(d.cd_items + c1 + tid);
+#pragma unroll
+      for (int q = 0; q < UB; ++q)
+        if (u1 + tid + q * NT < nu1) tn[q] = ld_rec(d.up_tgt + u1 + tid + q * NT);
+      if (r1 + tid < nr1) rn = ld_rec(d.rb_tgt + r1 + tid);
+      if (lev + 2 < nlev) {
+        nnc1 = cdp[lev + 3];
+        nnu1 = upp[lev + 3];
+        nnr1 = rbp[lev + 3];
+      }
+    }
+    // ---- column phase: pivots, y_j, and the column blocks X with X L^T = M
     for (int it = c0 + tid; it < c1; it += NT) {
-      const Rec4 c = (it == c0 + tid) ? cpre : ld_rec(d.cd_items + it);
-      const double* D = vals + c.x;
+      const bool first = it == c0 + tid;
+      const Rec4 c = first ? crec : ld_rec(d.cd_items + it);
+      double a00, a10, a11;
+      if (first) {
+        a00 = dv0; a10 = dv1; a11 = dv3;
+      } else {
+        const double* D = vals + c.x;
+        a00 = D[0]; a10 = D[1]; a11 = D[3];
+      }
       double l00, l10, l11, i00, i11;
-      if (!chol2(D[0], D[1], D[3], l00, l10, l11, i00, i11)) {
+      if (!chol2(a00, a10, a11, l00, l10, l11, i00, i11)) {
         bad = true;
         l00 = l11 = i00 = i11 = 1.0;
         l10 = 0.0;
@@ -645,9 +720,14 @@ __global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int
         lst[c.w] = y0;
         lst[c.w + 1] = y1;
       } else {
-        double* M = vals + c.y;  // X L^T = M
-        const double2 m0 = *reinterpret_cast<const double2*>(M);
-        const double2 m1 = *reinterpret_cast<const double2*>(M + 2);
+        double* M = vals + c.y;
+        double2 m0, m1;
+        if (first) {
+          m0 = mv0; m1 = mv1;
+        } else {
+          m0 = *reinterpret_cast<const double2*>(M);
+          m1 = *reinterpret_cast<const double2*>(M + 2);
+        }
         const double x00 = m0.x * i00, x10 = m0.y * i00;
         const double x01 = (m1.x - x00 * l10) * i11, x11 = (m1.y - x10 * l10) * i11;
         *reinterpret_cast<double2*>(M) = make_double2(x00, x10);
@@ -656,24 +736,45 @@ __global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int
         *reinterpret_cast<double2*>(lst + c.w + 2) = make_double2(x01, x11);
       }
     }
-    __syncthreads();
-    if (lev + 1 < sm.nlev) {
-      nc0 = c1;
-      nc1 = cdp[lev + 2];
-      if (nc0 + tid < nc1) cpre = ld_rec(d.cd_items + nc0 + tid);
-    }
-    for (int it0 = u0 + tid; it0 < u1; it0 += NT * UB) {
+    // the update phase reads the column phase's results from LDS only
+    // (with the rhs in HBM, y_i of a later column is not written above)
+    lds_barrier();
+    // ---- update phase: target -= sum_j L_ij L_pj^T, fixed order
+    auto update = [&](const Rec4 t, double c00, double c10, double c01, double c11, Rec2 p0) {
+      double a00 = 0, a10 = 0, a01 = 0, a11 = 0;
+      const bool single = (t.y & UP_SINGLE_FLAG) != 0;
+      const int stride = t.y & ~UP_SINGLE_FLAG;
+      const int cb = single ? 0 : t.z, ce = single ? 1 : t.w;
+      bool sym = false;
+      for (int c = cb; c < ce; ++c) {
+        const Rec2 u = single ? Rec2{t.z, t.w} : (c == cb ? p0 : ld_rec(d.up_con + c));
+        const double2 L0 = *reinterpret_cast<const double2*>(lst + u.x);
+        const double2 L1 = *reinterpret_cast<const double2*>(lst + u.x + 2);
+        const double2 P0 = *reinterpret_cast<const double2*>(lst + u.y);
+        const double2 P1 = *reinterpret_cast<const double2*>(lst + u.y + 2);
+        a00 += L0.x * P0.x + L1.x * P1.x;
+        a10 += L0.y * P0.x + L1.y * P1.x;
+        a01 += L0.x * P0.y + L1.x * P1.y;
+        a11 += L0.y * P0.y + L1.y * P1.y;
+        sym = (u.x == u.y);
+      }
+      if (sym) a01 = a10;
+      double* C = vals + t.x;
+      C[0] = c00 - a00;
+      C[1] = c10 - a10;
+      C[stride] = c01 - a01;
+      C[stride + 1] = c11 - a11;
+    };
+#pragma unroll
+    for (int q = 0; q < UB; ++q)
+      if (trec[q].x >= 0) update(trec[q], cv[q][0], cv[q][1], cv[q][2], cv[q][3], uc[q]);
+    for (int it0 = u0 + tid + NT * UB; it0 < u1; it0 += NT * UB) {
       Rec4 t[UB];
       double c00[UB], c10[UB], c01[UB], c11[UB];
 #pragma unroll
       for (int q = 0; q < UB; ++q) {
         const int it = it0 + q * NT;
-        if (it0 == u0 + tid) {
-          t[q] = tpre[q];
-        } else {
-          t[q] = Rec4{-1, 0, 0, 0};
-          if (it < u1) t[q] = ld_rec(d.up_tgt + it);
-        }
+        t[q] = it < u1 ? ld_rec(d.up_tgt + it) : none;
       }
 #pragma unroll
       for (int q = 0; q < UB; ++q) {
@@ -688,36 +789,18 @@ __global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int
 #pragma unroll
       for (int q = 0; q < UB; ++q) {
         if (t[q].x < 0) continue;
-        double a00 = 0, a10 = 0, a01 = 0, a11 = 0;
         const bool single = (t[q].y & UP_SINGLE_FLAG) != 0;
-        const int stride = t[q].y & ~UP_SINGLE_FLAG;
-        const int cb = single ? 0 : t[q].z, ce = single ? 1 : t[q].w;
-        bool sym = false;
-        for (int c = cb; c < ce; ++c) {
-          const Rec2 u = single ? Rec2{t[q].z, t[q].w} : ld_rec(d.up_con + c);
-          const double2 L0 = *reinterpret_cast<const double2*>(lst + u.x);
-          const double2 L1 = *reinterpret_cast<const double2*>(lst + u.x + 2);
-          const double2 P0 = *reinterpret_cast<const double2*>(lst + u.y);
-          const double2 P1 = *reinterpret_cast<const double2*>(lst + u.y + 2);
-          a00 += L0.x * P0.x + L1.x * P1.x;
-          a10 += L0.y * P0.x + L1.y * P1.x;
-          a01 += L0.x * P0.y + L1.x * P1.y;
-          a11 += L0.y * P0.y + L1.y * P1.y;
-          sym = (u.x == u.y);
-        }
-        if (sym) a01 = a10;
-        double* C = vals + t[q].x;
-        C[0] = c00[q] - a00;
-        C[1] = c10[q] - a10;
-        C[stride] = c01[q] - a01;
-        C[stride + 1] = c11[q] - a11;
+        const Rec2 p0 = single ? Rec2{0, 0} : ld_rec(d.up_con + t[q].z);
+        update(t[q], c00[q], c10[q], c01[q], c11[q], p0);
       }
     }
+    // ---- rhs targets: y_i -= sum_j L_ij y_j
     for (int it = r0 + tid; it < r1; it += NT) {
-      const Rec4 t = (it == r0 + tid) ? rpre : ld_rec(d.rb_tgt + it);
+      const bool first = it == r0 + tid;
+      const Rec4 t = first ? rrec : ld_rec(d.rb_tgt + it);
       double b0 = 0, b1 = 0;
       for (int c = t.y; c < t.z; ++c) {
-        const Rec2 u = ld_rec(d.rb_con + c);
+        const Rec2 u = (first && c == t.y) ? rc : ld_rec(d.rb_con + c);
         const double* L = lst + u.x;
         const double y0 = lst[u.y], y1 = lst[u.y + 1];
         b0 += L[0] * y0 + L[2] * y1;
@@ -726,7 +809,17 @@ __global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int
       rhs[t.x] -= b0;
       rhs[t.x + 1] -= b1;
     }
+    // the next level reads the blocks stored above
     __syncthreads();
+    // level bounds are uniform: keep them in scalar registers
+    c0 = c1; c1 = nc1; u0 = u1; u1 = nu1; r0 = r1; r1 = nr1;
+    nc1 = __builtin_amdgcn_readfirstlane(nnc1);
+    nu1 = __builtin_amdgcn_readfirstlane(nnu1);
+    nr1 = __builtin_amdgcn_readfirstlane(nnr1);
+    crec = cn;
+    rrec = rn;
+#pragma unroll
+    for (int q = 0; q < UB; ++q) trec[q] = tn[q];
   }
   if (RL)
     for (int i = tid; i < 2 * sm.nn; i += NT) rhs_g[i] = rhs[i];
