@@ -119,7 +119,7 @@ int upload_plan(mase_ctx* c) {
   const int K = p.n_area;
   std::vector<SysMeta> sm(K + 1);
   std::vector<AreaMeta> am(K);
-  std::vector<int32_t> gbus, cd_ptr, up_ptr, rb_ptr, bs_ptr;
+  std::vector<int32_t> gbus, cd_ptr, up_ptr, rb_ptr, bs_ptr, bs_lg;
   std::vector<I4> cd_items, up_tgt, rb_tgt, bs_items, up_tgt_img;
   std::vector<I2> up_con, rb_con, bs_con, up_con_img, rb_con_img;
   // the areas' elimination runs the level engine over HBM; MASE_AREA_LDS=1
@@ -163,6 +163,7 @@ int upload_plan(mase_ctx* c) {
     rb_con.insert(rb_con.end(), s.rb_con.begin(), s.rb_con.end());
     m.bs_ptr = (int32_t)bs_ptr.size();
     append_rebased(bs_ptr, s.bs_ptr, (int32_t)bs_items.size());
+    bs_lg.insert(bs_lg.end(), s.bs_lg.begin(), s.bs_lg.end());  // parallel to bs_ptr
     for (const I4& t : s.bs_items)
       bs_items.push_back({t.x, t.y, t.z + (int32_t)bs_con.size(), t.w + (int32_t)bs_con.size()});
     bs_con.insert(bs_con.end(), s.bs_con.begin(), s.bs_con.end());
@@ -449,7 +450,7 @@ int upload_plan(mase_ctx* c) {
   UP(inc_ptr, inc_ptr); UP(inc_end, inc_end);
   UP(row_type, row_type); UP(row_loc, row_loc); UP(row_meas, row_meas); UP(rowrec, rowrec);
   UP(slot, slot); UP(scon, scon); UP(rslot, rslot); UP(rcon, rcon); UP(slot_rhs, slot_rhs);
-  UP(cd_ptr, cd_ptr); UP(up_ptr, up_ptr); UP(rb_ptr, rb_ptr); UP(bs_ptr, bs_ptr);
+  UP(cd_ptr, cd_ptr); UP(up_ptr, up_ptr); UP(rb_ptr, rb_ptr); UP(bs_ptr, bs_ptr); UP(bs_lg, bs_lg);
   UP(cd_items, cd_items); UP(up_tgt, up_tgt); UP(up_con, up_con);
   UP(rb_tgt, rb_tgt); UP(rb_con, rb_con); UP(bs_items, bs_items); UP(bs_con, bs_con);
   UP(up_tgt_img, up_tgt_img); UP(up_con_img, up_con_img); UP(rb_con_img, rb_con_img); UP(cimg, cimg);

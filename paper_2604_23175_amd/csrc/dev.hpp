@@ -53,6 +53,7 @@ struct Dev {
   const int32_t* slot_rhs;  // per slot: rhs offset 2 v of a diagonal slot (v, v), else -1
   const int4* rcon;   // per rhs contribution: {type, loc, meas, role}
   const int32_t *cd_ptr, *up_ptr, *rb_ptr, *bs_ptr;
+  const int32_t* bs_lg;  // parallel to bs_ptr: log2 of the lanes per column of each level
   const int4* cd_items;
   const int4* up_tgt;
   const int2* up_con;

@@ -1862,9 +1862,6 @@ __global__ void __launch_bounds__(TAIL_NT) k_gamma_tail(Dev d, int s0, int nblk)
 // ---------------------------------------------------------------------------
 template <int NT, bool XL>
 __global__ void __launch_bounds__(NT) k_backsolve(Dev d, int sys0, int nsys, int s0, int ns, int fixed_bnd) {
-  // lanes per column: the boundary system's levels hold a few wide columns,
-  // an area's levels many narrow ones
-  constexpr int G = (NT >= 1024) ? 64 : 8;
   int si, s;
   area_snap_of_block(blockIdx.x, nsys, ns, si, s);
   s += s0;
@@ -1894,48 +1891,101 @@ __global__ void __launch_bounds__(NT) k_backsolve(Dev d, int sys0, int nsys, int
     for (int i = 2 * sm.ne + tid; i < 2 * sm.nn; i += NT) xl[i] = rhs[i];
   }
   __syncthreads();
-  const int grp = tid / G, gl = tid % G;
-  // Each level's first item per lane group and that item's first factor
-  // block record per lane are loaded one level ahead.  With x in LDS the
-  // threads share nothing else (the factor is only read), so the barriers
-  // wait for LDS traffic alone and those loads stay in flight across them.
+  // Lanes per column vary by level (2^lg of them, from the plan: many short
+  // columns near the leaves, a few long ones near the root); lane gl of a
+  // group sums rows gl, gl + G, ... of its column, then the group reduces.
+  // The factor is only read here, so every load of a level's first pass (a
+  // factor block per lane, the pivot block per group) goes out in one burst
+  // together with the next level's first contribution records, the item
+  // records two levels ahead and the level bounds three ahead; one wait
+  // covers them all.  Loads complete in issue order, so records fetched
+  // early are only free if nothing waits in between.  With x in LDS the
+  // barriers order LDS only.
   const int32_t* bsp = d.bs_ptr + sm.bs_ptr;
-  const int4 none = make_int4(0, 0, 0, 0);
-  int b0 = 0, b1 = 0;
-  int4 bpre = none;
-  int2 upre = make_int2(0, 0);
-  if (sm.nlev > 0) {
-    b0 = bsp[sm.nlev - 1];
-    b1 = bsp[sm.nlev];
-    if (b0 + grp < b1) bpre = d.bs_items[b0 + grp];
-    if (bpre.z + gl < bpre.w) upre = d.bs_con[bpre.z + gl];
+  const int32_t* bsg = d.bs_lg + sm.bs_ptr;
+  const int nlev = sm.nlev;
+  const Rec4 none{0, 0, 0, 0};
+  // this level: items [b0, b1), 2^lg lanes per item; the next level: items
+  // [n_b0, b0); the one after: [nn_b0, n_b0)
+  int b0 = 0, b1 = 0, lg = 0, n_b0 = 0, n_lg = 0, nn_b0 = 0, nn_lg = 0;
+  Rec4 irec = none, n_irec = none;
+  Rec2 crec{0, 0};
+  if (nlev > 0) {
+    b1 = __builtin_amdgcn_readfirstlane(bsp[nlev]);
+    b0 = __builtin_amdgcn_readfirstlane(bsp[nlev - 1]);
+    lg = __builtin_amdgcn_readfirstlane(bsg[nlev - 1]);
+    if (b0 + (tid >> lg) < b1) irec = ld_rec(d.bs_items + b0 + (tid >> lg));
+    if (irec.z + (tid & ((1 << lg) - 1)) < irec.w) crec = ld_rec(d.bs_con + irec.z + (tid & ((1 << lg) - 1)));
+    if (nlev > 1) {
+      n_b0 = __builtin_amdgcn_readfirstlane(bsp[nlev - 2]);
+      n_lg = __builtin_amdgcn_readfirstlane(bsg[nlev - 2]);
+      if (n_b0 + (tid >> n_lg) < b0) n_irec = ld_rec(d.bs_items + n_b0 + (tid >> n_lg));
+    }
+    if (nlev > 2) {
+      nn_b0 = __builtin_amdgcn_readfirstlane(bsp[nlev - 3]);
+      nn_lg = __builtin_amdgcn_readfirstlane(bsg[nlev - 3]);
+    }
   }
-  for (int lev = sm.nlev - 1; lev >= 0; --lev) {
-    const int nb0 = lev > 0 ? bsp[lev - 1] : b0;
-    int4 bnext = none;
-    if (lev > 0 && nb0 + grp < b0) bnext = d.bs_items[nb0 + grp];
-    for (int it = b0 + grp; it < b1; it += NT / G) {
+  for (int lev = nlev - 1; lev >= 0; --lev) {
+    const int G = 1 << lg, grp = tid >> lg, gl = tid & (G - 1);
+    // ---- the burst
+    const bool has_item = b0 + grp < b1;
+    double p0 = 0, p1 = 0, p2 = 0, p3 = 0, q0 = 0, q1 = 0, q3 = 0;
+    if (has_item && irec.z + gl < irec.w) {
+      const double* Lb = vals + crec.x;
+      p0 = Lb[0]; p1 = Lb[1]; p2 = Lb[2]; p3 = Lb[3];
+    }
+    if (has_item && gl == 0) {
+      const double* D = vals + irec.x;
+      q0 = D[0]; q1 = D[1]; q3 = D[3];
+    }
+    Rec2 n_crec{0, 0};
+    if (lev >= 1) {
+      const int ngl = tid & ((1 << n_lg) - 1);
+      if (n_b0 + (tid >> n_lg) < b0 && n_irec.z + ngl < n_irec.w) n_crec = ld_rec(d.bs_con + n_irec.z + ngl);
+    }
+    Rec4 nn_irec = none;
+    if (lev >= 2 && nn_b0 + (tid >> nn_lg) < n_b0) nn_irec = ld_rec(d.bs_items + nn_b0 + (tid >> nn_lg));
+    int nnn_b0 = 0, nnn_lg = 0;
+    if (lev >= 3) {
+      nnn_b0 = bsp[lev - 3];
+      nnn_lg = bsg[lev - 3];
+    }
+    // ---- the level's columns
+    for (int it = b0 + grp; it < b1; it += NT >> lg) {
       const bool first = it == b0 + grp;
-      const int4 b = first ? bpre : d.bs_items[it];
+      const Rec4 b = first ? irec : ld_rec(d.bs_items + it);
       double t0 = 0.0, t1 = 0.0;
       for (int c = b.z + gl; c < b.w; c += G) {
-        const int2 u = (first && c == b.z + gl) ? upre : d.bs_con[c];
-        const double* Lb = vals + u.x;
+        const bool pre = first && c == b.z + gl;
+        const Rec2 u = pre ? crec : ld_rec(d.bs_con + c);
+        double l0, l1, l2, l3;
+        if (pre) {
+          l0 = p0; l1 = p1; l2 = p2; l3 = p3;
+        } else {
+          const double* Lb = vals + u.x;
+          l0 = Lb[0]; l1 = Lb[1]; l2 = Lb[2]; l3 = Lb[3];
+        }
         const double x0 = xl[u.y], x1 = xl[u.y + 1];
-        t0 += Lb[0] * x0 + Lb[1] * x1;
-        t1 += Lb[2] * x0 + Lb[3] * x1;
+        t0 += l0 * x0 + l1 * x1;
+        t1 += l2 * x0 + l3 * x1;
       }
-#pragma unroll
-      for (int off = G / 2; off > 0; off >>= 1) {
-        t0 += __shfl_xor(t0, off, G);
-        t1 += __shfl_xor(t1, off, G);
+      for (int off = G >> 1; off > 0; off >>= 1) {
+        t0 += __shfl_xor(t0, off);
+        t1 += __shfl_xor(t1, off);
       }
       if (gl == 0) {
         t0 = xl[b.y] - t0;
         t1 = xl[b.y + 1] - t1;
-        const double* D = vals + b.x;
+        double a00, a10, a11;
+        if (first) {
+          a00 = q0; a10 = q1; a11 = q3;
+        } else {
+          const double* D = vals + b.x;
+          a00 = D[0]; a10 = D[1]; a11 = D[3];
+        }
         double l00, l10, l11, i00, i11;
-        if (!chol2(D[0], D[1], D[3], l00, l10, l11, i00, i11)) {
+        if (!chol2(a00, a10, a11, l00, l10, l11, i00, i11)) {
           l00 = l11 = i00 = i11 = 1.0;
           l10 = 0.0;
         }
@@ -1944,15 +1994,15 @@ __global__ void __launch_bounds__(NT) k_backsolve(Dev d, int sys0, int nsys, int
         xl[b.y] = (t0 - l10 * x1) * i00;
       }
     }
-    // the next level's first block record, once its item record is in
-    int2 unext = make_int2(0, 0);
-    if (bnext.z + gl < bnext.w) unext = d.bs_con[bnext.z + gl];
     if constexpr (XL) lds_barrier();
     else __syncthreads();
-    b1 = b0;
-    b0 = nb0;
-    bpre = bnext;
-    upre = unext;
+    b1 = b0; b0 = n_b0; lg = n_lg;
+    n_b0 = nn_b0; n_lg = nn_lg;
+    nn_b0 = __builtin_amdgcn_readfirstlane(nnn_b0);
+    nn_lg = __builtin_amdgcn_readfirstlane(nnn_lg);
+    irec = n_irec;
+    n_irec = nn_irec;
+    crec = n_crec;
   }
   if (XL)
     for (int i = tid; i < 2 * sm.nn; i += NT) rhs[i] = xl[i];
@@ -1966,7 +2016,6 @@ __global__ void __launch_bounds__(NT) k_backsolve(Dev d, int sys0, int nsys, int
 // ---------------------------------------------------------------------------
 template <int NT>
 __global__ void __launch_bounds__(NT) k_back_lds(Dev d, int a0, int na, int s0, int ns, int fixed_bnd) {
-  constexpr int G = 8;  // lanes per column
   int ai, s;
   area_snap_of_block(blockIdx.x, na, ns, ai, s);
   s += s0;
@@ -1992,24 +2041,28 @@ __global__ void __launch_bounds__(NT) k_back_lds(Dev d, int a0, int na, int s0, 
     xl[2 * (sm.ne + t) + 1] = fixed_bnd ? 0.0 : rb[src + 1];
   }
   __syncthreads();
-  const int grp = tid / G, gl = tid % G;
-  // records one level ahead, as in k_backsolve; factor and x are in LDS
+  // the lane groups of k_backsolve (2^lg lanes per column, per level) and
+  // its summation order; records one level ahead; factor and x in LDS
   const int32_t* bsp = d.bs_ptr + sm.bs_ptr;
+  const int32_t* bsg = d.bs_lg + sm.bs_ptr;
   const int4 none = make_int4(0, 0, 0, 0);
-  int b0 = 0, b1 = 0;
+  int b0 = 0, b1 = 0, lg = 0;
   int4 bpre = none;
   int2 upre = make_int2(0, 0);
   if (sm.nlev > 0) {
     b0 = bsp[sm.nlev - 1];
     b1 = bsp[sm.nlev];
-    if (b0 + grp < b1) bpre = d.bs_items[b0 + grp];
-    if (bpre.z + gl < bpre.w) upre = d.bs_con[bpre.z + gl];
+    lg = bsg[sm.nlev - 1];
+    if (b0 + (tid >> lg) < b1) bpre = d.bs_items[b0 + (tid >> lg)];
+    if (bpre.z + (tid & ((1 << lg) - 1)) < bpre.w) upre = d.bs_con[bpre.z + (tid & ((1 << lg) - 1))];
   }
   for (int lev = sm.nlev - 1; lev >= 0; --lev) {
+    const int G = 1 << lg, grp = tid >> lg, gl = tid & (G - 1);
     const int nb0 = lev > 0 ? bsp[lev - 1] : b0;
+    const int nlg = lev > 0 ? bsg[lev - 1] : 0;
     int4 bnext = none;
-    if (lev > 0 && nb0 + grp < b0) bnext = d.bs_items[nb0 + grp];
-    for (int it = b0 + grp; it < b1; it += NT / G) {
+    if (lev > 0 && nb0 + (tid >> nlg) < b0) bnext = d.bs_items[nb0 + (tid >> nlg)];
+    for (int it = b0 + grp; it < b1; it += NT >> lg) {
       const bool first = it == b0 + grp;
       const int4 b = first ? bpre : d.bs_items[it];
       double t0 = 0.0, t1 = 0.0;
@@ -2020,10 +2073,9 @@ __global__ void __launch_bounds__(NT) k_back_lds(Dev d, int a0, int na, int s0, 
         t0 += Lb[0] * x0 + Lb[1] * x1;
         t1 += Lb[2] * x0 + Lb[3] * x1;
       }
-#pragma unroll
-      for (int off = G / 2; off > 0; off >>= 1) {
-        t0 += __shfl_xor(t0, off, G);
-        t1 += __shfl_xor(t1, off, G);
+      for (int off = G >> 1; off > 0; off >>= 1) {
+        t0 += __shfl_xor(t0, off);
+        t1 += __shfl_xor(t1, off);
       }
       if (gl == 0) {
         t0 = xl[b.y] - t0;
@@ -2040,10 +2092,11 @@ __global__ void __launch_bounds__(NT) k_back_lds(Dev d, int a0, int na, int s0, 
       }
     }
     int2 unext = make_int2(0, 0);
-    if (bnext.z + gl < bnext.w) unext = d.bs_con[bnext.z + gl];
+    if (bnext.z + (tid & ((1 << nlg) - 1)) < bnext.w) unext = d.bs_con[bnext.z + (tid & ((1 << nlg) - 1))];
     lds_barrier();
     b1 = b0;
     b0 = nb0;
+    lg = nlg;
     bpre = bnext;
     upre = unext;
   }

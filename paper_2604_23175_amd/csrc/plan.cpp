@@ -76,7 +76,7 @@ std::vector<int> relabel(SysPlan& s, const std::vector<int>& gbus_old, int nelim
 
 // Packed offsets, levels and the level schedule of a system whose nn, ne,
 // gbus and strct are set.
-void finish_system(SysPlan& s) {
+void finish_system(SysPlan& s, int bs_threads) {
   s.nt = s.nn - s.ne;
   s.col_off.assign(s.ne, 0);
   int64_t cur = 0;
@@ -214,6 +214,26 @@ void finish_system(SysPlan& s) {
     s.up_ptr.push_back((int32_t)s.up_tgt.size());
     s.rb_ptr.push_back((int32_t)s.rb_tgt.size());
     s.bs_ptr.push_back((int32_t)s.bs_items.size());
+  }
+  // back substitution lane groups: with G lanes per column a level takes
+  // ceil(items / (threads / G)) passes, each a round trip for its item
+  // records and two (record, then factor block) per step along the longest
+  // column, ceil(longest column / G) steps; the cheapest G wins, ties to the
+  // larger G
+  s.bs_lg.assign(s.nlev + 1, 0);
+  for (int lev = 0; lev < s.nlev; ++lev) {
+    const int n = s.bs_ptr[lev + 1] - s.bs_ptr[lev];
+    int m = 0;
+    for (int it = s.bs_ptr[lev]; it < s.bs_ptr[lev + 1]; ++it)
+      m = std::max(m, s.bs_items[it].w - s.bs_items[it].z);
+    int best = -1;
+    int64_t best_cost = 0;
+    for (int lg = 0; (1 << lg) <= 64 && (1 << lg) <= bs_threads; ++lg) {
+      const int G = 1 << lg, per = bs_threads / G;
+      const int64_t cost = (int64_t)((n + per - 1) / per) * (1 + 2 * std::max(1, (m + G - 1) / G));
+      if (best < 0 || cost <= best_cost) { best = lg; best_cost = cost; }
+    }
+    s.bs_lg[lev] = best;
   }
 }
 
@@ -604,7 +624,7 @@ std::string build_plan(const Input& in, Plan& p) {
     for (auto& sv : sup)
       for (auto& a : sv) a.bus = newof[a.bus];
     s.packed_tail = true;
-    try { finish_system(s); } catch (std::exception& ex) { return ex.what(); }
+    try { finish_system(s, BS_THREADS_AREA); } catch (std::exception& ex) { return ex.what(); }
     if (p.slack >= 0 && area[p.slack] == k && !p.is_bnd[p.slack]) s.pin_off = s.col_off[lob[p.slack]];
 
     // templates
@@ -738,7 +758,7 @@ std::string build_plan(const Input& in, Plan& p) {
       g.ne = 0;
     }
     try {
-      finish_system(g);
+      finish_system(g, BS_THREADS_GAMMA);
       g.build_supernodes();
     } catch (std::exception& ex) { return ex.what(); }
     std::vector<int> gpos(N, -1);  // bus -> Gamma local index

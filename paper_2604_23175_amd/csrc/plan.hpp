@@ -25,6 +25,10 @@ constexpr int32_t UP_SINGLE = 1 << 30;
 constexpr int LDS_STAGE_DOUBLES = 6144;
 // Widest supernode (buses): its panel is at most 64 variables wide.
 constexpr int SN_MAX_W = 32;
+// Workgroup sizes the back substitution's lane groups are chosen for (areas,
+// boundary system).
+constexpr int BS_THREADS_AREA = 256;
+constexpr int BS_THREADS_GAMMA = 1024;
 // LDS of one workgroup on gfx950 (doubles): the budget for holding an area's
 // whole packed storage (or all but its Schur block) during its elimination.
 constexpr int AREA_LDS_DOUBLES = 160 * 1024 / 8;
@@ -123,6 +127,12 @@ struct SysPlan {
   std::vector<int32_t> bs_ptr;  // [nlev+1] -> bs_items (same levels, run top-down)
   std::vector<I4> bs_items;     // {diag_off, rhs_j, cbeg, cend}
   std::vector<I2> bs_con;       // {off L_ij, rhs_i}: t -= L_ij^T * x_i
+  // [nlev+1] (last entry unused): log2 of the lanes that share one column of
+  // a level in the back substitution (1..64 lanes; the sum over the column's
+  // rows is split over them), chosen per level for the fewest rounds of
+  // dependent loads: many short columns near the leaves, few long ones near
+  // the root
+  std::vector<int32_t> bs_lg;
 
   void build_supernodes();               // fills sn*, after the schedule
   void group_supernodes(int max_groups); // sn_grp*: roots packed into at most max_groups groups
