@@ -841,10 +841,41 @@ std::string build_plan(const Input& in, Plan& p) {
   // launch order: largest elimination work first
   p.area_order.resize(K);
   std::iota(p.area_order.begin(), p.area_order.end(), 0);
+  // The area kernels run one workgroup per (area, snapshot), and their time
+  // is set by the level elimination's chain of dependent memory round trips:
+  // two per level plus two per extra pass over its column items (256 per
+  // pass) or update targets (512 per pass).
   std::vector<double> work(K);
-  for (int k = 0; k < K; ++k) work[k] = p.sys[k].elim_flops() + 40.0 * p.tpl[k].scon.size();
+  for (int k = 0; k < K; ++k) {
+    const SysPlan& s = p.sys[k];
+    double rt = 0;
+    for (int l = 0; l < s.nlev; ++l) {
+      const int items = s.cd_ptr[l + 1] - s.cd_ptr[l], targets = s.up_ptr[l + 1] - s.up_ptr[l];
+      rt += 2.0 * ((items + 255) / 256 + (targets + 511) / 512);
+    }
+    work[k] = rt;
+  }
   std::stable_sort(p.area_order.begin(), p.area_order.end(),
                    [&](int a, int b) { return work[a] > work[b]; });
+  // With a multiple of 8 areas the kernels give launch position xcd + 8 m to
+  // the chiplet xcd (workgroup b runs on chiplet b mod 8), so every chiplet
+  // runs K / 8 areas for all snapshots.  Assign areas to chiplets longest
+  // first, each to the least loaded chiplet with room, and order each
+  // chiplet's areas longest first.
+  if (K % 8 == 0) {
+    const int per = K / 8;
+    std::vector<std::vector<int>> xcd(8);
+    std::vector<double> load(8, 0.0);
+    for (int k : p.area_order) {
+      int best = -1;
+      for (int x = 0; x < 8; ++x)
+        if ((int)xcd[x].size() < per && (best < 0 || load[x] < load[best])) best = x;
+      xcd[best].push_back(k);
+      load[best] += work[k];
+    }
+    for (int x = 0; x < 8; ++x)
+      for (int m = 0; m < per; ++m) p.area_order[x + 8 * m] = xcd[x][m];
+  }
   return "";
 }
 

@@ -222,7 +222,8 @@ struct Plan {
   std::vector<int32_t> tail_src_ptr;  // [n_area+1]
   // per bus: rhs offset (relative to snapshot rhs base) holding its dx
   std::vector<int32_t> bus_dx_src;
-  // area order for launches: largest elimination work first
+  // area order for launches: longest elimination first, balanced over the
+  // 8 chiplets when the area count is a multiple of 8
   std::vector<int32_t> area_order;
 
   int max_levels() const;
