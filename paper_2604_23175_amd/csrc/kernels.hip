@@ -695,6 +695,9 @@ __global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int
         nnr1 = rbp[lev + 3];
       }
     }
+    // every wave waits for the burst here, so no later use of its data
+    // waits behind the stores this level issues
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     // ---- column phase: pivots, y_j, and the column blocks X with X L^T = M
     for (int it = c0 + tid; it < c1; it += NT) {
       const bool first = it == c0 + tid;
@@ -744,10 +747,7 @@ __global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int
       double a00 = 0, a10 = 0, a01 = 0, a11 = 0;
       const bool single = (t.y & UP_SINGLE_FLAG) != 0;
       const int stride = t.y & ~UP_SINGLE_FLAG;
-      const int cb = single ? 0 : t.z, ce = single ? 1 : t.w;
-      bool sym = false;
-      for (int c = cb; c < ce; ++c) {
-        const Rec2 u = single ? Rec2{t.z, t.w} : (c == cb ? p0 : ld_rec(d.up_con + c));
+      auto acc = [&](const Rec2 u) {
         const double2 L0 = *reinterpret_cast<const double2*>(lst + u.x);
         const double2 L1 = *reinterpret_cast<const double2*>(lst + u.x + 2);
         const double2 P0 = *reinterpret_cast<const double2*>(lst + u.y);
@@ -756,9 +756,17 @@ __global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int
         a10 += L0.y * P0.x + L1.y * P1.x;
         a01 += L0.x * P0.y + L1.x * P1.y;
         a11 += L0.y * P0.y + L1.y * P1.y;
-        sym = (u.x == u.y);
-      }
-      if (sym) a01 = a10;
+      };
+      // the first contribution is in registers already (no wait behind this
+      // level's stores); further ones are loaded here
+      Rec2 u = single ? Rec2{t.z, t.w} : p0;
+      acc(u);
+      if (!single)
+        for (int c = t.z + 1; c < t.w; ++c) {
+          u = ld_rec(d.up_con + c);
+          acc(u);
+        }
+      if (u.x == u.y) a01 = a10;
       double* C = vals + t.x;
       C[0] = c00 - a00;
       C[1] = c10 - a10;
@@ -799,13 +807,14 @@ __global__ void __launch_bounds__(NT) k_eliminate(Dev d, int sys0, int nsys, int
       const bool first = it == r0 + tid;
       const Rec4 t = first ? rrec : ld_rec(d.rb_tgt + it);
       double b0 = 0, b1 = 0;
-      for (int c = t.y; c < t.z; ++c) {
-        const Rec2 u = (first && c == t.y) ? rc : ld_rec(d.rb_con + c);
+      auto acc = [&](const Rec2 u) {
         const double* L = lst + u.x;
         const double y0 = lst[u.y], y1 = lst[u.y + 1];
         b0 += L[0] * y0 + L[2] * y1;
         b1 += L[1] * y0 + L[3] * y1;
-      }
+      };
+      if (t.y < t.z) acc(first ? rc : ld_rec(d.rb_con + t.y));
+      for (int c = t.y + 1; c < t.z; ++c) acc(ld_rec(d.rb_con + c));
       rhs[t.x] -= b0;
       rhs[t.x + 1] -= b1;
     }
