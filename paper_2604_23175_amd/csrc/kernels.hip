@@ -393,8 +393,10 @@ __device__ inline bool chol2(double a00, double a10, double a11, double& l00, do
 // workgroups, and the gathers are latency-bound, so waves are what hide it.
 constexpr int ASM_NT = 1024;
 
-template <bool BR_LDS, bool STAGE_HBM>
+// WZ: the rows' weights and measurements are staged in LDS (with the area).
+template <bool BR_LDS, bool STAGE_HBM, bool WZ>
 __global__ void __launch_bounds__(ASM_NT) k_assemble(Dev d, int a0, int na, int s0, int ns, int mode) {
+  static_assert(!(WZ && STAGE_HBM), "weights are staged only with the area in LDS");
   int ai, s;
   area_snap_of_block(blockIdx.x, na, ns, ai, s);
   s += s0;
@@ -416,7 +418,7 @@ __global__ void __launch_bounds__(ASM_NT) k_assemble(Dev d, int a0, int na, int 
   const int tid = threadIdx.x, nt = blockDim.x;
 
   for (int v = tid; v < am.nn; v += nt) xs[v] = xsnap[d.gbus[sm.gbus + v]];
-  if (mode == MODE_ASSEMBLE && d.asm_wz && !STAGE_HBM) {
+  if (WZ && mode == MODE_ASSEMBLE) {
     const double* zsn = d.z + (int64_t)s * d.n_meas;
     for (int r = tid; r < am.nrow; r += nt) {
       const int m = d.rowrec[am.row + r].z;
@@ -495,60 +497,81 @@ __global__ void __launch_bounds__(ASM_NT) k_assemble(Dev d, int a0, int na, int 
   // rows are staged in LDS (wz) when they fit.  The next record is in flight
   // while one is evaluated, and the next slot's header and first record are
   // requested before this slot's results are stored.
-  const double2* wz = d.asm_wz ? reinterpret_cast<const double2*>(wzs) : nullptr;
   auto wz_of = [&](int r) -> double2 {
-    if (wz) return wz[r];
-    const int m = d.rowrec[am.row + r].z;
-    return make_double2(d.w[m], zs[m]);
+    if constexpr (WZ) {
+      return wzs[r];
+    } else {
+      const int m = d.rowrec[am.row + r].z;
+      return make_double2(d.w[m], zs[m]);
+    }
   };
   const int lane = tid & 63;
   const int4 zero4 = make_int4(0, -1, -1, 0);
   int i = tid;
   int4 sl = i < am.nslot ? d.slot[am.slot + i] : zero4;
   int rb2 = i < am.nslot ? d.slot_rhs[am.slot + i] : -1;
-  int4 r0 = (i < am.nslot && sl.w > 0) ? d.scon[sl.z + lane] : zero4;
+  // Two records in flight.  A slot's contribution records are taken
+  // alternately from two registers, each refilled (unconditionally, the index
+  // clamped to the slot's last record) as soon as its record has been taken,
+  // so that the loads stay in flight across the contributions' arithmetic
+  // (a wave's loads complete in issue order, and a conditional load would
+  // make every later wait cover all of them).
+  double c00 = 0, c10 = 0, c01 = 0, c11 = 0, b0 = 0, b1 = 0;
+  auto contribution = [&](const int4 cr) {
+    const int rp = cr.w & 0xFFFF, rq = (cr.w >> 16) & 0xFFFF;
+    double hP, hQ, Ppt, Ppv, Pqt, Pqv, Qpt, Qpv, Qqt, Qqv;
+    X.eval_pq(cr.x & 7, cr.x >> 3, rp, rq, hP, hQ, Ppt, Ppv, Pqt, Pqv, Qpt, Qpv, Qqt, Qqv);
+    if (cr.y >= 0) {
+      const double2 wzp = wz_of(cr.y);
+      if (rb2 >= 0 && rp == rq) {
+        const double wres = wzp.x * (wzp.y - hP);
+        b0 += Ppt * wres;
+        b1 += Ppv * wres;
+      }
+      Ppt *= wzp.x;
+      Ppv *= wzp.x;
+      c00 += Ppt * Pqt;
+      c10 += Ppv * Pqt;
+      c01 += Ppt * Pqv;
+      c11 += Ppv * Pqv;
+    }
+    if (cr.z >= 0) {
+      const double2 wzq = wz_of(cr.z);
+      if (rb2 >= 0 && rp == rq) {
+        const double wres = wzq.x * (wzq.y - hQ);
+        b0 += Qpt * wres;
+        b1 += Qpv * wres;
+      }
+      Qpt *= wzq.x;
+      Qpv *= wzq.x;
+      c00 += Qpt * Qqt;
+      c10 += Qpv * Qqt;
+      c01 += Qpt * Qqv;
+      c11 += Qpv * Qqv;
+    }
+  };
+  int4 rA = d.scon[(i < am.nslot && sl.w > 0) ? sl.z + lane : 0];
+  int4 rB = d.scon[(i < am.nslot && sl.w > 1) ? sl.z + 64 + lane : 0];
   for (; i < am.nslot; i += nt) {
-    double c00 = 0, c10 = 0, c01 = 0, c11 = 0, b0 = 0, b1 = 0;
-    for (int c = 0; c < sl.w; ++c) {
-      const int4 cr = r0;
-      if (c + 1 < sl.w) r0 = d.scon[sl.z + (c + 1) * 64 + lane];
-      const int rp = cr.w & 0xFFFF, rq = (cr.w >> 16) & 0xFFFF;
-      double hP, hQ, Ppt, Ppv, Pqt, Pqv, Qpt, Qpv, Qqt, Qqv;
-      X.eval_pq(cr.x & 7, cr.x >> 3, rp, rq, hP, hQ, Ppt, Ppv, Pqt, Pqv, Qpt, Qpv, Qqt, Qqv);
-      if (cr.y >= 0) {
-        const double2 wzp = wz_of(cr.y);
-        if (rb2 >= 0 && rp == rq) {
-          const double wres = wzp.x * (wzp.y - hP);
-          b0 += Ppt * wres;
-          b1 += Ppv * wres;
-        }
-        Ppt *= wzp.x;
-        Ppv *= wzp.x;
-        c00 += Ppt * Pqt;
-        c10 += Ppv * Pqt;
-        c01 += Ppt * Pqv;
-        c11 += Ppv * Pqv;
-      }
-      if (cr.z >= 0) {
-        const double2 wzq = wz_of(cr.z);
-        if (rb2 >= 0 && rp == rq) {
-          const double wres = wzq.x * (wzq.y - hQ);
-          b0 += Qpt * wres;
-          b1 += Qpv * wres;
-        }
-        Qpt *= wzq.x;
-        Qpv *= wzq.x;
-        c00 += Qpt * Qqt;
-        c10 += Qpv * Qqt;
-        c01 += Qpt * Qqv;
-        c11 += Qpv * Qqv;
-      }
+    c00 = c10 = c01 = c11 = b0 = b1 = 0;
+    const int w = sl.w;
+    for (int c = 0; c < w; c += 2) {
+      const int4 ca = rA;
+      rA = d.scon[sl.z + min(c + 2, w - 1) * 64 + lane];
+      contribution(ca);
+      const int4 cb = rB;
+      rB = d.scon[sl.z + min(c + 3, w - 1) * 64 + lane];
+      if (c + 1 < w) contribution(cb);
     }
     // the next slot, requested before the stores below
     const int in = i + nt;
-    const int4 sln = in < am.nslot ? d.slot[am.slot + in] : zero4;
-    const int rbn = in < am.nslot ? d.slot_rhs[am.slot + in] : -1;
-    r0 = (in < am.nslot && sln.w > 0) ? d.scon[sln.z + lane] : zero4;
+    const int inc = in < am.nslot ? in : am.nslot - 1;
+    const int4 slr = d.slot[am.slot + inc];
+    const int rbr = d.slot_rhs[am.slot + inc];
+    const int4 sln = in < am.nslot ? slr : zero4;
+    const int rbn = in < am.nslot ? rbr : -1;
+    rA = d.scon[(in < am.nslot && sln.w > 0) ? sln.z + lane : 0];
+    rB = d.scon[(in < am.nslot && sln.w > 1) ? sln.z + 64 + lane : 0];
     const bool diag = sl.y < 0;
     const int stride = diag ? -sl.y : sl.y;
     if (diag) c01 = c10;
@@ -2347,11 +2370,20 @@ hipError_t launch_assemble(const Dev& d, int a0, int na, int s0, int ns, int mod
                            bool br_lds, hipStream_t st) {
   if (na <= 0 || ns <= 0) return hipSuccess;
   if (d.asm_stage)
-    hipLaunchKernelGGL((k_assemble<false, true>), dim3(na * ns), dim3(ASM_NT), 0, st, d, a0, na, s0, ns, mode);
+    hipLaunchKernelGGL((k_assemble<false, true, false>), dim3(na * ns), dim3(ASM_NT), 0, st, d, a0, na, s0, ns,
+                       mode);
+  else if (br_lds && d.asm_wz)
+    hipLaunchKernelGGL((k_assemble<true, false, true>), dim3(na * ns), dim3(ASM_NT), lds, st, d, a0, na, s0, ns,
+                       mode);
   else if (br_lds)
-    hipLaunchKernelGGL((k_assemble<true, false>), dim3(na * ns), dim3(ASM_NT), lds, st, d, a0, na, s0, ns, mode);
+    hipLaunchKernelGGL((k_assemble<true, false, false>), dim3(na * ns), dim3(ASM_NT), lds, st, d, a0, na, s0, ns,
+                       mode);
+  else if (d.asm_wz)
+    hipLaunchKernelGGL((k_assemble<false, false, true>), dim3(na * ns), dim3(ASM_NT), lds, st, d, a0, na, s0, ns,
+                       mode);
   else
-    hipLaunchKernelGGL((k_assemble<false, false>), dim3(na * ns), dim3(ASM_NT), lds, st, d, a0, na, s0, ns, mode);
+    hipLaunchKernelGGL((k_assemble<false, false, false>), dim3(na * ns), dim3(ASM_NT), lds, st, d, a0, na, s0, ns,
+                       mode);
   return hipGetLastError();
 }
 
@@ -2561,11 +2593,15 @@ hipError_t launch_stream_copy(const Dev& d, const int32_t* retire, const int32_t
 }
 
 hipError_t allow_assemble_lds(size_t bytes, bool br_lds) {
-  if (br_lds)
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_assemble<true, false>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_assemble<false, false>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  const void* f[2] = {br_lds ? reinterpret_cast<const void*>(&k_assemble<true, false, true>)
+                             : reinterpret_cast<const void*>(&k_assemble<false, false, true>),
+                      br_lds ? reinterpret_cast<const void*>(&k_assemble<true, false, false>)
+                             : reinterpret_cast<const void*>(&k_assemble<false, false, false>)};
+  for (const void* fn : f) {
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace mase
