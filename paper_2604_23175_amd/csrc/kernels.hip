@@ -1576,11 +1576,20 @@ __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
   constexpr int NW = SN_NT / 64, UL = 8, TB = 4;
   const int li = lane & 15, lk = lane >> 4;
   if (tid == 0) bad = 0;
-  const int qe = d.sn_grp_ptr[gi + 1];
-  for (int qi = d.sn_grp_ptr[gi]; qi < qe; ++qi) {
+  const int qb = d.sn_grp_ptr[gi], qe = d.sn_grp_ptr[gi + 1];
+  // the plan records of the group's next supernode are fetched while the
+  // current one is factored
+  int4 snx = make_int4(0, 0, 0, 0), sn2x = make_int4(0, 0, 0, 0);
+  if (qb < qe) {
+    const int q0 = d.sn_grp[qb];
+    snx = d.sn[q0];
+    sn2x = d.sn2[q0];
+  }
+  for (int qi = qb; qi < qe; ++qi) {
     const int q = d.sn_grp[qi];
-    const int4 sn = d.sn[q];
-    const int4 sn2 = d.sn2[q];
+    const int qn = (qi + 1 < qe) ? d.sn_grp[qi + 1] : 0;
+    const int4 sn = snx;
+    const int4 sn2 = sn2x;
     const int c0 = sn.x, w = sn.y, r = sn.z, rb = sn.w;
     const int nrs = r - sn2.w;  // R buses outside the tail
     const int W = 2 * w, Wp = (W + 15) & ~15, M = Wp + ((2 * r + 15) & ~15);
@@ -1589,17 +1598,41 @@ __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
     double* P = sl;              // [Wp columns][M rows], pitch ldp
     double* yv = sl + ldp * Wp;  // [M]
     int* tg = reinterpret_cast<int*>(yv + M);
+    int* rows = tg + ntg;        // [r] the R bus ids
+    // (1) staging.  Every load of the stage is issued first (the panel's
+    // first UL values per thread, the own rhs, the R bus ids, the target
+    // table), the LDS is cleared meanwhile (a barrier on LDS alone keeps
+    // them in flight), and only the rhs of the R rows, which needs the bus
+    // ids, waits for a first round trip.
+    double v[UL];
+#pragma unroll
+    for (int u = 0; u < UL; ++u) {
+      const int i = tid + u * SN_NT;
+      v[u] = (i < T) ? vals[sn2.x + i] : 0.0;
+    }
+    const double yown = tid < W ? rhs[2 * c0 + tid] : 0.0;
+    const int rid = tid < r ? d.sn_rows[rb + tid] : 0;
+    int tgv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) tgv[u] = (tid + u * SN_NT < ntg) ? d.sn_tgt[sn2.z + tid + u * SN_NT] : 0;
     for (int i = tid; i < ldp * Wp; i += SN_NT) P[i] = 0.0;
     for (int i = tid; i < M; i += SN_NT) yv[i] = 0.0;
-    __syncthreads();
-    // (1) staging: UL loads in flight per thread; identity on the padding
+    lds_barrier();
+    if (tid < r) rows[tid] = rid;
+    for (int i = tid + SN_NT; i < r; i += SN_NT) rows[i] = d.sn_rows[rb + i];
     if (tid < Wp - W) P[(W + tid) * ldp + W + tid] = 1.0;
-    for (int i0 = tid; i0 < T; i0 += UL * SN_NT) {
-      double v[UL];
+    if (tid < W) yv[tid] = yown;
 #pragma unroll
-      for (int u = 0; u < UL; ++u) {
-        const int i = i0 + u * SN_NT;
-        v[u] = (i < T) ? vals[sn2.x + i] : 0.0;
+    for (int u = 0; u < 4; ++u)
+      if (tid + u * SN_NT < ntg) tg[tid + u * SN_NT] = tgv[u];
+    for (int i = tid + 4 * SN_NT; i < ntg; i += SN_NT) tg[i] = d.sn_tgt[sn2.z + i];
+    for (int i0 = tid; i0 < T; i0 += UL * SN_NT) {
+      if (i0 != tid) {
+#pragma unroll
+        for (int u = 0; u < UL; ++u) {
+          const int i = i0 + u * SN_NT;
+          v[u] = (i < T) ? vals[sn2.x + i] : 0.0;
+        }
       }
 #pragma unroll
       for (int u = 0; u < UL; ++u) {
@@ -1611,9 +1644,12 @@ __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
         P[colv * ldp + rowv] = v[u];
       }
     }
-    for (int i = tid; i < W; i += SN_NT) yv[i] = rhs[2 * c0 + i];
-    for (int i = tid; i < 2 * nrs; i += SN_NT) yv[Wp + i] = rhs[2 * d.sn_rows[rb + (i >> 1)] + (i & 1)];
-    for (int i = tid; i < ntg; i += SN_NT) tg[i] = d.sn_tgt[sn2.z + i];
+    if (qi + 1 < qe) {
+      snx = d.sn[qn];
+      sn2x = d.sn2[qn];
+    }
+    lds_barrier();
+    for (int i = tid; i < 2 * nrs; i += SN_NT) yv[Wp + i] = rhs[2 * rows[i >> 1] + (i & 1)];
     __syncthreads();
     // (2) blocked Cholesky of the panel and forward solve
     for (int cb = 0; cb < Wp; cb += 16) {
@@ -1685,7 +1721,7 @@ __global__ void __launch_bounds__(SN_NT) k_gamma_snode(Dev d, int s0) {
       vals[sn2.x + i] = val;
     }
     for (int i = tid; i < W; i += SN_NT) rhs[2 * c0 + i] = yv[i];
-    for (int i = tid; i < 2 * nrs; i += SN_NT) rhs[2 * d.sn_rows[rb + (i >> 1)] + (i & 1)] = yv[Wp + i];
+    for (int i = tid; i < 2 * nrs; i += SN_NT) rhs[2 * rows[i >> 1] + (i & 1)] = yv[Wp + i];
     const int mt = 2 * sn2.w;  // tail rows: their rhs started at 0, so they now hold c_q
     const int4 s3 = d.sn3[q];
     for (int i = tid; i < mt; i += SN_NT) tl[s3.y + i] = yv[Wp + 2 * nrs + i];
@@ -1890,7 +1926,8 @@ __global__ void __launch_bounds__(TAIL_NT) k_gamma_tail(Dev d, int s0, int nblk)
 // boundary buses from the boundary solution (dx_b^k = E_k dx_Gamma); then,
 // level by level from the top, dx_j = L_jj^-T (y_j - sum_i L_ij^T dx_i),
 // which is Eq. 8 through the cached factor.  Each column's sum is split over
-// a group of 8 lanes and combined by a fixed shuffle tree.
+// a group of lanes (1 to 64, chosen per level by the plan) and combined by a
+// fixed shuffle tree.
 // ---------------------------------------------------------------------------
 template <int NT, bool XL>
 __global__ void __launch_bounds__(NT) k_backsolve(Dev d, int sys0, int nsys, int s0, int ns, int fixed_bnd) {

@@ -36,12 +36,13 @@ constexpr int AREA_LDS_DOUBLES = 160 * 1024 / 8;
 // Panel geometry of a supernode of w buses with r row buses below: the LDS
 // panel has sn_rows_padded() rows (the 2w own variables padded to a multiple
 // of 16, then the 2r row variables padded likewise) and sn_cols_padded()
-// columns, column-major with pitch rows + 1.
+// columns, column-major with pitch rows + 1; after it the rhs, the Schur
+// target table and the r row bus ids.
 inline int sn_cols_padded(int w) { return (2 * w + 15) / 16 * 16; }
 inline int sn_rows_padded(int w, int r) { return sn_cols_padded(w) + (2 * r + 15) / 16 * 16; }
 inline int sn_lds_bytes_of(int w, int r) {
   const int M = sn_rows_padded(w, r);
-  return 8 * ((M + 1) * sn_cols_padded(w) + M) + 4 * (r * (r + 1) / 2);
+  return 8 * ((M + 1) * sn_cols_padded(w) + M) + 4 * (r * (r + 1) / 2) + 4 * r;
 }
 
 // One symmetric positive definite system over "buses" (2x2 blocks: theta, |V|)
