@@ -40,6 +40,8 @@ def _ctx(g, slack=None, gamma_mode=0, n_snap=2):
 CASES = [
     ("c0", None), ("c1", None),
     ("k2", None), ("k4b", None), ("k5", None), ("slack_bnd", "bnd"),
+    # the benchmark grids (9241 buses / 32 areas, 10000 buses / 16 areas)
+    ("c2", None), ("c3", None),
 ]
 
 
@@ -72,7 +74,7 @@ def test_maps_bit_exact(name, slack):
         np.testing.assert_array_equal(m.mase_export_map("E", k), A.E[k])
 
 
-@pytest.mark.parametrize("name,slack", CASES[:4])
+@pytest.mark.parametrize("name,slack", CASES[:4] + CASES[6:])
 def test_patterns_bit_exact(name, slack):
     g = _grid(name)
     m, net, A = _ctx(g, slack)
