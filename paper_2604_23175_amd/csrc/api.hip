@@ -516,6 +516,9 @@ int upload_plan(mase_ctx* c) {
   // stream solve: active flags and stream positions of two alternate passes
   HIPTRY(hipHostMalloc((void**)&c->h_st_active, sizeof(int32_t) * (2 * (size_t)S + 4), hipHostMallocDefault));
   c->h_st_pos = c->h_st_active + 2 * S;
+  // the refill kernel writes them directly (no copy per pass)
+  HIPTRY(hipHostGetDevicePointer((void**)&c->h_st_active_dev, c->h_st_active, 0));
+  c->h_st_pos_dev = c->h_st_active_dev + 2 * S;
   for (auto& e : c->st_ev) HIPTRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   HIPTRY(hipMemcpy(c->dtol, c->h_tol, sizeof(double), hipMemcpyHostToDevice));
 
@@ -1570,7 +1573,8 @@ int stream_solve(mase_ctx* c, const double* z_dev, const double* vm0_dev, const 
                           c->stream));
   // the first refill hands out positions [0, S), the first pass up to 2 S
   if (io && (rc = io->ensure(2 * (int64_t)S, c->stream))) return rc;
-  HIPTRY(launch_stream_refill(c->d, slot_id, next, retire, refill, out_iters, out_flag, nt, max_iter, c->stream));
+  HIPTRY(launch_stream_refill(c->d, slot_id, next, retire, refill, out_iters, out_flag, nt, max_iter, nullptr,
+                              nullptr, c->stream));
   HIPTRY(launch_stream_copy(c->d, retire, refill, z_dev, vm0_dev, va0_dev, vm_dev, va_dev, c->stream));
   if ((rc = read_flags(c))) return rc;
   c->have_z = true;
@@ -1584,7 +1588,9 @@ int stream_solve(mase_ctx* c, const double* z_dev, const double* vm0_dev, const 
   // at most max_iter passes remain
   const int64_t limit = (n_total * max_iter + S - 1) / S + max_iter + 1;
   int32_t* hpos = c->h_st_pos;  // [2][2] pinned: next[0..1] of alternate passes
-  auto launch_pass = [&]() -> int {
+  // host_active / host_pos: where the refill kernel leaves the pass's active
+  // flags and stream positions for the host (pinned buffers), or null
+  auto launch_pass = [&](int32_t* host_active, int32_t* host_pos) -> int {
     if (use_graph) {
       if (!c->gexec) {
         HIPTRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
@@ -1602,7 +1608,7 @@ int stream_solve(mase_ctx* c, const double* z_dev, const double* vm0_dev, const 
       if (e0) return e0;
     }
     HIPTRY(launch_stream_refill(c->d, slot_id, next, retire, refill, out_iters, out_flag, nt, max_iter,
-                                c->stream));
+                                host_active, host_pos, c->stream));
     HIPTRY(launch_stream_copy(c->d, retire, refill, z_dev, vm0_dev, va0_dev, vm_dev, va_dev, c->stream));
     return 0;
   };
@@ -1621,11 +1627,9 @@ int stream_solve(mase_ctx* c, const double* z_dev, const double* vm0_dev, const 
     auto enqueue = [&](int64_t j) -> int {
       // passes j - 1 and j may hand out up to 2 S positions past the last known one
       if (io && (rc = io->ensure(known_next + 2 * (int64_t)S, c->stream))) return rc;
-      if ((rc = launch_pass())) return rc;
-      HIPTRY(hipMemcpyAsync(c->h_st_active + (j & 1) * S, c->d.active, sizeof(int32_t) * S, hipMemcpyDeviceToHost,
-                            c->stream));
-      if (io)
-        HIPTRY(hipMemcpyAsync(hpos + 2 * (j & 1), next, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, c->stream));
+      // the refill kernel leaves the active flags and stream positions in
+      // the pinned buffers of this pass's parity
+      if ((rc = launch_pass(c->h_st_active_dev + (j & 1) * S, c->h_st_pos_dev + 2 * (j & 1)))) return rc;
       HIPTRY(hipEventRecord(c->st_ev[j & 1], c->stream));
       return 0;
     };
@@ -1653,7 +1657,7 @@ int stream_solve(mase_ctx* c, const double* z_dev, const double* vm0_dev, const 
       if (nact == 0) break;
       if (++pass > limit) return fail(MASE_ERR_STATE, "stream solve did not drain");
       if (io && (rc = io->ensure(known_next + (int64_t)S, c->stream))) return rc;
-      if ((rc = launch_pass())) return rc;
+      if ((rc = launch_pass(nullptr, nullptr))) return rc;
       if ((rc = read_flags(c))) return rc;
       if ((rc = accumulate_profile(c, nact))) return rc;
       if (io) {

@@ -72,6 +72,8 @@ struct mase_ctx {
   int64_t st_out_cap = 0;
   int32_t* h_st_active = nullptr;  // [2][n_snap] pinned: active flags of alternate passes
   int32_t* h_st_pos = nullptr;     // [2][2] pinned: stream position, lowest position in a slot
+  int32_t* h_st_active_dev = nullptr;  // the same two buffers as the device addresses them
+  int32_t* h_st_pos_dev = nullptr;
   hipEvent_t st_ev[2] = {};
   // device address, on this context's GPU, of the library's fixed scratch
   // array that mase_solve_stream_noalloc uses for the same bookkeeping

@@ -2265,9 +2265,13 @@ __global__ void k_reset_flags(Dev d) {
 // snapshot leaves and which enters slot s (-1: none). next[0] is the stream
 // position; next[1] receives the lowest stream position still in a slot
 // (next[0] when every slot is idle): every earlier snapshot has left.
+// host_active / host_pos: device addresses of pinned host buffers that
+// receive the slots' active flags and next[0..1] after the hand-over (so the
+// host reads them without a copy), or null.
 __global__ void __launch_bounds__(256) k_stream_refill(Dev d, int32_t* slot_id, int32_t* next,
                                                        int32_t* retire, int32_t* refill, int32_t* out_iters,
-                                                       int32_t* out_flag, int32_t n_total, int32_t max_iter) {
+                                                       int32_t* out_flag, int32_t n_total, int32_t max_iter,
+                                                       int32_t* host_active, int32_t* host_pos) {
   __shared__ int cnt[4];
   __shared__ int base;
   __shared__ int lows[4];
@@ -2278,7 +2282,7 @@ __global__ void __launch_bounds__(256) k_stream_refill(Dev d, int32_t* slot_id, 
   __syncthreads();
   for (int c0 = 0; c0 < d.n_snap; c0 += 256) {
     const int s = c0 + tid;
-    int want = 0, leaving = -1, keep = -1;
+    int want = 0, leaving = -1, keep = -1, fin = 1;
     if (s < d.n_snap) {
       const int id = slot_id[s];
       keep = id;
@@ -2316,12 +2320,14 @@ __global__ void __launch_bounds__(256) k_stream_refill(Dev d, int32_t* slot_id, 
         entering = take ? rank : -1;
         keep = entering;
         slot_id[s] = entering;
-        d.active[s] = take ? 1 : 0;
+        fin = take ? 1 : 0;
+        d.active[s] = fin;
         d.iters[s] = 0;
         d.maxdx[s] = 0.0;
         for (int k = 0; k < K1; ++k) d.status[(int64_t)s * K1 + k] = 0;
       }
       refill[s] = entering;
+      if (host_active) host_active[s] = fin;
       if (keep >= 0 && keep < low) low = keep;
     }
     __syncthreads();
@@ -2336,6 +2342,10 @@ __global__ void __launch_bounds__(256) k_stream_refill(Dev d, int32_t* slot_id, 
     const int lo = min(min(lows[0], lows[1]), min(lows[2], lows[3]));
     next[0] = nx;
     next[1] = lo < nx ? lo : nx;
+    if (host_pos) {
+      host_pos[0] = nx;
+      host_pos[1] = lo < nx ? lo : nx;
+    }
   }
 }
 
@@ -2607,9 +2617,9 @@ hipError_t launch_reset_flags(const Dev& d, hipStream_t st) {
 
 hipError_t launch_stream_refill(const Dev& d, int32_t* slot_id, int32_t* next, int32_t* retire,
                                 int32_t* refill, int32_t* out_iters, int32_t* out_flag, int32_t n_total,
-                                int32_t max_iter, hipStream_t st) {
+                                int32_t max_iter, int32_t* host_active, int32_t* host_pos, hipStream_t st) {
   hipLaunchKernelGGL(k_stream_refill, dim3(1), dim3(256), 0, st, d, slot_id, next, retire, refill, out_iters,
-                     out_flag, n_total, max_iter);
+                     out_flag, n_total, max_iter, host_active, host_pos);
   return hipGetLastError();
 }
 

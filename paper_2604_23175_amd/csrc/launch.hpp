@@ -54,7 +54,7 @@ hipError_t launch_reset_flags(const Dev& d, hipStream_t st);
 // continuous batching (one refill workgroup, then the slots' copies)
 hipError_t launch_stream_refill(const Dev& d, int32_t* slot_id, int32_t* next, int32_t* retire,
                                 int32_t* refill, int32_t* out_iters, int32_t* out_flag, int32_t n_total,
-                                int32_t max_iter, hipStream_t st);
+                                int32_t max_iter, int32_t* host_active, int32_t* host_pos, hipStream_t st);
 hipError_t launch_stream_init(int32_t* slot_id, int32_t* next, int n_snap, hipStream_t st);
 hipError_t launch_stream_copy(const Dev& d, const int32_t* retire, const int32_t* refill, const double* zs,
                               const double* vm0, const double* va0, double* vm_out, double* va_out,
